@@ -1,0 +1,210 @@
+/*
+ * cpamg.h -- C ABI of the gfx950 hot path for multigrid CP decomposition.
+ *
+ * Method: H. De Sterck and K. Miller, "An adaptive algebraic multigrid
+ * algorithm for low-rank canonical tensor decomposition".  The library runs the
+ * ALS relaxation sweep (Section 3), the multilinear restriction and
+ * prolongation of the setup phase (Section 4.1) and the CP-FAS V-cycle of the
+ * solve phase (Section 5, Algorithm 2) on one AMD Instinct MI355X.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pointers are DEVICE pointers unless a parameter says (host).
+ * Tensor layout: dense, mode 1 fastest: entry (i_1..i_N) sits at
+ *   i_1 + I_1*(i_2 + I_2*(i_3 + ...)), 0-based indices.
+ * Factor layout: A^(n) is I_n x R, row-major with r fastest (leading dim R).
+ * Mode numbers in this interface are 0-based (mode n here is mode n+1 of the
+ * paper).  Rank R <= CP_MAX_RANK, order 2 <= N <= CP_MAX_ORDER.
+ *
+ * Ownership: the caller owns every tensor, factor and output buffer.  The
+ * library allocates only its own workspace inside the context; it grows on
+ * demand (the stream is synchronized before a reallocation) and is released by
+ * cp_ctx_destroy.  No caller pointer is retained after a call returns.
+ *
+ * Asynchrony: every compute call only enqueues work on the context's stream and
+ * returns; outputs are valid once that stream has been synchronized.  Scalar
+ * results (f, g, norms) are written to device memory, so no call synchronizes
+ * except cp_get_status and workspace growth.
+ *
+ * Errors: argument errors are found on the host before anything is enqueued:
+ * the call returns a negative cp_status, writes nothing, and cp_last_error()
+ * describes the problem.  Numerical events found on the device are OR-ed into
+ * a device flag word read by cp_get_status().  No exception or abort crosses
+ * the ABI.  A context is used by one host thread at a time.
+ *
+ * Precision: CP_FP64 computes everything in IEEE double.  CP_MIXED runs the
+ * tensor contractions (MTTKRP GEMM stage, restriction GEMMs) in FP32 on the
+ * matrix cores with FP32 accumulation, reading the FP32 shadows z32 / a32;
+ * the Hadamard-reduce stage, Gram matrices, R x R solves, objective and FAS
+ * right-hand sides stay in FP64.
+ */
+#ifndef CPAMG_H
+#define CPAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CP_MAX_ORDER 8
+#define CP_MAX_RANK 32
+
+typedef enum {
+  CP_OK = 0,
+  CP_ERR_INVALID = -1,     /* NULL or inconsistent argument */
+  CP_ERR_SHAPE = -2,       /* dimension / rank outside the supported range */
+  CP_ERR_NOT_SPD = -3,     /* reported by cp_get_status when a solve failed */
+  CP_ERR_NONFINITE = -4,   /* reported by cp_get_status on NaN/Inf */
+  CP_ERR_HIP = -5,         /* a HIP runtime call failed (message in cp_last_error) */
+  CP_ERR_NOMEM = -6,       /* workspace allocation failed */
+  CP_ERR_UNSUPPORTED = -7  /* valid request that this build does not implement */
+} cp_status;
+
+typedef enum { CP_FP64 = 0, CP_MIXED = 1 } cp_prec;
+typedef enum { CP_SOLVE_CHOL = 0, CP_SOLVE_GS = 1 } cp_solver;
+
+/* Device flag bits reported by cp_get_status(). */
+#define CP_FLAG_PINV_FALLBACK 1u  /* a Gamma had a pivot <= R*eps*max(diag): pseudoinverse used */
+#define CP_FLAG_NOT_SPD 2u        /* a Gamma was zero: the update left A unchanged */
+#define CP_FLAG_NONFINITE 4u      /* a non-finite value appeared in a solve */
+
+typedef struct cp_ctx_s* cp_ctx;
+
+/* Dense tensor.  z64: FP64 master (required by CP_FP64 calls); z32: FP32
+ * shadow (required by CP_MIXED contractions; fill it with cp_cast_f32).
+ * norm2: device scalar holding ||Z||^2 in FP64 (cp_norm2 writes it); it is
+ * needed only where a call says so, NULL otherwise. */
+typedef struct {
+  int32_t order;
+  int64_t dims[CP_MAX_ORDER];
+  const double* z64;
+  const float* z32;
+  const double* norm2;
+} cp_tensor;
+
+/* Kruskal factors A^(0..N-1), each I_n x R row-major (FP64 master).  a32[n] is
+ * the FP32 shadow used by CP_MIXED contractions (updated by the library
+ * whenever it writes a[n]); may be NULL for CP_FP64. */
+typedef struct {
+  int32_t rank;
+  double* a[CP_MAX_ORDER];
+  float* a32[CP_MAX_ORDER];
+} cp_factors;
+
+/* One level of a multigrid hierarchy (Section 4.1, Algorithm 1/2).  z: the
+ * level tensor (level 0 is the finest).  phat[n]: dense P^ = P L^{-T} of mode
+ * n mapping the next coarser level to this one, I_n x I_{n,c} row-major, or
+ * NULL when mode n is not coarsened on this level (n in I_c').  The coarsest
+ * level has every phat[n] NULL. */
+typedef struct {
+  cp_tensor z;
+  const double* phat[CP_MAX_ORDER];
+} cp_level;
+
+/* CP-FAS parameters (Table 1: nu1 = nu2 = 1, nuc = 50; Section 5.2: 10
+ * Gauss-Seidel iterations).  ic_rule: coarse right-hand side for modes that
+ * are not coarsened: 0 = tau-corrected F - H(A) + H_c(A~_c) (keeps the FAS
+ * fixed point), 1 = Algorithm 2 as printed (F_c = F). */
+typedef struct {
+  int32_t nu1, nu2, nuc, gs_iters;
+  int32_t ic_rule;
+} cp_fas_params;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  *out receives the
+ * handle. */
+cp_status cp_ctx_create(cp_ctx* out, void* hip_stream);
+/* Synchronize the context's stream, free its workspace and the handle. */
+cp_status cp_ctx_destroy(cp_ctx ctx);
+/* Re-bind the context to another stream (work already enqueued stays where it is). */
+cp_status cp_set_stream(cp_ctx ctx, void* hip_stream);
+/* Text of the last host-side error of this context ("" if none); owned by ctx. */
+const char* cp_last_error(cp_ctx ctx);
+/* Synchronize the stream, return the OR of device flag bits since the last call
+ * in *flags (host) and clear them. */
+cp_status cp_get_status(cp_ctx ctx, int32_t* flags);
+
+/* ---- utilities -------------------------------------------------------- */
+
+/* dst[i] = (float)src[i], i < count (FP32 shadow of a tensor or factor). */
+cp_status cp_cast_f32(cp_ctx ctx, const double* src, float* dst, int64_t count);
+/* *out (device) = ||Z||^2 accumulated in FP64 from Z->z64. */
+cp_status cp_norm2(cp_ctx ctx, const cp_tensor* Z, double* out);
+
+/* ---- hot path (the calls named by the method) -------------------------- */
+
+/* MTTKRP of eq. (6): M = Z_(n) Phi^(n), Phi^(n) the Khatri-Rao product of all
+ * factors but n in the order of eq. (7).  Computed as a matrix-core GEMM that
+ * contracts one mode with its factor, followed by a Hadamard-reduce over the
+ * remaining modes; the Khatri-Rao matrix is never formed.  M: I_n x R
+ * row-major FP64 (written, not accumulated).  CP_MIXED reads z32/a32. */
+cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
+                    double* M, cp_prec prec);
+
+/* `nsweeps` iterations of block nonlinear Gauss-Seidel (Section 3 ALS, or the
+ * FAS relaxation of Section 5.2 when F != NULL) on A^(n) Gamma^(n) =
+ * Z_(n) Phi^(n) + F^(n), n = 0..N-1, updating A (and its shadows) in place.
+ * solver: CP_SOLVE_CHOL = A^(n) <- (M + F) Gamma^dagger (Cholesky, pseudoinverse
+ * fallback); CP_SOLVE_GS = `gs_iters` Gauss-Seidel iterations warm-started from
+ * the current A^(n).  normalize != 0 applies eq. (10) after every sweep.
+ * F: NULL for plain ALS, else F->a[n] (I_n x R FP64).  f_hist (optional,
+ * device, nsweeps doubles): f = 1/2||Z - [[A]]||^2 after each sweep from the
+ * fused identity (needs Z->norm2; with CP_MIXED it uses the FP32 MTTKRP). */
+cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_factors* F,
+                       int32_t nsweeps, cp_solver solver, int32_t gs_iters, int32_t normalize,
+                       cp_prec prec, double* f_hist);
+
+/* Objective eq. (2) and stopping measure eq. (30) at fixed A.  exact != 0:
+ * f from one streaming pass over Z->z64 forming the residual on the fly;
+ * exact == 0: fused identity 1/2(||Z||^2 - 2<A^(N), M^(N)> + 1^T(*Upsilon)1)
+ * (needs Z->norm2).  f (device scalar, optional), g (device scalar, optional;
+ * needs Z->norm2; N MTTKRPs in precision `prec`). */
+cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t exact,
+                       double* f, double* g, cp_prec prec);
+
+/* Coarse tensor eq. (15): Zc = Z x_{n : phat[n] != NULL} phat[n]^T, applied as
+ * one mode-n matrix-core GEMM after another.  phat[n]: I_n x I_{n,c}
+ * row-major, or NULL (identity).  Zc->dims must equal the coarse dims; CP_FP64
+ * writes Zc->z64 from Z->z64, CP_MIXED writes Zc->z32 from Z->z32. */
+cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[CP_MAX_ORDER],
+                      cp_tensor* Zc, cp_prec prec);
+
+/* Prolongation.  Ac_tilde == NULL: A = P^ Ac (eq. (18), coarse-grid correction
+ * of the setup phase); else A += P^ (Ac - Ac_tilde) (eq. (28), FAS).  phat:
+ * I x Ic row-major; Ac, Ac_tilde: Ic x R; A: I x R; all FP64.  With phat ==
+ * NULL the identity is used (Ic must equal I). */
+cp_status cp_prolong(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const double* phat,
+                     const double* Ac, const double* Ac_tilde, double* A);
+
+/* Restriction of factors, eq. (21): Ac = P^^T A (Ic x R), FP64. */
+cp_status cp_restrict_factor(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const double* phat,
+                             const double* A, double* Ac);
+
+/* Transfer operator of Section 4.1 / Algorithm 1 steps 4-6 for geometric
+ * coarsening (Section 4.3): from per-row weights w (I x 2; row i odd (0-based)
+ * interpolates from coarse points (i-1)/2 and (i+1)/2 with weights w[i][0],
+ * w[i][1]; the last row of an even I uses w[i][0] only; rows of coarse points
+ * are ignored) builds B = P^T P (tridiagonal), L = chol(B) (bidiagonal) and
+ * writes phat = P L^{-T} (I x Ic row-major, Ic = ceil(I/2)). */
+cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat);
+
+/* One CP-FAS V-cycle (Algorithm 2) from level 0 with F = 0 there, updating A
+ * (level-0 factors, and shadows) in place.  levels[0..nlevels-1]: finest to
+ * coarsest; each level tensor needs z64 (CP_FP64) or z32 (CP_MIXED).
+ * Relaxation is BNGS with Gauss-Seidel inner solves; eq. (10) normalization is
+ * applied on level 0 only.  params NULL = Table 1 defaults. */
+cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t nlevels, cp_factors* A,
+                        const cp_fas_params* params, cp_prec prec);
+
+/* Stable sort of the rank-one terms by decreasing lambda_r (remark after
+ * eq. (10)); permutes the columns of every A^(n) (and shadows) in place. */
+cp_status cp_sort(cp_ctx ctx, const int64_t* dims /*host, N*/, int32_t order, cp_factors* A);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPAMG_H */

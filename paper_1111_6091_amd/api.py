@@ -1,0 +1,249 @@
+"""Python binding of libcpamg: same call names as the C ABI, argument marshalling only.
+
+PyTorch supplies device memory and the stream; every computation runs in the
+HIP kernels of libcpamg.  Device tensors use the library layouts: a tensor is a
+1-D buffer with mode 1 fastest; a factor A^(n) is an (I_n, R) row-major tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (CP_FP64, CP_MIXED, CP_SOLVE_CHOL, CP_SOLVE_GS, CpFactors, CpFasParams,
+                   CpLevel, CpTensor)
+
+
+class CpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcpamg error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else int(t.data_ptr()))
+
+
+class Context:
+    """A libcpamg context bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self._lib = L.load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self._lib.cp_ctx_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise CpError(rc, "cp_ctx_create failed")
+        self.handle = h
+
+    def check(self, rc):
+        if rc != 0:
+            msg = self._lib.cp_last_error(self.handle)
+            raise CpError(rc, msg.decode() if msg else "")
+
+    def status(self):
+        flags = ctypes.c_int32(0)
+        self.check(self._lib.cp_get_status(self.handle, ctypes.byref(flags)))
+        return flags.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.cp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceTensor:
+    """Dense tensor in device memory (mode 1 fastest), FP64 master + optional FP32 shadow."""
+
+    def __init__(self, dims, z64=None, z32=None, norm2=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.z64, self.z32, self.norm2 = z64, z32, norm2
+
+    @property
+    def order(self):
+        return len(self.dims)
+
+    @property
+    def numel(self):
+        return int(np.prod(self.dims))
+
+    @classmethod
+    def from_numpy(cls, ctx, Z, fp32=False, device="cuda"):
+        torch = _torch()
+        Z = np.asarray(Z, dtype=np.float64)
+        z64 = torch.from_numpy(np.ascontiguousarray(Z.ravel(order="F"))).to(device)
+        t = cls(Z.shape, z64=z64)
+        t.norm2 = torch.zeros(1, dtype=torch.float64, device=device)
+        cp_norm2(ctx, t, t.norm2)
+        if fp32:
+            t.z32 = torch.empty(t.numel, dtype=torch.float32, device=device)
+            cp_cast_f32(ctx, t.z64, t.z32)
+        return t
+
+    @classmethod
+    def empty(cls, dims, fp64=True, fp32=False, device="cuda"):
+        torch = _torch()
+        P = int(np.prod(dims))
+        return cls(dims, z64=torch.empty(P, dtype=torch.float64, device=device) if fp64 else None,
+                   z32=torch.empty(P, dtype=torch.float32, device=device) if fp32 else None)
+
+    def struct(self):
+        s = CpTensor()
+        s.order = self.order
+        for i, d in enumerate(self.dims):
+            s.dims[i] = d
+        s.z64 = _ptr(self.z64).value
+        s.z32 = _ptr(self.z32).value
+        s.norm2 = _ptr(self.norm2).value
+        return s
+
+    def to_numpy(self, which="z64"):
+        buf = getattr(self, which)
+        return buf.detach().cpu().numpy().astype(np.float64).reshape(self.dims, order="F")
+
+
+class DeviceFactors:
+    """Kruskal factors: list of (I_n, R) float64 device tensors (+ optional FP32 shadows)."""
+
+    def __init__(self, mats, mats32=None):
+        self.mats = list(mats)
+        self.mats32 = list(mats32) if mats32 is not None else None
+
+    @property
+    def rank(self):
+        return int(self.mats[0].shape[1])
+
+    @property
+    def dims(self):
+        return tuple(int(m.shape[0]) for m in self.mats)
+
+    @classmethod
+    def from_numpy(cls, ctx, A, fp32=False, device="cuda"):
+        torch = _torch()
+        mats = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device) for a in A]
+        m32 = None
+        if fp32:
+            m32 = [torch.empty(m.shape, dtype=torch.float32, device=device) for m in mats]
+            for a, b in zip(mats, m32):
+                cp_cast_f32(ctx, a, b)
+        return cls(mats, m32)
+
+    @classmethod
+    def zeros(cls, dims, R, fp32=False, device="cuda"):
+        torch = _torch()
+        mats = [torch.zeros((d, R), dtype=torch.float64, device=device) for d in dims]
+        m32 = [torch.zeros((d, R), dtype=torch.float32, device=device) for d in dims] if fp32 else None
+        return cls(mats, m32)
+
+    def clone(self):
+        return DeviceFactors([m.clone() for m in self.mats],
+                             [m.clone() for m in self.mats32] if self.mats32 else None)
+
+    def struct(self):
+        s = CpFactors()
+        s.rank = self.rank
+        for i, m in enumerate(self.mats):
+            s.a[i] = int(m.data_ptr())
+            if self.mats32 is not None:
+                s.a32[i] = int(self.mats32[i].data_ptr())
+        return s
+
+    def to_numpy(self):
+        return [m.detach().cpu().numpy().copy() for m in self.mats]
+
+
+# ---------------------------------------------------------------------------
+# calls (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def cp_cast_f32(ctx, src, dst):
+    ctx.check(ctx._lib.cp_cast_f32(ctx.handle, _ptr(src), _ptr(dst), ctypes.c_int64(src.numel())))
+
+
+def cp_norm2(ctx, Z, out):
+    s = Z.struct()
+    ctx.check(ctx._lib.cp_norm2(ctx.handle, ctypes.byref(s), _ptr(out)))
+
+
+def cp_mttkrp(ctx, Z, A, n, M, prec=CP_FP64):
+    zs, fs = Z.struct(), A.struct()
+    ctx.check(ctx._lib.cp_mttkrp(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), n, _ptr(M), prec))
+
+
+def cp_als_sweep(ctx, Z, A, F=None, nsweeps=1, solver=CP_SOLVE_CHOL, gs_iters=10, normalize=True,
+                 prec=CP_FP64, f_hist=None):
+    zs, fs = Z.struct(), A.struct()
+    Fs = F.struct() if F is not None else None
+    ctx.check(ctx._lib.cp_als_sweep(ctx.handle, ctypes.byref(zs), ctypes.byref(fs),
+                                    ctypes.byref(Fs) if Fs is not None else None, nsweeps, solver,
+                                    gs_iters, int(bool(normalize)), prec, _ptr(f_hist)))
+
+
+def cp_objective(ctx, Z, A, exact=True, f=None, g=None, prec=CP_FP64):
+    zs, fs = Z.struct(), A.struct()
+    ctx.check(ctx._lib.cp_objective(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), int(bool(exact)),
+                                    _ptr(f), _ptr(g), prec))
+
+
+def _phat_array(phat):
+    arr = (ctypes.c_void_p * L.CP_MAX_ORDER)()
+    for i, p in enumerate(phat):
+        arr[i] = None if p is None else int(p.data_ptr())
+    return arr
+
+
+def cp_restrict(ctx, Z, phat, Zc, prec=CP_FP64):
+    zs, cs = Z.struct(), Zc.struct()
+    ctx.check(ctx._lib.cp_restrict(ctx.handle, ctypes.byref(zs), _phat_array(phat), ctypes.byref(cs),
+                                   prec))
+
+
+def cp_prolong(ctx, phat, Ac, Ac_tilde, A):
+    I, R = A.shape
+    Ic = Ac.shape[0]
+    ctx.check(ctx._lib.cp_prolong(ctx.handle, I, Ic, R, _ptr(phat), _ptr(Ac), _ptr(Ac_tilde), _ptr(A)))
+
+
+def cp_restrict_factor(ctx, phat, A, Ac):
+    I, R = A.shape
+    Ic = Ac.shape[0]
+    ctx.check(ctx._lib.cp_restrict_factor(ctx.handle, I, Ic, R, _ptr(phat), _ptr(A), _ptr(Ac)))
+
+
+def cp_transfer_build(ctx, w, phat):
+    I = w.shape[0]
+    ctx.check(ctx._lib.cp_transfer_build(ctx.handle, I, _ptr(w), _ptr(phat)))
+
+
+def cp_fas_vcycle(ctx, levels, A, nu1=1, nu2=1, nuc=50, gs_iters=10, ic_rule=0, prec=CP_FP64):
+    """levels: list of (DeviceTensor, [phat_n or None per mode]) from finest to coarsest."""
+    arr = (CpLevel * len(levels))()
+    for i, (Zl, ph) in enumerate(levels):
+        arr[i].z = Zl.struct()
+        for n in range(L.CP_MAX_ORDER):
+            p = ph[n] if ph is not None and n < len(ph) else None
+            arr[i].phat[n] = None if p is None else int(p.data_ptr())
+    prm = CpFasParams(nu1, nu2, nuc, gs_iters, ic_rule)
+    fs = A.struct()
+    ctx.check(ctx._lib.cp_fas_vcycle(ctx.handle, arr, len(levels), ctypes.byref(fs),
+                                     ctypes.byref(prm), prec))
+
+
+def cp_sort(ctx, A):
+    dims = (ctypes.c_int64 * L.CP_MAX_ORDER)(*A.dims)
+    fs = A.struct()
+    ctx.check(ctx._lib.cp_sort(ctx.handle, dims, len(A.mats), ctypes.byref(fs)))

@@ -1,0 +1,786 @@
+// C ABI of libcpamg: argument checking, workspace and launch sequencing.
+// Every compute call validates its arguments on the host, sizes the workspace,
+// then only enqueues kernels on the context's stream.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace cpamg;
+
+namespace {
+
+constexpr int kTargetWgs = 512;
+constexpr int kNumCounters = 16;
+enum CounterId { CNT_EPI = 0, CNT_RES = 1, CNT_DOT = 2, CNT_DOT2 = 3 };
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct cp_ctx_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  // fixed region: counters, flags, factorization of Gamma, scalars
+  char* fixed = nullptr;
+  int32_t* counters = nullptr;
+  uint32_t* flags = nullptr;
+  double* chol = nullptr;
+  int32_t* chol_kind = nullptr;
+  double* scal = nullptr;   // 64 scratch scalars
+};
+
+namespace {
+
+cp_status set_err(cp_ctx c, cp_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+cp_status hip_check(cp_ctx c, hipError_t e, const char* what) {
+  if (e != hipSuccess) return set_err(c, CP_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return CP_OK;
+}
+
+#define HIPCHK(expr)                                        \
+  do {                                                      \
+    cp_status _s = hip_check(ctx, (expr), #expr);           \
+    if (_s != CP_OK) return _s;                             \
+  } while (0)
+
+// Grow the workspace to at least `bytes` (synchronizes the stream first).
+cp_status ensure_ws(cp_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->ws_cap) return CP_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->ws) HIPCHK(hipFree(ctx->ws));
+  ctx->ws = nullptr;
+  ctx->ws_cap = 0;
+  size_t cap = std::max(bytes, size_t(1) << 20);
+  hipError_t e = hipMalloc((void**)&ctx->ws, cap);
+  if (e != hipSuccess) return set_err(ctx, CP_ERR_NOMEM, "workspace of %zu bytes: %s", cap, hipGetErrorString(e));
+  ctx->ws_cap = cap;
+  return CP_OK;
+}
+
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(char* b) : base(b) {}
+  template <typename T> T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+// sizes-only pass of the same carving
+struct Sizer {
+  size_t off = 0;
+  template <typename T> T* take(size_t count) {
+    off += align_up(count * sizeof(T));
+    return nullptr;
+  }
+};
+
+int64_t numel(const cp_tensor* Z) {
+  int64_t p = 1;
+  for (int m = 0; m < Z->order; ++m) p *= Z->dims[m];
+  return p;
+}
+
+cp_status check_ctx(cp_ctx ctx) { return ctx ? CP_OK : CP_ERR_INVALID; }
+
+cp_status check_tensor(cp_ctx ctx, const cp_tensor* Z, bool need64, bool need32, const char* name) {
+  if (!Z) return set_err(ctx, CP_ERR_INVALID, "%s is NULL", name);
+  if (Z->order < 2 || Z->order > CP_MAX_ORDER)
+    return set_err(ctx, CP_ERR_SHAPE, "%s: order %d outside [2, %d]", name, Z->order, CP_MAX_ORDER);
+  for (int m = 0; m < Z->order; ++m)
+    if (Z->dims[m] < 1 || Z->dims[m] > (int64_t(1) << 31))
+      return set_err(ctx, CP_ERR_SHAPE, "%s: dims[%d] = %lld out of range", name, m, (long long)Z->dims[m]);
+  if (need64 && !Z->z64) return set_err(ctx, CP_ERR_INVALID, "%s: z64 is NULL", name);
+  if (need32 && !Z->z32) return set_err(ctx, CP_ERR_INVALID, "%s: z32 is NULL (CP_MIXED needs the FP32 shadow)", name);
+  return CP_OK;
+}
+
+cp_status check_factors(cp_ctx ctx, const cp_factors* A, int N, bool need32, const char* name) {
+  if (!A) return set_err(ctx, CP_ERR_INVALID, "%s is NULL", name);
+  if (A->rank < 1 || A->rank > CP_MAX_RANK)
+    return set_err(ctx, CP_ERR_SHAPE, "%s: rank %d outside [1, %d]", name, A->rank, CP_MAX_RANK);
+  for (int m = 0; m < N; ++m) {
+    if (!A->a[m]) return set_err(ctx, CP_ERR_INVALID, "%s: a[%d] is NULL", name, m);
+    if (need32 && !A->a32[m])
+      return set_err(ctx, CP_ERR_INVALID, "%s: a32[%d] is NULL (CP_MIXED needs FP32 shadows)", name, m);
+  }
+  return CP_OK;
+}
+
+cp_status check_prec(cp_ctx ctx, cp_prec p) {
+  if (p != CP_FP64 && p != CP_MIXED) return set_err(ctx, CP_ERR_INVALID, "unknown precision %d", (int)p);
+  return CP_OK;
+}
+
+// Enqueue M^(n) partials for tensor Z (precision prec); returns the plan.
+cp_status enqueue_mttkrp(cp_ctx ctx, const int64_t* dims, int N, int n, int R, const void* z,
+                         bool fp32, const double* const* a64, const float* const* a32,
+                         const MttkrpPlan& plan, double* out) {
+  HIPCHK(mttkrp_launch(plan, dims, N, n, R, z, fp32, a64, a32, out, ctx->stream));
+  return CP_OK;
+}
+
+size_t max_partial(const int64_t* dims, int N, int R, std::vector<MttkrpPlan>* plans) {
+  size_t mx = 0;
+  for (int n = 0; n < N; ++n) {
+    MttkrpPlan p = mttkrp_plan(N, dims, n, R, kTargetWgs);
+    if (plans) plans->push_back(p);
+    mx = std::max(mx, p.partial_doubles);
+  }
+  return mx;
+}
+
+int64_t max_dim(const int64_t* dims, int N) {
+  int64_t m = 0;
+  for (int i = 0; i < N; ++i) m = std::max(m, dims[i]);
+  return m;
+}
+
+int64_t epi_blocks(int64_t In) { return (In + epi_rows_per_wg() - 1) / epi_rows_per_wg(); }
+
+// Everything one BNGS/ALS sweep needs, carved from the workspace.
+struct SweepWS {
+  double* grams;
+  double* partial;
+  double* gram_part;
+  double* scal_part;
+};
+
+template <typename Carver>
+void carve_sweep(Carver& c, int N, int R, size_t partial, int64_t maxI, SweepWS* out) {
+  const int64_t nwg = epi_blocks(maxI);
+  out->grams = c.template take<double>((size_t)N * R * R);
+  out->partial = c.template take<double>(partial);
+  out->gram_part = c.template take<double>((size_t)nwg * R * R);
+  out->scal_part = c.template take<double>((size_t)std::max<int64_t>(nwg, 2048));
+}
+
+// One BNGS sweep over all modes (grams must hold Upsilon of the current A).
+cp_status enqueue_sweep(cp_ctx ctx, const int64_t* dims, int N, int R, const void* z, bool fp32,
+                        double* const* A, float* const* A32, double* const* F,
+                        const std::vector<MttkrpPlan>& plans, const SweepWS& w, cp_solver solver,
+                        int gs_iters, int normalize, double* f_slot, const double* norm2) {
+  for (int n = 0; n < N; ++n) {
+    if (solver == CP_SOLVE_CHOL)
+      HIPCHK(gamma_prep_launch(w.grams, N, n, R, ctx->chol, ctx->chol_kind, ctx->flags, solver,
+                               ctx->stream));
+    cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
+                                 (const float* const*)A32, plans[n], w.partial);
+    if (s != CP_OK) return s;
+    EpiDesc d{};
+    d.op = EPI_UPDATE;
+    d.solver = solver;
+    d.gs_iters = gs_iters;
+    d.R = R;
+    d.N = N;
+    d.n = n;
+    d.nsplit = plans[n].nsplit;
+    d.In = dims[n];
+    d.partial = w.partial;
+    d.F = F ? F[n] : nullptr;
+    d.A = A[n];
+    d.A32 = A32 ? A32[n] : nullptr;
+    d.grams = w.grams;
+    d.chol = ctx->chol;
+    d.chol_kind = ctx->chol_kind;
+    d.gram_part = w.gram_part;
+    d.scal_part = w.scal_part;
+    d.counter = ctx->counters + CNT_EPI;
+    d.flags = ctx->flags;
+    d.want_obj = (f_slot && n == N - 1) ? 1 : 0;
+    d.scalar_out = f_slot;
+    d.norm2 = norm2;
+    HIPCHK(epi_launch(d, ctx->stream));
+  }
+  if (normalize) HIPCHK(normalize_launch(A, A32, dims, N, R, w.grams, ctx->stream));
+  return CP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+cp_status cp_ctx_create(cp_ctx* out, void* hip_stream) {
+  if (!out) return CP_ERR_INVALID;
+  *out = nullptr;
+  cp_ctx ctx = new (std::nothrow) cp_ctx_s();
+  if (!ctx) return CP_ERR_NOMEM;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&ctx->device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return CP_ERR_HIP;
+  }
+  const size_t fixed_bytes = align_up(kNumCounters * sizeof(int32_t)) + align_up(64) +
+                             align_up(kMaxRank * kMaxRank * sizeof(double)) + align_up(64) +
+                             align_up(64 * sizeof(double));
+  e = hipMalloc((void**)&ctx->fixed, fixed_bytes);
+  if (e != hipSuccess) {
+    delete ctx;
+    return CP_ERR_NOMEM;
+  }
+  e = hipMemset(ctx->fixed, 0, fixed_bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(ctx->fixed);
+    delete ctx;
+    return CP_ERR_HIP;
+  }
+  Arena a(ctx->fixed);
+  ctx->counters = a.take<int32_t>(kNumCounters);
+  ctx->flags = a.take<uint32_t>(16);
+  ctx->chol = a.take<double>(kMaxRank * kMaxRank);
+  ctx->chol_kind = a.take<int32_t>(16);
+  ctx->scal = a.take<double>(64);
+  *out = ctx;
+  return CP_OK;
+}
+
+cp_status cp_ctx_destroy(cp_ctx ctx) {
+  if (!ctx) return CP_ERR_INVALID;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->fixed) (void)hipFree(ctx->fixed);
+  delete ctx;
+  return CP_OK;
+}
+
+cp_status cp_set_stream(cp_ctx ctx, void* hip_stream) {
+  if (!ctx) return CP_ERR_INVALID;
+  ctx->stream = (hipStream_t)hip_stream;
+  return CP_OK;
+}
+
+const char* cp_last_error(cp_ctx ctx) { return ctx ? ctx->err.c_str() : "invalid context"; }
+
+cp_status cp_get_status(cp_ctx ctx, int32_t* flags) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!flags) return set_err(ctx, CP_ERR_INVALID, "flags is NULL");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  uint32_t h = 0;
+  HIPCHK(hipMemcpy(&h, ctx->flags, sizeof(h), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemset(ctx->flags, 0, sizeof(uint32_t)));
+  HIPCHK(hipDeviceSynchronize());
+  *flags = (int32_t)h;
+  return CP_OK;
+}
+
+cp_status cp_cast_f32(cp_ctx ctx, const double* src, float* dst, int64_t count) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!src || !dst) return set_err(ctx, CP_ERR_INVALID, "cp_cast_f32: NULL pointer");
+  if (count < 0) return set_err(ctx, CP_ERR_SHAPE, "cp_cast_f32: negative count");
+  if (count == 0) return CP_OK;
+  HIPCHK(cast_launch(src, dst, count, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_norm2(cp_ctx ctx, const cp_tensor* Z, double* out) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_tensor(ctx, Z, true, false, "Z");
+  if (s != CP_OK) return s;
+  if (!out) return set_err(ctx, CP_ERR_INVALID, "cp_norm2: out is NULL");
+  s = ensure_ws(ctx, align_up(2048 * sizeof(double)));
+  if (s != CP_OK) return s;
+  HIPCHK(norm2_launch(Z->z64, numel(Z), (double*)ctx->ws, ctx->counters + CNT_DOT, out, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n, double* M,
+                    cp_prec prec) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
+  if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: mode %d outside [0, %d)", n, N);
+  if (!M) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: M is NULL");
+  const int R = A->rank;
+  MttkrpPlan plan = mttkrp_plan(N, Z->dims, n, R, kTargetWgs);
+  const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  if (plan.nsplit == 1)
+    return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M);
+  if ((s = ensure_ws(ctx, align_up(plan.partial_doubles * sizeof(double)))) != CP_OK) return s;
+  double* part = (double*)ctx->ws;
+  if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan,
+                          part)) != CP_OK)
+    return s;
+  EpiDesc d{};
+  d.op = EPI_STORE_M;
+  d.R = R;
+  d.N = N;
+  d.n = n;
+  d.nsplit = plan.nsplit;
+  d.In = Z->dims[n];
+  d.partial = part;
+  d.outbuf = M;
+  HIPCHK(epi_launch(d, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_factors* F,
+                       int32_t nsweeps, cp_solver solver, int32_t gs_iters, int32_t normalize,
+                       cp_prec prec, double* f_hist) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
+  if (F) {
+    for (int m = 0; m < N; ++m)
+      if (!F->a[m]) return set_err(ctx, CP_ERR_INVALID, "F->a[%d] is NULL", m);
+  }
+  if (nsweeps < 0) return set_err(ctx, CP_ERR_INVALID, "nsweeps < 0");
+  if (solver != CP_SOLVE_CHOL && solver != CP_SOLVE_GS)
+    return set_err(ctx, CP_ERR_INVALID, "unknown solver %d", (int)solver);
+  if (solver == CP_SOLVE_GS && (gs_iters < 1 || gs_iters > 1000))
+    return set_err(ctx, CP_ERR_INVALID, "gs_iters %d outside [1, 1000]", gs_iters);
+  if (f_hist && !Z->norm2) return set_err(ctx, CP_ERR_INVALID, "f_hist needs Z->norm2");
+  if (nsweeps == 0) return CP_OK;
+  const int R = A->rank;
+  std::vector<MttkrpPlan> plans;
+  const size_t part = max_partial(Z->dims, N, R, &plans);
+  Sizer sz;
+  SweepWS w{};
+  carve_sweep(sz, N, R, part, max_dim(Z->dims, N), &w);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  carve_sweep(ar, N, R, part, max_dim(Z->dims, N), &w);
+  float* const* a32 = A->a32;
+  bool have32 = true;
+  for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
+  const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  HIPCHK(gram_launch(A->a, have32 ? a32 : nullptr, Z->dims, N, R, w.grams, ctx->stream));
+  for (int k = 0; k < nsweeps; ++k) {
+    s = enqueue_sweep(ctx, Z->dims, N, R, z, mixed, A->a, have32 ? A->a32 : nullptr,
+                      F ? F->a : nullptr, plans, w, solver, gs_iters, normalize,
+                      f_hist ? f_hist + k : nullptr, Z->norm2);
+    if (s != CP_OK) return s;
+  }
+  return CP_OK;
+}
+
+cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t exact,
+                       double* f, double* g, cp_prec prec) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  const bool need64 = (f && exact) || !mixed;
+  if ((s = check_tensor(ctx, Z, need64, mixed && (g || (f && !exact)), "Z")) != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, mixed && (g || (f && !exact)), "A")) != CP_OK) return s;
+  if (!f && !g) return CP_OK;
+  if ((g || (f && !exact)) && !Z->norm2)
+    return set_err(ctx, CP_ERR_INVALID, "cp_objective: g and the fused f need Z->norm2");
+  const int R = A->rank;
+  std::vector<MttkrpPlan> plans;
+  const size_t part = max_partial(Z->dims, N, R, &plans);
+  const int64_t In_last = Z->dims[N - 1];
+  Sizer sz;
+  SweepWS w{};
+  carve_sweep(sz, N, R, part, max_dim(Z->dims, N), &w);
+  sz.take<double>((size_t)In_last * R);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  carve_sweep(ar, N, R, part, max_dim(Z->dims, N), &w);
+  double* Mlast = ar.take<double>((size_t)In_last * R);
+  const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  if (f && exact)
+    HIPCHK(residual_launch(Z->z64, Z->dims, N, R, A->a, w.scal_part, ctx->counters + CNT_RES, f,
+                           ctx->stream));
+  if (g || (f && !exact)) HIPCHK(gram_launch(A->a, nullptr, Z->dims, N, R, w.grams, ctx->stream));
+  if (g) {
+    for (int n = 0; n < N; ++n) {
+      if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32,
+                              plans[n], w.partial)) != CP_OK)
+        return s;
+      EpiDesc d{};
+      d.op = EPI_GRAD;
+      d.R = R;
+      d.N = N;
+      d.n = n;
+      d.nsplit = plans[n].nsplit;
+      d.In = Z->dims[n];
+      d.partial = w.partial;
+      d.A = A->a[n];
+      d.grams = w.grams;
+      d.scal_part = w.scal_part;
+      d.counter = ctx->counters + CNT_EPI;
+      d.scalar_out = ctx->scal;
+      d.accumulate = n > 0;
+      HIPCHK(epi_launch(d, ctx->stream));
+    }
+    HIPCHK(finish_g_launch(ctx->scal, Z->norm2, g, ctx->stream));
+  }
+  if (f && !exact) {
+    if ((s = enqueue_mttkrp(ctx, Z->dims, N, N - 1, R, z, mixed, A->a, (const float* const*)A->a32,
+                            plans[N - 1], w.partial)) != CP_OK)
+      return s;
+    EpiDesc d{};
+    d.op = EPI_STORE_M;
+    d.R = R;
+    d.N = N;
+    d.n = N - 1;
+    d.nsplit = plans[N - 1].nsplit;
+    d.In = In_last;
+    d.partial = w.partial;
+    d.outbuf = Mlast;
+    HIPCHK(epi_launch(d, ctx->stream));
+    HIPCHK(inner_launch(A->a[N - 1], Mlast, In_last * R, w.gram_part, ctx->counters + CNT_DOT,
+                        ctx->scal + 1, ctx->stream));
+    HIPCHK(fused_f_launch(w.grams, N, R, ctx->scal + 1, Z->norm2, f, ctx->stream));
+  }
+  return CP_OK;
+}
+
+cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[CP_MAX_ORDER],
+                      cp_tensor* Zc, cp_prec prec) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  if (!Zc) return set_err(ctx, CP_ERR_INVALID, "Zc is NULL");
+  if (!phat) return set_err(ctx, CP_ERR_INVALID, "phat array is NULL");
+  const int N = Z->order;
+  if (Zc->order != N) return set_err(ctx, CP_ERR_SHAPE, "Zc order %d != %d", Zc->order, N);
+  if (mixed ? !Zc->z32 : !Zc->z64) return set_err(ctx, CP_ERR_INVALID, "Zc has no output buffer for this precision");
+  int64_t dc[CP_MAX_ORDER];
+  std::vector<int> modes;
+  for (int m = 0; m < N; ++m) {
+    dc[m] = phat[m] ? (Z->dims[m] + 1) / 2 : Z->dims[m];
+    if (Zc->dims[m] != dc[m])
+      return set_err(ctx, CP_ERR_SHAPE, "Zc->dims[%d] = %lld, expected %lld", m,
+                     (long long)Zc->dims[m], (long long)dc[m]);
+    if (phat[m]) modes.push_back(m);
+  }
+  const size_t esz = mixed ? 4 : 8;
+  const void* src = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  void* dst = mixed ? (void*)Zc->z32 : (void*)Zc->z64;
+  const int64_t P = numel(Z);
+  if (modes.empty()) {
+    HIPCHK(hipMemcpyAsync(dst, src, P * esz, hipMemcpyDeviceToDevice, ctx->stream));
+    return CP_OK;
+  }
+  // intermediate sizes: after each restricted mode
+  int64_t cur[CP_MAX_ORDER];
+  for (int m = 0; m < N; ++m) cur[m] = Z->dims[m];
+  size_t maxmid = 0;
+  for (size_t q = 0; q + 1 < modes.size(); ++q) {
+    cur[modes[q]] = dc[modes[q]];
+    int64_t p = 1;
+    for (int m = 0; m < N; ++m) p *= cur[m];
+    maxmid = std::max(maxmid, (size_t)p);
+  }
+  Sizer sz;
+  sz.take<char>(maxmid * esz);
+  sz.take<char>(maxmid * esz);
+  if (mixed)
+    for (int m : modes) sz.take<float>((size_t)Z->dims[m] * dc[m]);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  char* buf[2] = {ar.take<char>(maxmid * esz), ar.take<char>(maxmid * esz)};
+  const void* pmat[CP_MAX_ORDER] = {};
+  for (int m : modes) {
+    if (mixed) {
+      float* p32 = ar.take<float>((size_t)Z->dims[m] * dc[m]);
+      HIPCHK(cast_launch(phat[m], p32, Z->dims[m] * dc[m], ctx->stream));
+      pmat[m] = p32;
+    } else {
+      pmat[m] = phat[m];
+    }
+  }
+  for (int m = 0; m < N; ++m) cur[m] = Z->dims[m];
+  const void* in = src;
+  for (size_t q = 0; q < modes.size(); ++q) {
+    const int n = modes[q];
+    void* outp = (q + 1 == modes.size()) ? dst : (void*)buf[q & 1];
+    int64_t L = 1, T = 1;
+    for (int m = 0; m < n; ++m) L *= cur[m];
+    for (int m = n + 1; m < N; ++m) T *= cur[m];
+    const int64_t In = cur[n], Ic = dc[n];
+    GemmDesc g{};
+    if (n == 0) {
+      // C (Ic x T) = P^^T (Ic x In) * X (In x T)
+      g.A = pmat[n]; g.B = in; g.C = outp;
+      g.M = Ic; g.N = T; g.K = In; g.batch = 1;
+      g.a_rs = 1; g.a_cs = Ic; g.a_bs = 0;
+      g.b_rs = 1; g.b_cs = In; g.b_bs = 0;
+      g.c_rs = 1; g.c_cs = Ic; g.c_bs = 0;
+    } else {
+      // per t: C_t (L x Ic) = X_t (L x In) * P^ (In x Ic)
+      g.A = in; g.B = pmat[n]; g.C = outp;
+      g.M = L; g.N = Ic; g.K = In; g.batch = T;
+      g.a_rs = 1; g.a_cs = L; g.a_bs = L * In;
+      g.b_rs = Ic; g.b_cs = 1; g.b_bs = 0;
+      g.c_rs = 1; g.c_cs = L; g.c_bs = L * Ic;
+    }
+    if (g.batch > 65535) return set_err(ctx, CP_ERR_UNSUPPORTED, "cp_restrict: batch %lld too large", (long long)g.batch);
+    HIPCHK(gemm_launch(g, mixed, ctx->stream));
+    cur[n] = Ic;
+    in = outp;
+  }
+  return CP_OK;
+}
+
+cp_status cp_prolong(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const double* phat,
+                     const double* Ac, const double* Ac_tilde, double* A) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!Ac || !A) return set_err(ctx, CP_ERR_INVALID, "cp_prolong: NULL pointer");
+  if (I < 1 || Ic < 1 || R < 1 || R > CP_MAX_RANK) return set_err(ctx, CP_ERR_SHAPE, "cp_prolong: bad sizes");
+  if (!phat && Ic != I) return set_err(ctx, CP_ERR_SHAPE, "cp_prolong: identity transfer needs Ic == I");
+  HIPCHK(prolong_launch(I, Ic, R, phat, Ac, Ac_tilde, A, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_restrict_factor(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const double* phat,
+                             const double* A, double* Ac) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!A || !Ac) return set_err(ctx, CP_ERR_INVALID, "cp_restrict_factor: NULL pointer");
+  if (I < 1 || Ic < 1 || R < 1 || R > CP_MAX_RANK) return set_err(ctx, CP_ERR_SHAPE, "cp_restrict_factor: bad sizes");
+  if (!phat && Ic != I) return set_err(ctx, CP_ERR_SHAPE, "cp_restrict_factor: identity transfer needs Ic == I");
+  HIPCHK(restrict_factor_launch(I, Ic, R, phat, A, Ac, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!w || !phat) return set_err(ctx, CP_ERR_INVALID, "cp_transfer_build: NULL pointer");
+  if (I < 2) return set_err(ctx, CP_ERR_SHAPE, "cp_transfer_build: I = %lld < 2", (long long)I);
+  const int64_t Ic = (I + 1) / 2;
+  cp_status s = ensure_ws(ctx, align_up(2 * Ic * sizeof(double)));
+  if (s != CP_OK) return s;
+  HIPCHK(transfer_build_launch(I, w, phat, (double*)ctx->ws, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_sort(cp_ctx ctx, const int64_t* dims, int32_t order, cp_factors* A) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!dims) return set_err(ctx, CP_ERR_INVALID, "cp_sort: dims is NULL");
+  if (order < 1 || order > CP_MAX_ORDER) return set_err(ctx, CP_ERR_SHAPE, "cp_sort: bad order");
+  cp_status s = check_factors(ctx, A, order, false, "A");
+  if (s != CP_OK) return s;
+  bool have32 = true;
+  for (int m = 0; m < order; ++m) have32 = have32 && A->a32[m];
+  HIPCHK(sort_launch(A->a, have32 ? A->a32 : nullptr, dims, order, A->rank, nullptr, ctx->stream));
+  return CP_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// CP-FAS V-cycle (Algorithm 2).  Host recursion over the levels; every step is
+// a kernel enqueued on the context's stream.
+namespace {
+
+struct FasLevel {
+  int64_t dims[CP_MAX_ORDER];
+  const void* z = nullptr;
+  const double* phat[CP_MAX_ORDER] = {};
+  double* A[CP_MAX_ORDER] = {};
+  float* A32[CP_MAX_ORDER] = {};
+  double* At[CP_MAX_ORDER] = {};
+  double* F[CP_MAX_ORDER] = {};
+  double* H[CP_MAX_ORDER] = {};
+  double* grams = nullptr;
+  std::vector<MttkrpPlan> plans;
+  bool has32 = false;
+};
+
+struct FasRun {
+  cp_ctx ctx;
+  int N, R, L;
+  bool mixed;
+  cp_fas_params p;
+  std::vector<FasLevel> lv;
+  double* partial;
+  double* gram_part;
+  double* scal_part;
+};
+
+cp_status fas_relax(FasRun& r, int l, int times) {
+  cp_ctx ctx = r.ctx;
+  FasLevel& L = r.lv[l];
+  if (times <= 0) return CP_OK;
+  HIPCHK(gram_launch(L.A, L.has32 ? L.A32 : nullptr, L.dims, r.N, r.R, L.grams, ctx->stream));
+  SweepWS w{L.grams, r.partial, r.gram_part, r.scal_part};
+  for (int k = 0; k < times; ++k) {
+    cp_status s = enqueue_sweep(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A,
+                                L.has32 ? L.A32 : nullptr, l == 0 ? nullptr : L.F, L.plans, w,
+                                CP_SOLVE_GS, r.p.gs_iters, l == 0 ? 1 : 0, nullptr, nullptr);
+    if (s != CP_OK) return s;
+  }
+  return CP_OK;
+}
+
+// H^(n)(A) = A^(n) Gamma^(n) - Z_(n) Phi^(n) for every mode of level l.
+cp_status fas_H(FasRun& r, int l, double* const* A, float* const* A32, double* const* Hout) {
+  cp_ctx ctx = r.ctx;
+  FasLevel& L = r.lv[l];
+  HIPCHK(gram_launch(A, A32, L.dims, r.N, r.R, L.grams, ctx->stream));
+  for (int n = 0; n < r.N; ++n) {
+    cp_status s = enqueue_mttkrp(ctx, L.dims, r.N, n, r.R, L.z, r.mixed, (const double* const*)A,
+                                 (const float* const*)A32, L.plans[n], r.partial);
+    if (s != CP_OK) return s;
+    EpiDesc d{};
+    d.op = EPI_H;
+    d.R = r.R;
+    d.N = r.N;
+    d.n = n;
+    d.nsplit = L.plans[n].nsplit;
+    d.In = L.dims[n];
+    d.partial = r.partial;
+    d.A = A[n];
+    d.grams = L.grams;
+    d.outbuf = Hout[n];
+    HIPCHK(epi_launch(d, ctx->stream));
+  }
+  return CP_OK;
+}
+
+cp_status fas_vcycle_rec(FasRun& r, int l) {
+  cp_ctx ctx = r.ctx;
+  if (l == r.L - 1) return fas_relax(r, l, r.p.nuc);
+  cp_status s = fas_relax(r, l, r.p.nu1);
+  if (s != CP_OK) return s;
+  FasLevel& cur = r.lv[l];
+  FasLevel& nx = r.lv[l + 1];
+  const int R = r.R;
+  // coarse initial guess A~_c (eq. (21))
+  for (int n = 0; n < r.N; ++n)
+    HIPCHK(restrict_factor_launch(cur.dims[n], nx.dims[n], R, cur.phat[n], cur.A[n], nx.At[n],
+                                  ctx->stream));
+  // H(A) on this level and H_c(A~_c) on the next
+  if ((s = fas_H(r, l, cur.A, cur.has32 ? cur.A32 : nullptr, cur.H)) != CP_OK) return s;
+  if ((s = fas_H(r, l + 1, nx.At, nx.has32 ? nx.A32 : nullptr, nx.H)) != CP_OK) return s;
+  // coarse right-hand side (eq. (27)); modes that are not coarsened use ic_rule
+  for (int n = 0; n < r.N; ++n) {
+    const double* F = (l == 0) ? nullptr : cur.F[n];
+    if (cur.phat[n])
+      HIPCHK(fas_rhs_launch(cur.dims[n], nx.dims[n], R, cur.phat[n], F, cur.H[n], nx.H[n], nx.F[n],
+                            ctx->stream));
+    else
+      HIPCHK(fas_rhs_identity_launch(cur.dims[n] * R, F, cur.H[n], nx.H[n], r.p.ic_rule, nx.F[n],
+                                     ctx->stream));
+    HIPCHK(copy_launch(nx.At[n], nx.A[n], nx.dims[n] * R, ctx->stream));
+  }
+  if ((s = fas_vcycle_rec(r, l + 1)) != CP_OK) return s;
+  // coarse-grid correction (eq. (28))
+  for (int n = 0; n < r.N; ++n)
+    HIPCHK(prolong_launch(cur.dims[n], nx.dims[n], R, cur.phat[n], nx.A[n], nx.At[n], cur.A[n],
+                          ctx->stream));
+  return fas_relax(r, l, r.p.nu2);
+}
+
+}  // namespace
+
+extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t nlevels,
+                                   cp_factors* A, const cp_fas_params* params, cp_prec prec) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if (!levels || nlevels < 1) return set_err(ctx, CP_ERR_INVALID, "cp_fas_vcycle: no levels");
+  const int N = levels[0].z.order;
+  for (int l = 0; l < nlevels; ++l) {
+    char name[32];
+    snprintf(name, sizeof(name), "levels[%d].z", l);
+    if ((s = check_tensor(ctx, &levels[l].z, !mixed, mixed, name)) != CP_OK) return s;
+    if (levels[l].z.order != N) return set_err(ctx, CP_ERR_SHAPE, "level %d has order %d != %d", l, levels[l].z.order, N);
+    if (l + 1 < nlevels) {
+      for (int n = 0; n < N; ++n) {
+        const int64_t want = levels[l].phat[n] ? (levels[l].z.dims[n] + 1) / 2 : levels[l].z.dims[n];
+        if (levels[l + 1].z.dims[n] != want)
+          return set_err(ctx, CP_ERR_SHAPE, "level %d mode %d: dims %lld, expected %lld", l + 1, n,
+                         (long long)levels[l + 1].z.dims[n], (long long)want);
+      }
+    }
+  }
+  if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
+  cp_fas_params p{1, 1, 50, 10, 0};
+  if (params) p = *params;
+  if (p.nu1 < 0 || p.nu2 < 0 || p.nuc < 0 || p.gs_iters < 1 || p.gs_iters > 1000 ||
+      (p.ic_rule != 0 && p.ic_rule != 1))
+    return set_err(ctx, CP_ERR_INVALID, "cp_fas_vcycle: bad parameters");
+  const int R = A->rank;
+  FasRun r{ctx, N, R, nlevels, mixed, p, std::vector<FasLevel>(nlevels), nullptr, nullptr, nullptr};
+  bool have32 = true;
+  for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
+  size_t maxpart = 0;
+  int64_t maxI = 0;
+  for (int l = 0; l < nlevels; ++l) {
+    FasLevel& L = r.lv[l];
+    for (int n = 0; n < N; ++n) {
+      L.dims[n] = levels[l].z.dims[n];
+      L.phat[n] = (l + 1 < nlevels) ? levels[l].phat[n] : nullptr;
+    }
+    L.z = mixed ? (const void*)levels[l].z.z32 : (const void*)levels[l].z.z64;
+    maxpart = std::max(maxpart, max_partial(L.dims, N, R, &L.plans));
+    maxI = std::max(maxI, max_dim(L.dims, N));
+  }
+  auto carve = [&](auto& c, bool real) {
+    for (int l = 0; l < nlevels; ++l) {
+      FasLevel& L = r.lv[l];
+      for (int n = 0; n < N; ++n) {
+        const size_t cnt = (size_t)L.dims[n] * R;
+        if (l >= 1) {
+          double* a = c.template take<double>(cnt);
+          double* at = c.template take<double>(cnt);
+          double* f = c.template take<double>(cnt);
+          float* a32 = (mixed || have32) ? c.template take<float>(cnt) : nullptr;
+          if (real) { L.A[n] = a; L.At[n] = at; L.F[n] = f; L.A32[n] = a32; }
+        }
+        double* h = c.template take<double>(cnt);
+        if (real) L.H[n] = h;
+      }
+      double* g = c.template take<double>((size_t)N * R * R);
+      if (real) L.grams = g;
+    }
+    double* part = c.template take<double>(maxpart);
+    const int64_t nwg = epi_blocks(maxI);
+    double* gp = c.template take<double>((size_t)nwg * R * R);
+    double* sp = c.template take<double>((size_t)std::max<int64_t>(nwg, 2048));
+    if (real) { r.partial = part; r.gram_part = gp; r.scal_part = sp; }
+  };
+  Sizer sz;
+  carve(sz, false);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  carve(ar, true);
+  for (int n = 0; n < N; ++n) {
+    r.lv[0].A[n] = A->a[n];
+    r.lv[0].A32[n] = A->a32[n];
+  }
+  for (int l = 0; l < nlevels; ++l) r.lv[l].has32 = (l == 0) ? have32 : (mixed || have32);
+  if ((s = fas_vcycle_rec(r, 0)) != CP_OK) return s;
+  if (r.lv[0].has32)   // shadows of the finest factors follow the last correction
+    HIPCHK(gram_launch(A->a, A->a32, r.lv[0].dims, N, R, r.lv[0].grams, ctx->stream));
+  return CP_OK;
+}

@@ -1,0 +1,169 @@
+// Internal declarations shared by the HIP translation units of libcpamg.
+// Not part of the public ABI (see include/cpamg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cpamg.h"
+
+namespace cpamg {
+
+constexpr int kMaxOrder = CP_MAX_ORDER;
+constexpr int kMaxRank = CP_MAX_RANK;
+constexpr int kThreads = 256;   // threads per workgroup for every kernel (4 waves)
+
+// Row of the 16x16 MFMA result held in element v of a lane in lane group g = l/16
+// (column = l % 16).  v_mfma_f64_16x16x4f64 interleaves rows (g + 4v);
+// v_mfma_f32_16x16x4f32 gives each lane group four consecutive rows (4g + v).
+template <typename T> __device__ __forceinline__ constexpr int mfma_row(int g, int v);
+template <> __device__ __forceinline__ constexpr int mfma_row<double>(int g, int v) { return g + 4 * v; }
+template <> __device__ __forceinline__ constexpr int mfma_row<float>(int g, int v) { return 4 * g + v; }
+
+// ---------------------------------------------------------------------------
+// MTTKRP launch descriptor (passed by value to the kernels)
+// ---------------------------------------------------------------------------
+// The tensor is viewed as (I0, I1, S): mode 0 (fastest), mode 1, and the
+// "stripe" index s over modes 2..N-1 (mode 2 fastest).  Three kernel kinds:
+//   kind 1 (n == 0): GEMM rows = i0, contraction over i1, Hadamard weight per stripe
+//   kind 2 (n == 1): GEMM rows = i1, contraction over i0, Hadamard weight per stripe
+//   kind 3 (n >= 2): GEMM rows = i1, contraction over i0, Hadamard-reduce of the
+//                    rows with A^(1) and the stripe weight into output row s_n
+struct MttkrpDesc {
+  const void* z;                  // tensor (T*)
+  const void* ak;                 // factor of the contracted mode, in T (B operand)
+  const double* a64[kMaxOrder];   // FP64 factors (Hadamard stage)
+  double* out;                    // partials [nsplit][I_n][R] (or M when nsplit == 1)
+  int64_t I0, I1, S;              // view extents
+  int64_t In;                     // extent of the output mode
+  int32_t N, n, R;
+  int32_t kind;
+  // stripe decoding: the stripe index is s = sum_j s_j * sst[j] over stripe modes
+  int32_t ns;                     // number of stripe modes (N - 2, >= 0)
+  int64_t sext[kMaxOrder];        // extents of stripe modes (modes 2..N-1)
+  int64_t sst[kMaxOrder];         // strides in the stripe index
+  // work split
+  int32_t ngroups;                // kind 1: row panels of 64; kind 2: row groups; kind 3: outputs I_n
+  int32_t nsplit;                 // workgroups per group
+  int64_t units;                  // units per group (a unit = one stripe (kind 1/2) or
+                                  // one (row group, rest stripe) pair (kind 3)) times ksplit
+  int64_t chunk;                  // units per workgroup
+  int32_t ksplit;                 // contraction range split into this many pieces
+  int32_t kchunk;                 // contraction length per piece (multiple of 16)
+  int32_t rgroups;                // kind 3: number of row groups over I1
+  int64_t rest_count;             // kind 3: number of stripes per output value
+};
+
+// planner + launcher (mttkrp.hip)
+struct MttkrpPlan {
+  int32_t kind, nsplit, ngroups, ksplit, kchunk, rgroups;
+  int64_t chunk, units;
+  size_t partial_doubles;   // nsplit * I_n * R
+  int32_t tw;               // row tiles per wave (kind 2/3)
+  int32_t nt;               // 16-column tiles (ceil(R/16))
+};
+
+MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs);
+hipError_t mttkrp_launch(const MttkrpPlan& plan, const int64_t* dims, int N, int n, int R,
+                         const void* z, bool fp32, const double* const* a64,
+                         const float* const* a32, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Mode epilogue: reduce MTTKRP partials and act on the rows
+// ---------------------------------------------------------------------------
+enum EpiOp : int32_t {
+  EPI_STORE_M = 0,   // M = sum of partials (cp_mttkrp)
+  EPI_UPDATE = 1,    // A^(n) <- solve((M + F) , Gamma)  + Gram^(n) + objective pieces
+  EPI_GRAD = 2,      // accumulate ||A Gamma - M||^2 into a scalar
+  EPI_H = 3,         // H = A Gamma - M (FAS operator) into a buffer
+};
+
+struct EpiDesc {
+  int32_t op, solver, gs_iters, R, N, n;
+  int32_t nsplit;
+  int64_t In;
+  const double* partial;      // [nsplit][In][R]
+  const double* F;            // optional (I_n x R) right-hand side
+  double* A;                  // factor n (FP64)
+  float* A32;                 // optional shadow
+  double* outbuf;             // EPI_STORE_M / EPI_H target
+  double* grams;              // [N][R][R]  (Upsilon of each mode)
+  const double* chol;         // [R][R] factor of Gamma^(n) (written by prep kernel) or pinv
+  const int32_t* chol_kind;   // 0 = Cholesky L, 1 = pseudoinverse matrix, 2 = unusable
+  double* gram_part;          // [nwg][R][R] workspace
+  double* scal_part;          // [nwg] workspace
+  int32_t* counter;           // last-block counter (zero between launches)
+  double* scalar_out;         // objective: f_hist slot; grad: accumulator
+  const double* norm2;        // ||Z||^2 (device)
+  uint32_t* flags;
+  int32_t want_obj;           // EPI_UPDATE: write fused f into scalar_out
+  int32_t accumulate;         // EPI_GRAD: add to scalar_out instead of overwrite
+};
+
+hipError_t epi_launch(const EpiDesc& d, hipStream_t st);
+int epi_rows_per_wg();
+
+// Gamma^(n) factorization for the next update (one workgroup)
+hipError_t gamma_prep_launch(const double* grams, int N, int n, int R, double* chol,
+                             int32_t* chol_kind, uint32_t* flags, int32_t solver,
+                             hipStream_t st);
+
+// Grams of every mode at fixed A; optionally refresh FP32 shadows
+hipError_t gram_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
+                       double* grams, hipStream_t st);
+
+// Normalization eq. (10) using the diagonals of the Grams; rescales Grams too
+hipError_t normalize_launch(double* const* A, float* const* A32, const int64_t* dims, int N,
+                            int R, double* grams, hipStream_t st);
+
+// exact residual ||Z - [[A]]||^2 / 2
+hipError_t residual_launch(const double* z, const int64_t* dims, int N, int R,
+                           const double* const* A, double* part, int32_t* counter, double* f,
+                           hipStream_t st);
+
+// fused objective from a Gram set, inner product and norm (one thread)
+hipError_t fused_f_launch(const double* grams, int N, int R, const double* inner,
+                          const double* norm2, double* f, hipStream_t st);
+// g = sqrt(acc)/sqrt(norm2)
+hipError_t finish_g_launch(const double* acc, const double* norm2, double* g, hipStream_t st);
+hipError_t inner_launch(const double* A, const double* M, int64_t count, double* part,
+                        int32_t* counter, double* out, hipStream_t st);
+
+// utilities
+hipError_t cast_launch(const double* src, float* dst, int64_t count, hipStream_t st);
+hipError_t norm2_launch(const double* z, int64_t count, double* part, int32_t* counter,
+                        double* out, hipStream_t st);
+hipError_t fill_launch(double* dst, double v, int64_t count, hipStream_t st);
+hipError_t copy_launch(const double* src, double* dst, int64_t count, hipStream_t st);
+
+// transfer operators (transfer.hip)
+hipError_t transfer_build_launch(int64_t I, const double* w, double* phat, double* ws /*2*Ic*/,
+                                 hipStream_t st);
+hipError_t prolong_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* Ac,
+                          const double* Act, double* A, hipStream_t st);
+hipError_t restrict_factor_launch(int64_t I, int64_t Ic, int R, const double* phat,
+                                  const double* A, double* Ac, hipStream_t st);
+// Fc = Hc + P^^T (F - H)   (F may be NULL = 0)
+hipError_t fas_rhs_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* F,
+                          const double* H, const double* Hc, double* Fc, hipStream_t st);
+// Fc = F - H + Hc (tau rule, identity transfer) or Fc = F (literal)
+hipError_t fas_rhs_identity_launch(int64_t count, const double* F, const double* H,
+                                   const double* Hc, int literal, double* Fc, hipStream_t st);
+
+// batched strided GEMM on the matrix cores: C[b] = A[b] * B[b]
+struct GemmDesc {
+  const void* A; const void* B; void* C;
+  int64_t M, N, K, batch;
+  int64_t a_rs, a_cs, a_bs;
+  int64_t b_rs, b_cs, b_bs;
+  int64_t c_rs, c_cs, c_bs;
+};
+hipError_t gemm_launch(const GemmDesc& d, bool fp32, hipStream_t st);
+
+hipError_t sort_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
+                       double* scratch, hipStream_t st);
+
+}  // namespace cpamg

@@ -1,0 +1,427 @@
+// Dense MTTKRP  M^(n) = Z_(n) Phi^(n)  (eq. (6)-(7)) on gfx950.
+//
+// Stage 1 is a GEMM on the matrix cores that contracts one mode of Z with its
+// factor: v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (mixed form,
+// FP32 accumulation).  Stage 2 is a Hadamard-reduce of the GEMM tile with the
+// factors of the remaining modes, in FP64.  The Khatri-Rao matrix is never
+// formed.  The tensor is streamed once per call with 16- or 32-byte loads per
+// lane; the GEMM operand layout makes every group of 16 lanes read 64
+// consecutive entries (kind 1) or every 4 lanes one 16-entry fibre segment
+// (kinds 2/3).
+//
+// MFMA 16x16x4 operand layout (one 64-lane wave): lane l supplies
+//   A[m = l%16][k = l/16], B[k = l/16][n = l%16], and receives
+//   D[m = mfma_row<T>(l/16, v)][n = l%16], v = 0..3 (see internal.hpp).
+#include "internal.hpp"
+#include "smallla.hpp"
+
+namespace cpamg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { typedef d4 type; };
+template <> struct Vec4<float> { typedef f4 type; };
+
+__device__ __forceinline__ d4 mma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Load 4 consecutive entries p[0..3]; entries at index >= nvalid read as 0.
+template <typename T, bool VEC>
+__device__ __forceinline__ typename Vec4<T>::type load4(const T* __restrict__ p, int nvalid) {
+  typedef typename Vec4<T>::type V;
+  V v;
+  if (VEC) {
+    if (nvalid >= 4) {
+      v = *reinterpret_cast<const V*>(p);
+    } else {
+      v = V{0, 0, 0, 0};
+    }
+  } else {
+    v[0] = nvalid > 0 ? p[0] : T(0);
+    v[1] = nvalid > 1 ? p[1] : T(0);
+    v[2] = nvalid > 2 ? p[2] : T(0);
+    v[3] = nvalid > 3 ? p[3] : T(0);
+  }
+  return v;
+}
+
+// Product of the stripe-mode factors at stripe s, column col (skip mode `skip`).
+__device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, int col, int skip) {
+  if (col >= d.R) return 0.0;
+  double w = 1.0;
+  for (int j = 0; j < d.ns; ++j) {
+    const int m = j + 2;
+    const int64_t sj = (s / d.sst[j]) % d.sext[j];
+    if (m != skip) w *= d.a64[m][sj * d.R + col];
+  }
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// kind 1: output mode 0.  GEMM rows = i0 (64 per wave: 4 sub-tiles of 16 with
+// row i0 = p*64 + 16*(l/16)... see below), contraction over i1, stripes weighted.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool VEC>
+__global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
+  typedef typename Vec4<T>::type V;
+  __shared__ double red[4 * 64 * 16 * NT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g4 = lane >> 4;
+  const int grp = blockIdx.x % d.ngroups;
+  const int split = blockIdx.x / d.ngroups;
+  const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
+  const T* __restrict__ ak = reinterpret_cast<const T*>(d.ak);
+  const int R = d.R;
+  const int64_t I0 = d.I0, I1 = d.I1;
+  const int64_t i0b = (int64_t)grp * 64 + 4 * r;     // first of this lane's 4 rows
+  const int nrow = (int)((I0 - i0b) < 4 ? ((I0 - i0b) > 0 ? (I0 - i0b) : 0) : 4);
+
+  double acc[4][NT][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][t][v] = 0.0;
+
+  const int64_t ubeg = (int64_t)split * d.chunk;
+  const int64_t uend = min(d.units, ubeg + d.chunk);
+  for (int64_t u = ubeg + wave; u < uend; u += 4) {
+    const int64_t s = u / d.ksplit;
+    const int kp = (int)(u % d.ksplit);
+    const int64_t kbeg = (int64_t)kp * d.kchunk;
+    const int64_t kend = min(I1, kbeg + d.kchunk);
+    double w[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w[t] = stripe_weight(d, s, t * 16 + r, -1);
+    typename Vec4<T>::type D[4][NT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) D[a][t] = V{0, 0, 0, 0};
+    const T* __restrict__ zs = z + (size_t)s * I0 * I1 + i0b;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+      V zv[4];
+      T b[4][NT];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i1 = k0 + 4 * g4 + e;
+        const bool ok = i1 < kend;
+        zv[e] = load4<T, VEC>(zs + (ok ? i1 : 0) * I0, ok ? nrow : 0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int col = t * 16 + r;
+          b[e][t] = (ok && col < R) ? ak[i1 * R + col] : T(0);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) D[a][t] = mma(zv[e][a], b[e][t], D[a][t]);
+    }
+    // Hadamard-reduce with the stripe weight (FP64)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][t][v] += (double)D[a][t][v] * w[t];
+  }
+  // deterministic cross-wave reduction: GEMM row m holds i0 = grp*64 + 4*m + a
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        red[(wave * 64 + 4 * mfma_row<T>(g4, v) + a) * (16 * NT) + t * 16 + r] = acc[a][t][v];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * 16 * NT; idx += kThreads) {
+    const int row = idx / (16 * NT), col = idx % (16 * NT);
+    const int64_t i0 = (int64_t)grp * 64 + row;
+    if (col < R && i0 < I0) {
+      const double sum = red[idx] + red[64 * 16 * NT + idx] + red[2 * 64 * 16 * NT + idx] +
+                         red[3 * 64 * 16 * NT + idx];
+      d.out[((size_t)split * d.In + i0) * R + col] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kinds 2 and 3: GEMM rows = i1 (16*TW per wave), contraction over i0.
+// kind 2 (n == 1): rows are the outputs; kind 3 (n >= 2): rows are reduced
+// with A^(1)(i1, r) into output s_n.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int TW, bool KIND3, bool VEC>
+__global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
+  typedef typename Vec4<T>::type V;
+  constexpr int ROWS = 16 * TW;
+  __shared__ double red[KIND3 ? 4 * 16 * NT : 4 * ROWS * 16 * NT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g4 = lane >> 4;
+  const int grp = blockIdx.x % d.ngroups;
+  const int split = blockIdx.x / d.ngroups;
+  const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
+  const T* __restrict__ ak = reinterpret_cast<const T*>(d.ak);
+  const int R = d.R;
+  const int64_t I0 = d.I0, I1 = d.I1;
+
+  // kind 2: acc[tw][t][v] holds rows grp*ROWS + tw*16 + mfma_row<T>(g4, v)
+  // kind 3: acc[0][t][0] holds the running sum for column t*16 + r
+  double acc[TW][NT][4];
+#pragma unroll
+  for (int a = 0; a < TW; ++a)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][t][v] = 0.0;
+
+  const int64_t ubeg = (int64_t)split * d.chunk;
+  const int64_t uend = min(d.units, ubeg + d.chunk);
+  int64_t stride_n = 1;
+  int jn = d.n - 2;
+  if (KIND3) stride_n = d.sst[jn];
+  for (int64_t u = ubeg + wave; u < uend; u += 4) {
+    const int kp = (int)(u % d.ksplit);
+    const int64_t uu = u / d.ksplit;
+    int64_t s, rowbase;
+    if (KIND3) {
+      const int64_t g = uu % d.rgroups;
+      int64_t q = uu / d.rgroups;
+      rowbase = g * ROWS;
+      // stripe from output value grp (mode n) and rest index q (other stripe modes)
+      s = (int64_t)grp * stride_n;
+      for (int j = 0; j < d.ns; ++j) {
+        if (j == jn) continue;
+        const int64_t sj = q % d.sext[j];
+        q /= d.sext[j];
+        s += sj * d.sst[j];
+      }
+    } else {
+      s = uu;
+      rowbase = (int64_t)grp * ROWS;
+    }
+    const int64_t kbeg = (int64_t)kp * d.kchunk;
+    const int64_t kend = min(I0, kbeg + d.kchunk);
+    double w[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w[t] = stripe_weight(d, s, t * 16 + r, KIND3 ? d.n : -1);
+    V D[TW][NT];
+#pragma unroll
+    for (int a = 0; a < TW; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) D[a][t] = V{0, 0, 0, 0};
+    const T* __restrict__ zs = z + (size_t)s * I0 * I1;
+    int nrowok[TW];
+#pragma unroll
+    for (int a = 0; a < TW; ++a) nrowok[a] = (rowbase + a * 16 + r) < I1;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+      const int64_t kl = k0 + 4 * g4;
+      const int64_t nk = kend - kl;
+      const int nval = nk >= 4 ? 4 : (nk > 0 ? (int)nk : 0);
+      V zv[TW];
+#pragma unroll
+      for (int a = 0; a < TW; ++a) {
+        const int64_t i1 = rowbase + a * 16 + r;
+        zv[a] = load4<T, VEC>(zs + (nrowok[a] ? i1 : 0) * I0 + (nval ? kl : 0),
+                              nrowok[a] ? nval : 0);
+      }
+      T b[4][NT];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int col = t * 16 + r;
+          b[e][t] = (e < nval && col < R) ? ak[(kl + e) * R + col] : T(0);
+        }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < TW; ++a)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) D[a][t] = mma(zv[a][e], b[e][t], D[a][t]);
+    }
+    // Hadamard-reduce (FP64)
+    if (KIND3) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int col = t * 16 + r;
+        double part = 0.0;
+#pragma unroll
+        for (int a = 0; a < TW; ++a)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t i1 = rowbase + a * 16 + mfma_row<T>(g4, v);
+            const double a1 = (i1 < I1 && col < R) ? d.a64[1][i1 * R + col] : 0.0;
+            part += (double)D[a][t][v] * a1;
+          }
+        acc[0][t][0] += part * w[t];
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < TW; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[a][t][v] += (double)D[a][t][v] * w[t];
+    }
+  }
+  if (KIND3) {
+    // reduce over the 4 lane groups (rows), then over waves in fixed order
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double x = acc[0][t][0];
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      if (g4 == 0) red[wave * 16 * NT + t * 16 + r] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 * NT) {
+      const int col = threadIdx.x;
+      if (col < R) {
+        const double sum = red[col] + red[16 * NT + col] + red[32 * NT + col] + red[48 * NT + col];
+        d.out[((size_t)split * d.In + grp) * R + col] = sum;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < TW; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          red[(wave * ROWS + a * 16 + mfma_row<T>(g4, v)) * (16 * NT) + t * 16 + r] = acc[a][t][v];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ROWS * 16 * NT; idx += kThreads) {
+      const int row = idx / (16 * NT), col = idx % (16 * NT);
+      const int64_t i1 = (int64_t)grp * ROWS + row;
+      if (col < R && i1 < I1) {
+        const int st = ROWS * 16 * NT;
+        const double sum = red[idx] + red[st + idx] + red[2 * st + idx] + red[3 * st + idx];
+        d.out[((size_t)split * d.In + i1) * R + col] = sum;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: planning and dispatch
+// ---------------------------------------------------------------------------
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs) {
+  MttkrpPlan p{};
+  const int64_t I0 = dims[0], I1 = dims[1];
+  int64_t S = 1;
+  for (int m = 2; m < N; ++m) S *= dims[m];
+  p.nt = R <= 16 ? 1 : 2;
+  p.tw = 2;
+  const int64_t rows = 16 * p.tw;
+  int64_t base_units;
+  int64_t K;
+  if (n == 0) {
+    p.kind = 1;
+    p.ngroups = (int32_t)ceil_div(I0, 64);
+    base_units = S;
+    K = I1;
+  } else if (n == 1) {
+    p.kind = 2;
+    p.ngroups = (int32_t)ceil_div(I1, rows);
+    base_units = S;
+    K = I0;
+  } else {
+    p.kind = 3;
+    p.ngroups = (int32_t)dims[n];
+    p.rgroups = (int32_t)ceil_div(I1, rows);
+    base_units = p.rgroups * (S / dims[n]);
+    K = I0;
+  }
+  // split the contraction when there are too few (group, unit) pairs for the chip
+  const int64_t want_units = (int64_t)target_wgs * 4;
+  int64_t ks = 1;
+  const int64_t kchunks16 = ceil_div(K, 16);
+  if ((int64_t)p.ngroups * base_units < want_units)
+    ks = std::min<int64_t>(kchunks16, ceil_div(want_units, (int64_t)p.ngroups * base_units));
+  if (ks < 1) ks = 1;
+  int64_t kchunk = ceil_div(kchunks16, ks) * 16;
+  ks = ceil_div(K, kchunk);
+  p.ksplit = (int32_t)ks;
+  p.kchunk = (int32_t)kchunk;
+  p.units = base_units * ks;
+  int64_t nsplit = std::max<int64_t>(1, target_wgs / p.ngroups);
+  nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, ceil_div(p.units, 4)));
+  p.chunk = ceil_div(p.units, nsplit);
+  p.nsplit = (int32_t)ceil_div(p.units, p.chunk);
+  p.partial_doubles = (size_t)p.nsplit * dims[n] * R;
+  return p;
+}
+
+template <typename T, int NT>
+static hipError_t launch_typed(const MttkrpPlan& p, const MttkrpDesc& d, bool vec,
+                               hipStream_t st) {
+  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit)), block(kThreads);
+  if (p.kind == 1) {
+    if (vec) hipLaunchKernelGGL((mttkrp_kind1<T, NT, true>), grid, block, 0, st, d);
+    else hipLaunchKernelGGL((mttkrp_kind1<T, NT, false>), grid, block, 0, st, d);
+  } else if (p.kind == 2) {
+    if (vec) hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, false, true>), grid, block, 0, st, d);
+    else hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, false, false>), grid, block, 0, st, d);
+  } else {
+    if (vec) hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, true, true>), grid, block, 0, st, d);
+    else hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, true, false>), grid, block, 0, st, d);
+  }
+  return hipGetLastError();
+}
+
+hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
+                         const void* z, bool fp32, const double* const* a64,
+                         const float* const* a32, double* out, hipStream_t st) {
+  MttkrpDesc d{};
+  d.z = z;
+  d.N = N;
+  d.n = n;
+  d.R = R;
+  d.kind = p.kind;
+  d.I0 = dims[0];
+  d.I1 = dims[1];
+  d.S = 1;
+  for (int m = 2; m < N; ++m) d.S *= dims[m];
+  d.In = dims[n];
+  for (int m = 0; m < N; ++m) d.a64[m] = a64[m];
+  const int kmode = (p.kind == 1) ? 1 : 0;
+  d.ak = fp32 ? (const void*)a32[kmode] : (const void*)a64[kmode];
+  d.out = out;
+  d.ns = N - 2 > 0 ? N - 2 : 0;
+  int64_t st_acc = 1;
+  for (int j = 0; j < d.ns; ++j) {
+    d.sext[j] = dims[j + 2];
+    d.sst[j] = st_acc;
+    st_acc *= dims[j + 2];
+  }
+  d.ngroups = p.ngroups;
+  d.nsplit = p.nsplit;
+  d.units = p.units;
+  d.chunk = p.chunk;
+  d.ksplit = p.ksplit;
+  d.kchunk = p.kchunk;
+  d.rgroups = p.rgroups;
+  d.rest_count = (p.kind == 3) ? d.S / dims[n] : 0;
+  // 4-wide vector loads need the contiguous extent to be a multiple of 4 and
+  // an aligned base
+  const size_t esz = fp32 ? 4 : 8;
+  const bool vec = (dims[0] % 4 == 0) && (((uintptr_t)z) % (4 * esz) == 0);
+  if (fp32) {
+    return p.nt == 1 ? launch_typed<float, 1>(p, d, vec, st) : launch_typed<float, 2>(p, d, vec, st);
+  }
+  return p.nt == 1 ? launch_typed<double, 1>(p, d, vec, st) : launch_typed<double, 2>(p, d, vec, st);
+}
+
+}  // namespace cpamg

@@ -1,0 +1,236 @@
+// Transfer operators and coarse tensors (Section 4.1, Algorithm 1/2):
+//   B = P^T P, L = chol(B), P^ = P L^{-T}   (geometric coarsening, Section 4.3)
+//   Zc = Z x_n P^^T  (mode-n GEMM on the matrix cores)
+//   A = P^ Ac,  A += P^ (Ac - A~c),  A~c = P^^T A,  Fc = Hc + P^^T (F - H)
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace cpamg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// P^ from interpolation weights.  For the 0-based point i: even i is coarse
+// point i/2 (injection); odd i interpolates from (i-1)/2 (weight w[i][0]) and,
+// when i+1 < I, from (i+1)/2 (weight w[i][1]).  B = P^T P is tridiagonal:
+//   B_jj = 1 + w[2j-1][1]^2 + w[2j+1][0]^2,   B_{j,j+1} = w[2j+1][0] w[2j+1][1]
+// (terms whose row does not exist or has a single neighbour vanish).
+__global__ __launch_bounds__(kThreads) void transfer_kernel(int64_t I, const double* __restrict__ w,
+                                                            double* __restrict__ phat,
+                                                            double* __restrict__ ldiag,
+                                                            double* __restrict__ lsub) {
+  const int64_t Ic = (I + 1) / 2;
+  // B, then its bidiagonal Cholesky factor (sequential recurrence)
+  if (threadIdx.x == 0) {
+    double prev_sub = 0.0;
+    for (int64_t j = 0; j < Ic; ++j) {
+      double bjj = 1.0;
+      if (j >= 1) bjj += w[(2 * j - 1) * 2 + 1] * w[(2 * j - 1) * 2 + 1];
+      if (2 * j + 1 < I) bjj += w[(2 * j + 1) * 2 + 0] * w[(2 * j + 1) * 2 + 0];
+      const double ljj = sqrt(bjj - prev_sub * prev_sub);
+      ldiag[j] = ljj;
+      double bnext = 0.0;
+      if (2 * j + 2 < I) bnext = w[(2 * j + 1) * 2 + 0] * w[(2 * j + 1) * 2 + 1];
+      prev_sub = (j + 1 < Ic) ? bnext / ljj : 0.0;
+      if (j + 1 < Ic) lsub[j + 1] = prev_sub;   // L_{j+1, j}
+    }
+  }
+  __syncthreads();
+  // row i of P^: y = L^{-1} p_i (forward substitution on the bidiagonal L)
+  for (int64_t i = threadIdx.x; i < I; i += kThreads) {
+    int64_t j1;
+    double p1, p2 = 0.0;
+    if ((i & 1) == 0) {
+      j1 = i / 2;
+      p1 = 1.0;
+    } else {
+      j1 = (i - 1) / 2;
+      p1 = w[i * 2 + 0];
+      if (i + 1 < I) p2 = w[i * 2 + 1];
+    }
+    double* out = phat + i * Ic;
+    for (int64_t j = 0; j < j1; ++j) out[j] = 0.0;
+    double y = p1 / ldiag[j1];
+    out[j1] = y;
+    for (int64_t j = j1 + 1; j < Ic; ++j) {
+      const double pj = (j == j1 + 1) ? p2 : 0.0;
+      y = (pj - lsub[j] * y) / ldiag[j];
+      out[j] = y;
+    }
+  }
+}
+
+hipError_t transfer_build_launch(int64_t I, const double* w, double* phat, double* ws,
+                                 hipStream_t st) {
+  const int64_t Ic = (I + 1) / 2;
+  hipLaunchKernelGGL(transfer_kernel, dim3(1), dim3(kThreads), 0, st, I, w, phat, ws, ws + Ic);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void prolong_kernel(int64_t I, int64_t Ic, int R, const double* __restrict__ phat,
+                               const double* __restrict__ Ac, const double* __restrict__ Act,
+                               double* __restrict__ A) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= I * R) return;
+  const int64_t i = idx / R;
+  const int r = (int)(idx % R);
+  double acc;
+  if (phat) {
+    acc = 0.0;
+    for (int64_t j = 0; j < Ic; ++j)
+      acc += phat[i * Ic + j] * (Act ? (Ac[j * R + r] - Act[j * R + r]) : Ac[j * R + r]);
+  } else {
+    acc = Act ? (Ac[i * R + r] - Act[i * R + r]) : Ac[i * R + r];
+  }
+  A[idx] = Act ? A[idx] + acc : acc;
+}
+
+hipError_t prolong_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* Ac,
+                          const double* Act, double* A, hipStream_t st) {
+  const int64_t n = I * R;
+  hipLaunchKernelGGL(prolong_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, I, Ic,
+                     R, phat, Ac, Act, A);
+  return hipGetLastError();
+}
+
+__global__ void restrict_factor_kernel(int64_t I, int64_t Ic, int R,
+                                       const double* __restrict__ phat,
+                                       const double* __restrict__ A, double* __restrict__ Ac) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Ic * R) return;
+  const int64_t j = idx / R;
+  const int r = (int)(idx % R);
+  double acc = 0.0;
+  if (phat) {
+    for (int64_t i = 0; i < I; ++i) acc += phat[i * Ic + j] * A[i * R + r];
+  } else {
+    acc = A[j * R + r];
+  }
+  Ac[idx] = acc;
+}
+
+hipError_t restrict_factor_launch(int64_t I, int64_t Ic, int R, const double* phat,
+                                  const double* A, double* Ac, hipStream_t st) {
+  const int64_t n = Ic * R;
+  hipLaunchKernelGGL(restrict_factor_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     I, Ic, R, phat, A, Ac);
+  return hipGetLastError();
+}
+
+__global__ void fas_rhs_kernel(int64_t I, int64_t Ic, int R, const double* __restrict__ phat,
+                               const double* __restrict__ F, const double* __restrict__ H,
+                               const double* __restrict__ Hc, double* __restrict__ Fc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Ic * R) return;
+  const int64_t j = idx / R;
+  const int r = (int)(idx % R);
+  double acc = 0.0;
+  for (int64_t i = 0; i < I; ++i)
+    acc += phat[i * Ic + j] * ((F ? F[i * R + r] : 0.0) - H[i * R + r]);
+  Fc[idx] = Hc[idx] + acc;
+}
+
+hipError_t fas_rhs_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* F,
+                          const double* H, const double* Hc, double* Fc, hipStream_t st) {
+  const int64_t n = Ic * R;
+  hipLaunchKernelGGL(fas_rhs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, I, Ic,
+                     R, phat, F, H, Hc, Fc);
+  return hipGetLastError();
+}
+
+__global__ void fas_rhs_identity_kernel(int64_t n, const double* F, const double* H,
+                                        const double* Hc, int literal, double* Fc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const double f = F ? F[idx] : 0.0;
+  Fc[idx] = literal ? f : (f - H[idx] + Hc[idx]);
+}
+
+hipError_t fas_rhs_identity_launch(int64_t count, const double* F, const double* H,
+                                   const double* Hc, int literal, double* Fc, hipStream_t st) {
+  hipLaunchKernelGGL(fas_rhs_identity_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     st, count, F, H, Hc, literal, Fc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Strided batched GEMM on the matrix cores.  64x64 block tile, BK = 16, four
+// waves in a 2x2 arrangement of 32x32 wave tiles (2x2 MFMA 16x16x4 tiles).
+template <typename T> struct GAcc;
+template <> struct GAcc<double> { typedef d4 type; };
+template <> struct GAcc<float> { typedef f4 type; };
+
+__device__ __forceinline__ d4 gmma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 gmma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmDesc d) {
+  typedef typename GAcc<T>::type V;
+  __shared__ T As[64][17];
+  __shared__ T Bs[16][65];
+  const T* __restrict__ A = reinterpret_cast<const T*>(d.A);
+  const T* __restrict__ B = reinterpret_cast<const T*>(d.B);
+  T* __restrict__ C = reinterpret_cast<T*>(d.C);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int64_t bm = (int64_t)blockIdx.x * 64, bn = (int64_t)blockIdx.y * 64;
+  const int64_t b = blockIdx.z;
+  A += b * d.a_bs;
+  B += b * d.b_bs;
+  C += b * d.c_bs;
+  V acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = V{0, 0, 0, 0};
+  const bool a_mfast = d.a_rs == 1;   // consecutive m contiguous
+  const bool b_kfast = d.b_rs == 1;   // consecutive k contiguous
+  for (int64_t k0 = 0; k0 < d.K; k0 += 16) {
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      int mm, kk;
+      if (a_mfast) { mm = tid % 64; kk = tid / 64 + 4 * q; }
+      else { kk = tid % 16; mm = tid / 16 + 16 * q; }
+      const int64_t gm = bm + mm, gk = k0 + kk;
+      As[mm][kk] = (gm < d.M && gk < d.K) ? A[gm * d.a_rs + gk * d.a_cs] : T(0);
+      int nn, kb;
+      if (b_kfast) { kb = tid % 16; nn = tid / 16 + 16 * q; }
+      else { nn = tid % 64; kb = tid / 64 + 4 * q; }
+      const int64_t gn = bn + nn, gkb = k0 + kb;
+      Bs[kb][nn] = (gn < d.N && gkb < d.K) ? B[gkb * d.b_rs + gn * d.b_cs] : T(0);
+    }
+    __syncthreads();
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      T a0 = As[wy * 32 + (lane & 15)][kk];
+      T a1 = As[wy * 32 + 16 + (lane & 15)][kk];
+      T b0 = Bs[kk][wx * 32 + (lane & 15)];
+      T b1 = Bs[kk][wx * 32 + 16 + (lane & 15)];
+      acc[0][0] = gmma(a0, b0, acc[0][0]);
+      acc[0][1] = gmma(a0, b1, acc[0][1]);
+      acc[1][0] = gmma(a1, b0, acc[1][0]);
+      acc[1][1] = gmma(a1, b1, acc[1][1]);
+    }
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = bm + wy * 32 + i * 16 + mfma_row<T>(lane >> 4, v);
+        const int64_t gn = bn + wx * 32 + j * 16 + (lane & 15);
+        if (gm < d.M && gn < d.N) C[gm * d.c_rs + gn * d.c_cs] = acc[i][j][v];
+      }
+}
+
+hipError_t gemm_launch(const GemmDesc& d, bool fp32, hipStream_t st) {
+  dim3 grid((unsigned)((d.M + 63) / 64), (unsigned)((d.N + 63) / 64), (unsigned)d.batch);
+  if (fp32) hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(gemm_kernel<double>, grid, dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
+
+}  // namespace cpamg

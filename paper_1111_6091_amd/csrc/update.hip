@@ -1,0 +1,565 @@
+// Row-wise epilogues of the MTTKRP (R x R solves of Section 3 and 5.2), Gram
+// matrices, normalization eq. (10), objectives eq. (2)/(30) and utilities.
+#include <algorithm>
+
+#include "internal.hpp"
+#include "smallla.hpp"
+
+namespace cpamg {
+
+constexpr int EPI_ROWS = 16;
+constexpr int LDP = kMaxRank + 1;   // padded LDS row stride (doubles)
+
+int epi_rows_per_wg() { return EPI_ROWS; }
+
+// Block-wide sum of one double per thread (256 threads); result valid in thread 0.
+__device__ inline double block_sum(double v, double* sred) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) / 64;
+    for (int w = 0; w < nw; ++w) s += sred[w];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Last-block detection: every thread publishes its writes; returns true in all
+// threads of the block that arrives last.  The counter is reset by that block.
+__device__ inline bool arrive_last(int32_t* counter, int* s_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = atomicAdd(counter, 1);
+    *s_flag = (prev == (int)gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *s_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+__global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
+  __shared__ double sG[kMaxRank * kMaxRank];
+  __shared__ double sM[EPI_ROWS * LDP];
+  __shared__ double sX[EPI_ROWS * LDP];
+  __shared__ double sU[kMaxRank * kMaxRank];
+  __shared__ double sred[8];
+  __shared__ int s_flag;
+  const int R = d.R;
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * EPI_ROWS;
+  const int nrows = (int)std::min<int64_t>(EPI_ROWS, d.In - row0);
+  const bool chol = (d.op == EPI_UPDATE && d.solver == CP_SOLVE_CHOL);
+  int kind = 0;
+  if (d.op != EPI_STORE_M) {
+    if (chol) {
+      for (int idx = tid; idx < R * R; idx += kThreads) sG[idx] = d.chol[idx];
+      kind = *d.chol_kind;
+      __syncthreads();
+    } else {
+      hadamard_gamma(d.grams, d.N, d.n, R, sG);
+    }
+  }
+  // reduce the MTTKRP partials in a fixed order
+  for (int idx = tid; idx < nrows * R; idx += kThreads) {
+    const int row = idx / R, col = idx % R;
+    const double* p = d.partial + (row0 + row) * R + col;
+    const size_t stride = (size_t)d.In * R;
+    double s = 0.0;
+    for (int c = 0; c < d.nsplit; ++c) s += p[c * stride];
+    sM[row * LDP + col] = s;
+  }
+  __syncthreads();
+
+  if (d.op == EPI_STORE_M) {
+    for (int idx = tid; idx < nrows * R; idx += kThreads) {
+      const int row = idx / R, col = idx % R;
+      d.outbuf[(row0 + row) * R + col] = sM[row * LDP + col];
+    }
+    return;
+  }
+
+  if (d.op == EPI_H || d.op == EPI_GRAD) {
+    double sq = 0.0;
+    if (tid < nrows) {
+      const double* a = d.A + (row0 + tid) * R;
+      for (int j = 0; j < R; ++j) {
+        double h = 0.0;
+        for (int k = 0; k < R; ++k) h += a[k] * sG[k * R + j];
+        h -= sM[tid * LDP + j];
+        if (d.op == EPI_H) d.outbuf[(row0 + tid) * R + j] = h;
+        sq += h * h;
+      }
+    }
+    if (d.op == EPI_H) return;
+    const double tot = block_sum(sq, sred);
+    if (tid == 0) d.scal_part[blockIdx.x] = tot;
+    if (arrive_last(d.counter, &s_flag)) {
+      if (tid == 0) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) s += d.scal_part[b];
+        *d.scalar_out = d.accumulate ? (*d.scalar_out + s) : s;
+        atomicExch(d.counter, 0);
+      }
+    }
+    return;
+  }
+
+  // ---- EPI_UPDATE ---------------------------------------------------------
+  if (tid < nrows) {
+    double* x = sX + tid * LDP;
+    const double* m = sM + tid * LDP;
+    const double* f = d.F ? d.F + (row0 + tid) * R : nullptr;
+    bool finite = true;
+    if (chol) {
+      if (kind == 0) {
+        // X Gamma = B with Gamma = L L^T:  L y = b, then L^T x = y (per row)
+        for (int i = 0; i < R; ++i) {
+          double y = m[i] + (f ? f[i] : 0.0);
+          for (int k = 0; k < i; ++k) y -= sG[i * R + k] * x[k];
+          x[i] = y / sG[i * R + i];
+        }
+        for (int i = R - 1; i >= 0; --i) {
+          double y = x[i];
+          for (int k = i + 1; k < R; ++k) y -= sG[k * R + i] * x[k];
+          x[i] = y / sG[i * R + i];
+        }
+      } else {
+        // pseudoinverse (symmetric): x = b P
+        double b[kMaxRank];
+        for (int i = 0; i < R; ++i) b[i] = m[i] + (f ? f[i] : 0.0);
+        for (int j = 0; j < R; ++j) {
+          double acc = 0.0;
+          for (int i = 0; i < R; ++i) acc += b[i] * sG[i * R + j];
+          x[j] = acc;
+        }
+      }
+    } else {
+      // Gauss-Seidel, warm start from the current row, r = 0..R-1 in order
+      const double* a = d.A + (row0 + tid) * R;
+      for (int j = 0; j < R; ++j) x[j] = a[j];
+      for (int it = 0; it < d.gs_iters; ++it) {
+        for (int r = 0; r < R; ++r) {
+          const double dg = sG[r * R + r];
+          if (dg == 0.0) continue;
+          double s = 0.0;
+          for (int k = 0; k < R; ++k) s += x[k] * sG[k * R + r];
+          s = (m[r] + (f ? f[r] : 0.0)) - s + x[r] * dg;
+          x[r] = s / dg;
+        }
+      }
+    }
+    for (int j = 0; j < R; ++j) finite = finite && isfinite(x[j]);
+    if (!finite) atomicOr(d.flags, CP_FLAG_NONFINITE);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nrows * R; idx += kThreads) {
+    const int row = idx / R, col = idx % R;
+    const double v = sX[row * LDP + col];
+    d.A[(row0 + row) * R + col] = v;
+    if (d.A32) d.A32[(row0 + row) * R + col] = (float)v;
+  }
+  // Gram partial of this block's rows and <A, M> partial
+  for (int idx = tid; idx < R * R; idx += kThreads) {
+    const int a = idx / R, b = idx % R;
+    double s = 0.0;
+    for (int row = 0; row < nrows; ++row) s += sX[row * LDP + a] * sX[row * LDP + b];
+    d.gram_part[(size_t)blockIdx.x * R * R + idx] = s;
+  }
+  double ip = 0.0;
+  if (d.want_obj && tid < nrows)
+    for (int j = 0; j < R; ++j) ip += sX[tid * LDP + j] * sM[tid * LDP + j];
+  const double ipb = block_sum(ip, sred);
+  if (tid == 0) d.scal_part[blockIdx.x] = ipb;
+  if (arrive_last(d.counter, &s_flag)) {
+    const int nwg = gridDim.x;
+    for (int idx = tid; idx < R * R; idx += kThreads) {
+      double s = 0.0;
+      for (int b = 0; b < nwg; ++b) s += d.gram_part[(size_t)b * R * R + idx];
+      sU[idx] = s;
+      d.grams[(size_t)d.n * R * R + idx] = s;
+    }
+    __syncthreads();
+    if (d.want_obj && tid == 0) {
+      double inner = 0.0;
+      for (int b = 0; b < nwg; ++b) inner += d.scal_part[b];
+      double nrm = 0.0;
+      for (int idx = 0; idx < R * R; ++idx) {
+        double h = 1.0;
+        for (int m = 0; m < d.N; ++m) h *= (m == d.n) ? sU[idx] : d.grams[(size_t)m * R * R + idx];
+        nrm += h;
+      }
+      *d.scalar_out = 0.5 * (*d.norm2 - 2.0 * inner + nrm);
+    }
+    if (tid == 0) atomicExch(d.counter, 0);
+  }
+}
+
+hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {
+  const unsigned nwg = (unsigned)((d.In + EPI_ROWS - 1) / EPI_ROWS);
+  hipLaunchKernelGGL(epi_kernel, dim3(nwg), dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void gamma_prep_kernel(const double* grams, int N, int n,
+                                                               int R, double* chol,
+                                                               int32_t* kind, uint32_t* flags) {
+  __shared__ double lds[4 * kMaxRank * kMaxRank];
+  gamma_prepare(grams, N, n, R, chol, kind, flags, lds);
+}
+
+hipError_t gamma_prep_launch(const double* grams, int N, int n, int R, double* chol,
+                             int32_t* chol_kind, uint32_t* flags, int32_t solver,
+                             hipStream_t st) {
+  (void)solver;
+  hipLaunchKernelGGL(gamma_prep_kernel, dim3(1), dim3(kThreads), 0, st, grams, N, n, R, chol,
+                     chol_kind, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Grams of every mode (one workgroup per mode), optional FP32 shadow refresh.
+struct GramArgs {
+  double* A[kMaxOrder];
+  float* A32[kMaxOrder];
+  int64_t dims[kMaxOrder];
+};
+
+__global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, double* grams) {
+  __shared__ double tile[64 * LDP];
+  const int m = blockIdx.x;
+  const double* A = g.A[m];
+  float* A32 = g.A32[m];
+  const int64_t I = g.dims[m];
+  double acc[4] = {0, 0, 0, 0};
+  for (int64_t i0 = 0; i0 < I; i0 += 64) {
+    const int rows = (int)std::min<int64_t>(64, I - i0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rows * R; idx += kThreads) {
+      const double v = A[i0 * R + idx];
+      tile[(idx / R) * LDP + idx % R] = v;
+      if (A32) A32[i0 * R + idx] = (float)v;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int idx = threadIdx.x + q * kThreads;
+      if (idx < R * R) {
+        const int a = idx / R, b = idx % R;
+        double s = acc[q];
+        for (int row = 0; row < rows; ++row) s += tile[row * LDP + a] * tile[row * LDP + b];
+        acc[q] = s;
+      }
+    }
+  }
+  for (int q = 0; q < 4; ++q) {
+    const int idx = threadIdx.x + q * kThreads;
+    if (idx < R * R) grams[(size_t)m * R * R + idx] = acc[q];
+  }
+}
+
+hipError_t gram_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
+                       double* grams, hipStream_t st) {
+  GramArgs g{};
+  for (int m = 0; m < N; ++m) {
+    g.A[m] = A[m];
+    g.A32[m] = A32 ? A32[m] : nullptr;
+    g.dims[m] = dims[m];
+  }
+  hipLaunchKernelGGL(gram_kernel, dim3(N), dim3(kThreads), 0, st, g, R, grams);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Normalization eq. (10): lambda_r = (prod_n ||a_r^(n)||)^(1/N) with the column
+// norms taken from diag(Upsilon^(n)); components with a zero column are kept.
+__global__ __launch_bounds__(kThreads) void normalize_kernel(GramArgs g, int N, int R,
+                                                             double* grams) {
+  __shared__ double sc[kMaxOrder * kMaxRank];
+  if (threadIdx.x < R) {
+    const int r = threadIdx.x;
+    double nr[kMaxOrder];
+    bool ok = true;
+    double prod = 1.0;
+    for (int m = 0; m < N; ++m) {
+      nr[m] = sqrt(grams[(size_t)m * R * R + r * R + r]);
+      ok = ok && (nr[m] > 0.0);
+      prod *= nr[m];
+    }
+    const double lam = pow(prod, 1.0 / N);
+    for (int m = 0; m < N; ++m) sc[m * kMaxRank + r] = ok ? lam / nr[m] : 1.0;
+  }
+  __syncthreads();
+  for (int m = 0; m < N; ++m) {
+    const int64_t cnt = g.dims[m] * R;
+    for (int64_t idx = threadIdx.x; idx < cnt; idx += kThreads) {
+      const double v = g.A[m][idx] * sc[m * kMaxRank + (int)(idx % R)];
+      g.A[m][idx] = v;
+      if (g.A32[m]) g.A32[m][idx] = (float)v;
+    }
+    for (int idx = threadIdx.x; idx < R * R; idx += kThreads) {
+      const int a = idx / R, b = idx % R;
+      grams[(size_t)m * R * R + idx] *= sc[m * kMaxRank + a] * sc[m * kMaxRank + b];
+    }
+  }
+}
+
+hipError_t normalize_launch(double* const* A, float* const* A32, const int64_t* dims, int N,
+                            int R, double* grams, hipStream_t st) {
+  GramArgs g{};
+  for (int m = 0; m < N; ++m) {
+    g.A[m] = A[m];
+    g.A32[m] = A32 ? A32[m] : nullptr;
+    g.dims[m] = dims[m];
+  }
+  hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(kThreads), 0, st, g, N, R, grams);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact residual 1/2 ||Z - [[A]]||^2: one pass over Z; each block walks a range
+// of mode-0 fibres, forming W_f(r) = prod_{m>=1} A^(m)(f_m, r) once per fibre.
+struct ResArgs {
+  const double* A[kMaxOrder];
+  int64_t dims[kMaxOrder];
+};
+
+__global__ __launch_bounds__(kThreads) void residual_kernel(const double* __restrict__ z,
+                                                            ResArgs ra, int N, int R,
+                                                            int64_t fibres, int64_t fpb,
+                                                            double* part, int32_t* counter,
+                                                            double* f) {
+  __shared__ double W[kMaxRank];
+  __shared__ double sred[8];
+  __shared__ int s_flag;
+  const int64_t I0 = ra.dims[0];
+  const int64_t fb = (int64_t)blockIdx.x * fpb;
+  const int64_t fe = std::min<int64_t>(fibres, fb + fpb);
+  double acc = 0.0;
+  for (int64_t fi = fb; fi < fe; ++fi) {
+    __syncthreads();
+    if (threadIdx.x < R) {
+      int64_t q = fi;
+      double w = 1.0;
+      for (int m = 1; m < N; ++m) {
+        const int64_t im = q % ra.dims[m];
+        q /= ra.dims[m];
+        w *= ra.A[m][im * R + threadIdx.x];
+      }
+      W[threadIdx.x] = w;
+    }
+    __syncthreads();
+    const double* zf = z + fi * I0;
+    for (int64_t i0 = threadIdx.x; i0 < I0; i0 += kThreads) {
+      double mdl = 0.0;
+      for (int r = 0; r < R; ++r) mdl += ra.A[0][i0 * R + r] * W[r];
+      const double df = zf[i0] - mdl;
+      acc += df * df;
+    }
+  }
+  const double tot = block_sum(acc, sred);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (arrive_last(counter, &s_flag)) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += part[b];
+      *f = 0.5 * s;
+      atomicExch(counter, 0);
+    }
+  }
+}
+
+hipError_t residual_launch(const double* z, const int64_t* dims, int N, int R,
+                           const double* const* A, double* part, int32_t* counter, double* f,
+                           hipStream_t st) {
+  ResArgs ra{};
+  int64_t fibres = 1;
+  for (int m = 0; m < N; ++m) {
+    ra.A[m] = A[m];
+    ra.dims[m] = dims[m];
+    if (m >= 1) fibres *= dims[m];
+  }
+  // about 8k entries per block, at most 2048 blocks
+  int64_t fpb = std::max<int64_t>(1, 8192 / std::max<int64_t>(1, dims[0]));
+  int64_t nb = (fibres + fpb - 1) / fpb;
+  if (nb > 2048) {
+    fpb = (fibres + 2047) / 2048;
+    nb = (fibres + fpb - 1) / fpb;
+  }
+  hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nb), dim3(kThreads), 0, st, z, ra, N, R,
+                     fibres, fpb, part, counter, f);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict__ a,
+                                                       const double* __restrict__ b,
+                                                       int64_t count, double* part,
+                                                       int32_t* counter, double* out) {
+  __shared__ double sred[8];
+  __shared__ int s_flag;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * kThreads)
+    acc += a[i] * (b ? b[i] : a[i]);
+  const double tot = block_sum(acc, sred);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (arrive_last(counter, &s_flag)) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < (int)gridDim.x; ++k) s += part[k];
+      *out = s;
+      atomicExch(counter, 0);
+    }
+  }
+}
+
+static unsigned dot_blocks(int64_t count) {
+  int64_t nb = (count + kThreads * 8 - 1) / (kThreads * 8);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 1024));
+}
+
+hipError_t norm2_launch(const double* z, int64_t count, double* part, int32_t* counter,
+                        double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dot_kernel, dim3(dot_blocks(count)), dim3(kThreads), 0, st, z,
+                     (const double*)nullptr, count, part, counter, out);
+  return hipGetLastError();
+}
+
+hipError_t inner_launch(const double* A, const double* M, int64_t count, double* part,
+                        int32_t* counter, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dot_kernel, dim3(dot_blocks(count)), dim3(kThreads), 0, st, A, M, count,
+                     part, counter, out);
+  return hipGetLastError();
+}
+
+__global__ void fused_f_kernel(const double* grams, int N, int R, const double* inner,
+                               const double* norm2, double* f) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double nrm = 0.0;
+    for (int idx = 0; idx < R * R; ++idx) {
+      double h = 1.0;
+      for (int m = 0; m < N; ++m) h *= grams[(size_t)m * R * R + idx];
+      nrm += h;
+    }
+    *f = 0.5 * (*norm2 - 2.0 * (*inner) + nrm);
+  }
+}
+
+hipError_t fused_f_launch(const double* grams, int N, int R, const double* inner,
+                          const double* norm2, double* f, hipStream_t st) {
+  hipLaunchKernelGGL(fused_f_kernel, dim3(1), dim3(64), 0, st, grams, N, R, inner, norm2, f);
+  return hipGetLastError();
+}
+
+__global__ void finish_g_kernel(const double* acc, const double* norm2, double* g) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *g = sqrt(*acc) / sqrt(*norm2);
+}
+
+hipError_t finish_g_launch(const double* acc, const double* norm2, double* g, hipStream_t st) {
+  hipLaunchKernelGGL(finish_g_kernel, dim3(1), dim3(64), 0, st, acc, norm2, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void cast_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (float)s[i];
+}
+
+hipError_t cast_launch(const double* src, float* dst, int64_t count, hipStream_t st) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 1023) / 1024, 4096));
+  hipLaunchKernelGGL(cast_kernel, dim3(nb), dim3(kThreads), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+__global__ void fill_kernel(double* d, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = v;
+}
+
+hipError_t fill_launch(double* dst, double v, int64_t count, hipStream_t st) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 1023) / 1024, 4096));
+  hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(kThreads), 0, st, dst, v, count);
+  return hipGetLastError();
+}
+
+__global__ void copy_kernel(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+hipError_t copy_launch(const double* src, double* dst, int64_t count, hipStream_t st) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 1023) / 1024, 4096));
+  hipLaunchKernelGGL(copy_kernel, dim3(nb), dim3(kThreads), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stable sort of the components by decreasing lambda_r (one workgroup).
+__global__ __launch_bounds__(kThreads) void sort_kernel(GramArgs g, int N, int R) {
+  __shared__ double lam[kMaxRank];
+  __shared__ int perm[kMaxRank];
+  __shared__ double rowbuf[kThreads / kMaxRank + 1][kMaxRank];
+  if (threadIdx.x < R) {
+    const int r = threadIdx.x;
+    double prod = 1.0;
+    for (int m = 0; m < N; ++m) {
+      double s = 0.0;
+      for (int64_t i = 0; i < g.dims[m]; ++i) {
+        const double v = g.A[m][i * R + r];
+        s += v * v;
+      }
+      prod *= sqrt(s);
+    }
+    lam[r] = pow(prod, 1.0 / N);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int r = 0; r < R; ++r) perm[r] = r;
+    for (int i = 1; i < R; ++i) {   // insertion sort: stable, decreasing lambda
+      const int p = perm[i];
+      int j = i - 1;
+      while (j >= 0 && lam[perm[j]] < lam[p]) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = p;
+    }
+  }
+  __syncthreads();
+  // permute columns row by row; each thread owns one row at a time
+  for (int m = 0; m < N; ++m) {
+    for (int64_t i = threadIdx.x; i < g.dims[m]; i += kThreads) {
+      double tmp[kMaxRank];
+      for (int r = 0; r < R; ++r) tmp[r] = g.A[m][i * R + perm[r]];
+      for (int r = 0; r < R; ++r) {
+        g.A[m][i * R + r] = tmp[r];
+        if (g.A32[m]) g.A32[m][i * R + r] = (float)tmp[r];
+      }
+    }
+  }
+  (void)rowbuf;
+}
+
+hipError_t sort_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
+                       double* scratch, hipStream_t st) {
+  (void)scratch;
+  GramArgs g{};
+  for (int m = 0; m < N; ++m) {
+    g.A[m] = A[m];
+    g.A32[m] = A32 ? A32[m] : nullptr;
+    g.dims[m] = dims[m];
+  }
+  hipLaunchKernelGGL(sort_kernel, dim3(1), dim3(kThreads), 0, st, g, N, R);
+  return hipGetLastError();
+}
+
+}  // namespace cpamg

@@ -1,0 +1,134 @@
+"""Host-side solve loops on top of the C ABI (stopping decisions only).
+
+Each loop enqueues a chunk of device work, reads back a few scalars and decides
+whether to continue; all arithmetic happens in libcpamg's kernels.
+
+Stopping rules (Section 6 of the paper uses the gradient measure g < 1e-10 with
+caps of 1e4 ALS iterations and 500 multilevel iterations; the workloads here
+stop on the relative fit change):
+  * ALS / FP64 phase: |fit_k - fit_{k-1}| <= fit_tol * fit_k, fit = 1 - ||Z-[[A]]||/||Z||
+  * mixed form: FP32 sweeps until the exact fit changes by <= tol32 * fit per
+    sweep (checked every ``check`` sweeps), then FP64 sweeps as above.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import api
+from ._lib import CP_FP64, CP_MIXED, CP_SOLVE_CHOL, CP_SOLVE_GS
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class SolveResult:
+    sweeps: int = 0
+    sweeps32: int = 0
+    sweeps64: int = 0
+    fits: list = field(default_factory=list)
+    final_fit: float = float("nan")
+    converged: bool = False
+
+
+def fit_from_f(f, norm2):
+    return 1.0 - math.sqrt(max(2.0 * f, 0.0) / norm2)
+
+
+def als_solve(ctx, Z, A, max_sweeps=10000, fit_tol=1e-12, chunk=16, prec=CP_FP64,
+              solver=CP_SOLVE_CHOL, sort_at_end=True):
+    """Standalone ALS (Section 3) with the fused objective read back per chunk."""
+    torch = _torch()
+    norm2 = float(Z.norm2.item())
+    fh = torch.zeros(chunk, dtype=torch.float64, device=Z.z64.device if Z.z64 is not None else "cuda")
+    res = SolveResult()
+    prev = None
+    while res.sweeps < max_sweeps:
+        k = min(chunk, max_sweeps - res.sweeps)
+        api.cp_als_sweep(ctx, Z, A, None, k, solver, 10, True, prec, fh)
+        fv = fh[:k].cpu().numpy()
+        stop = False
+        for j in range(k):
+            fit = fit_from_f(float(fv[j]), norm2)
+            res.fits.append(fit)
+            res.sweeps += 1
+            if fit_tol and prev is not None and abs(fit - prev) <= fit_tol * abs(fit):
+                stop = True
+                res.converged = True
+                # the device already ran the rest of the chunk; keep counting them
+            prev = fit
+        if stop:
+            break
+    if sort_at_end:
+        api.cp_sort(ctx, A)
+    res.final_fit = res.fits[-1] if res.fits else float("nan")
+    return res
+
+
+def exact_fit(ctx, Z, A):
+    torch = _torch()
+    f = torch.zeros(1, dtype=torch.float64, device=Z.z64.device)
+    api.cp_objective(ctx, Z, A, exact=True, f=f)
+    return fit_from_f(float(f.item()), float(Z.norm2.item()))
+
+
+def mixed_solve(ctx, Z, A, tol32=1e-7, tol64=1e-12, check=4, max_sweeps=10000, chunk64=16):
+    """Mixed form: FP32-contraction sweeps, then FP64 refinement sweeps."""
+    res = SolveResult()
+    prev = exact_fit(ctx, Z, A)
+    while res.sweeps < max_sweeps:
+        api.cp_als_sweep(ctx, Z, A, None, check, CP_SOLVE_CHOL, 10, True, CP_MIXED, None)
+        res.sweeps += check
+        res.sweeps32 += check
+        fit = exact_fit(ctx, Z, A)
+        res.fits.append(fit)
+        if abs(fit - prev) <= tol32 * check * abs(fit):
+            break
+        prev = fit
+    r64 = als_solve(ctx, Z, A, max_sweeps=max(1, max_sweeps - res.sweeps), fit_tol=tol64,
+                    chunk=chunk64, prec=CP_FP64)
+    res.sweeps64 = r64.sweeps
+    res.sweeps += r64.sweeps
+    res.fits.extend(r64.fits)
+    res.final_fit = r64.final_fit
+    res.converged = r64.converged
+    return res
+
+
+def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False):
+    """Levels for cp_fas_vcycle from interpolation weights.
+
+    ``weights[l][n]``: (I_n x 2) numpy weights of mode n on level l, or None when
+    that mode is not coarsened.  Operator prep (B, L, P^) and the coarse tensors
+    run on the device (cp_transfer_build, cp_restrict).
+    """
+    torch = _torch()
+    levels = []
+    cur = Z
+    for wl in weights:
+        ph = []
+        for n, d in enumerate(cur.dims):
+            if wl[n] is None:
+                ph.append(None)
+                continue
+            w = torch.from_numpy(np.ascontiguousarray(wl[n], dtype=np.float64)).to(cur.z64.device
+                                                                                   if cur.z64 is not None else "cuda")
+            p = torch.empty((d, (d + 1) // 2), dtype=torch.float64, device=w.device)
+            api.cp_transfer_build(ctx, w, p)
+            ph.append(p)
+        cdims = tuple((d + 1) // 2 if ph[n] is not None else d for n, d in enumerate(cur.dims))
+        nxt = api.DeviceTensor.empty(cdims, fp64=(prec == CP_FP64) or not fp32,
+                                     fp32=fp32 or prec == CP_MIXED)
+        if prec == CP_MIXED:
+            api.cp_restrict(ctx, cur, ph, nxt, CP_MIXED)
+        if nxt.z64 is not None and cur.z64 is not None:
+            api.cp_restrict(ctx, cur, ph, nxt, CP_FP64)
+        levels.append((cur, ph))
+        cur = nxt
+    levels.append((cur, [None] * cur.order))
+    return levels

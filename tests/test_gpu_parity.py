@@ -1,0 +1,286 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded inputs.
+
+Tolerances: FP64 paths differ from the oracle only by summation order, so
+results agree to ~1e-13 relative; tests use 1e-11 for single calls and 1e-12 on
+fits.  Mixed-precision contractions (FP32 GEMM, FP32 accumulation over at most
+the contracted mode length) are compared at 2e-5 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import amg, cp
+from paper_1111_6091_amd import synth
+from tests.gpu_util import ctx as make_ctx, rel_err, say, sync
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_1111_6091_amd import api  # noqa: F401  (fails loudly if the library is missing)
+    return make_ctx()
+
+
+def dev_inputs(C, Z, A, fp32=False):
+    from paper_1111_6091_amd import api
+    return api.DeviceTensor.from_numpy(C, Z, fp32=fp32), api.DeviceFactors.from_numpy(C, A, fp32=fp32)
+
+
+MTTKRP_SHAPES = [
+    ((20, 20, 20), 3), ((5, 7, 9), 2), ((64, 33, 17), 5), ((3, 4, 5, 6), 4), ((12, 10, 9, 11), 8),
+    ((37, 19, 23), 16), ((16, 16, 16), 20), ((128, 64, 8), 10), ((7, 130, 5), 3), ((9, 8), 3),
+]
+
+
+@pytest.mark.parametrize("dims,R", MTTKRP_SHAPES)
+def test_mttkrp_fp64_matches_oracle(C, dims, R):
+    from paper_1111_6091_amd import api
+    say(f"mttkrp fp64 dims={dims} R={R}")
+    rng = np.random.default_rng(sum(dims) + R)
+    Z = rng.standard_normal(dims)
+    A = [rng.standard_normal((d, R)) for d in dims]
+    Zd, Ad = dev_inputs(C, Z, A)
+    for n in range(len(dims)):
+        M = torch.zeros((dims[n], R), dtype=torch.float64, device="cuda")
+        api.cp_mttkrp(C, Zd, Ad, n, M)
+        sync()
+        ref = cp.mttkrp(Z, A, n)
+        assert rel_err(M.cpu().numpy(), ref) < 1e-12, (n, rel_err(M.cpu().numpy(), ref))
+
+
+@pytest.mark.parametrize("dims,R", [((20, 20, 20), 3), ((64, 33, 17), 5), ((12, 10, 9, 11), 8),
+                                    ((37, 19, 23), 16), ((16, 16, 16), 20)])
+def test_mttkrp_mixed_matches_oracle(C, dims, R):
+    from paper_1111_6091_amd import api
+    say(f"mttkrp mixed dims={dims} R={R}")
+    rng = np.random.default_rng(7 + R)
+    Z = rng.standard_normal(dims)
+    A = [rng.standard_normal((d, R)) for d in dims]
+    Zd, Ad = dev_inputs(C, Z, A, fp32=True)
+    for n in range(len(dims)):
+        M = torch.zeros((dims[n], R), dtype=torch.float64, device="cuda")
+        api.cp_mttkrp(C, Zd, Ad, n, M, prec=api.CP_MIXED)
+        sync()
+        ref = cp.mttkrp(Z, A, n)
+        assert rel_err(M.cpu().numpy(), ref) < 2e-5
+
+
+def test_mttkrp_deterministic(C):
+    from paper_1111_6091_amd import api
+    rng = np.random.default_rng(3)
+    dims, R = (64, 48, 40), 7
+    Z = rng.standard_normal(dims)
+    A = [rng.standard_normal((d, R)) for d in dims]
+    Zd, Ad = dev_inputs(C, Z, A)
+    for n in range(3):
+        M1 = torch.zeros((dims[n], R), dtype=torch.float64, device="cuda")
+        M2 = torch.zeros_like(M1)
+        api.cp_mttkrp(C, Zd, Ad, n, M1)
+        api.cp_mttkrp(C, Zd, Ad, n, M2)
+        sync()
+        assert torch.equal(M1, M2)
+
+
+def test_norm2_and_objectives(C):
+    from paper_1111_6091_amd import api
+    say("objectives")
+    Z, _ = synth.collinear_tensor((20, 21, 22), 3, 0.5, 0.05, 0.0, seed=4)
+    A = synth.uniform_start(Z.shape, 3, 4)
+    Zd, Ad = dev_inputs(C, Z, A)
+    sync()
+    assert Zd.norm2.item() == pytest.approx(float(np.sum(Z * Z)), rel=1e-13)
+    f = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ff = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    api.cp_objective(C, Zd, Ad, exact=True, f=f, g=g)
+    api.cp_objective(C, Zd, Ad, exact=False, f=ff)
+    sync()
+    assert f.item() == pytest.approx(cp.objective(Z, A), rel=1e-12)
+    assert ff.item() == pytest.approx(cp.objective(Z, A), rel=1e-10)
+    assert g.item() == pytest.approx(cp.grad_norm(Z, A), rel=1e-11)
+
+
+@pytest.mark.parametrize("dims,R,seed", [((20, 20, 20), 3, 1), ((17, 9, 13), 4, 2), ((8, 9, 10, 7), 3, 3)])
+def test_als_sweeps_track_oracle(C, dims, R, seed):
+    from paper_1111_6091_amd import api
+    say(f"als trajectory dims={dims} R={R}")
+    Z, _ = synth.collinear_tensor(dims, R, 0.5, 0.01, 0.0, seed=seed)
+    A0 = synth.uniform_start(dims, R, seed)
+    Zd, Ad = dev_inputs(C, Z, A0)
+    K = 12
+    fh = torch.zeros(K, dtype=torch.float64, device="cuda")
+    api.cp_als_sweep(C, Zd, Ad, None, K, api.CP_SOLVE_CHOL, 10, True, api.CP_FP64, fh)
+    sync()
+    A = A0
+    fref = []
+    for _ in range(K):
+        A = cp.als_sweep(Z, A)
+        fref.append(cp.objective(Z, A))
+    got = Ad.to_numpy()
+    for n in range(len(dims)):
+        assert rel_err(got[n], A[n]) < 1e-9, (n, rel_err(got[n], A[n]))
+    np.testing.assert_allclose(fh.cpu().numpy(), fref, rtol=1e-9)
+    assert C.status() == 0
+
+
+def test_als_gs_with_rhs_matches_oracle_bngs(C):
+    from paper_1111_6091_amd import api
+    say("bngs gs10 with F")
+    dims, R = (14, 15, 16), 3
+    Z, _ = synth.collinear_tensor(dims, R, 0.7, 0.02, 0.0, seed=5)
+    A0 = synth.uniform_start(dims, R, 5)
+    rng = np.random.default_rng(5)
+    F = [0.2 * rng.standard_normal((d, R)) for d in dims]
+    Zd, Ad = dev_inputs(C, Z, A0)
+    Fd = api.DeviceFactors.from_numpy(C, F)
+    api.cp_als_sweep(C, Zd, Ad, Fd, 3, api.CP_SOLVE_GS, 10, False, api.CP_FP64, None)
+    sync()
+    A = A0
+    for _ in range(3):
+        A = amg.bngs(Z, A, F, gs_iters=10, normalize_after=False)
+    got = Ad.to_numpy()
+    for n in range(3):
+        assert rel_err(got[n], A[n]) < 1e-10
+
+
+def test_singular_gamma_uses_pseudoinverse(C):
+    from paper_1111_6091_amd import api
+    say("pinv fallback")
+    dims, R = (10, 11, 12), 3
+    rng = np.random.default_rng(6)
+    Z = rng.standard_normal(dims)
+    A0 = [rng.random((d, R)) for d in dims]
+    A0[1][:, 2] = 0.0   # zero column: Gamma^(0) and Gamma^(2) are singular
+    Zd, Ad = dev_inputs(C, Z, A0)
+    api.cp_als_sweep(C, Zd, Ad, None, 1, api.CP_SOLVE_CHOL, 10, False, api.CP_FP64, None)
+    sync()
+    flags = C.status()
+    from paper_1111_6091_amd import CP_FLAG_PINV_FALLBACK
+    assert flags & CP_FLAG_PINV_FALLBACK
+    ref = cp.als_sweep(Z, A0, normalize_after=False)
+    got = Ad.to_numpy()
+    for n in range(3):
+        assert rel_err(got[n], ref[n]) < 1e-9, (n, rel_err(got[n], ref[n]))
+
+
+def test_sort_components(C):
+    from paper_1111_6091_amd import api
+    rng = np.random.default_rng(8)
+    A0 = [rng.standard_normal((d, 5)) for d in (6, 7, 8)]
+    A0[0][:, 3] *= 10
+    Ad = api.DeviceFactors.from_numpy(C, A0)
+    api.cp_sort(C, Ad)
+    sync()
+    ref, _ = cp.sort_components(A0)
+    for g, r in zip(Ad.to_numpy(), ref):
+        np.testing.assert_array_equal(g, r)
+
+
+@pytest.mark.parametrize("I", [20, 21, 128, 7])
+def test_transfer_build_matches_oracle(C, I):
+    from paper_1111_6091_amd import api
+    rng = np.random.default_rng(I)
+    w = np.zeros((I, 2))
+    for i in range(1, I, 2):
+        w[i] = rng.uniform(0.1, 0.9, 2)
+        if i + 1 >= I:
+            w[i, 1] = 0.0
+    wd = torch.from_numpy(w).cuda()
+    Ic = (I + 1) // 2
+    ph = torch.zeros((I, Ic), dtype=torch.float64, device="cuda")
+    api.cp_transfer_build(C, wd, ph)
+    sync()
+    ref = amg.transfer(amg.interp_from_weights(I, w))[2]
+    assert rel_err(ph.cpu().numpy(), ref) < 1e-13
+
+
+@pytest.mark.parametrize("dims,mask", [((20, 20, 20), (1, 1, 1)), ((17, 12, 9), (1, 0, 1)),
+                                       ((16, 18, 10, 12), (1, 1, 1, 1)), ((33, 65, 40), (0, 1, 1))])
+def test_restrict_matches_oracle(C, dims, mask):
+    from paper_1111_6091_amd import api
+    say(f"restrict dims={dims} mask={mask}")
+    rng = np.random.default_rng(sum(dims))
+    Z = rng.standard_normal(dims)
+    phs, phd = [], []
+    for d, m in zip(dims, mask):
+        if not m:
+            phs.append(None)
+            phd.append(None)
+            continue
+        p = amg.transfer(amg.interp_from_weights(d, synth.linear_interp_weights(d)))[2]
+        phs.append(p)
+        phd.append(torch.from_numpy(p).cuda())
+    ref = amg.restrict_tensor(Z, [None if p is None else p.T for p in phs])
+    Zd = api.DeviceTensor.from_numpy(C, Z, fp32=True)
+    Zc = api.DeviceTensor.empty(ref.shape, fp64=True, fp32=True)
+    api.cp_restrict(C, Zd, phd, Zc, api.CP_FP64)
+    api.cp_restrict(C, Zd, phd, Zc, api.CP_MIXED)
+    sync()
+    assert rel_err(Zc.to_numpy("z64"), ref) < 1e-13
+    assert rel_err(Zc.to_numpy("z32"), ref) < 1e-5
+
+
+def test_identity_restriction_returns_z(C):
+    from paper_1111_6091_amd import api
+    Z = np.random.default_rng(1).standard_normal((5, 6, 7))
+    Zd = api.DeviceTensor.from_numpy(C, Z)
+    Zc = api.DeviceTensor.empty(Z.shape)
+    api.cp_restrict(C, Zd, [None, None, None], Zc)
+    sync()
+    np.testing.assert_array_equal(Zc.to_numpy(), Z)
+
+
+def test_prolong_and_restrict_factor(C):
+    from paper_1111_6091_amd import api
+    rng = np.random.default_rng(9)
+    I, R = 21, 4
+    p = amg.transfer(amg.interp_from_weights(I, synth.linear_interp_weights(I)))[2]
+    Ic = p.shape[1]
+    A = rng.standard_normal((I, R))
+    Ac = rng.standard_normal((Ic, R))
+    Act = rng.standard_normal((Ic, R))
+    pd = torch.from_numpy(p).cuda()
+    Ad = torch.from_numpy(A.copy()).cuda()
+    out = torch.zeros((Ic, R), dtype=torch.float64, device="cuda")
+    api.cp_restrict_factor(C, pd, Ad, out)
+    sync()
+    assert rel_err(out.cpu().numpy(), p.T @ A) < 1e-14
+    api.cp_prolong(C, pd, torch.from_numpy(Ac).cuda(), torch.from_numpy(Act).cuda(), Ad)
+    sync()
+    assert rel_err(Ad.cpu().numpy(), A + p @ (Ac - Act)) < 1e-14
+    api.cp_prolong(C, pd, torch.from_numpy(Ac).cuda(), None, Ad)
+    sync()
+    assert rel_err(Ad.cpu().numpy(), p @ Ac) < 1e-14
+
+
+def _oracle_levels(Z, weights, coarsest):
+    return amg.hierarchy_from_weights(Z, weights, coarsest)
+
+
+@pytest.mark.parametrize("dims,R,nlev", [((20, 20, 20), 3, 2), ((32, 32, 32), 3, 3), ((24, 20, 6), 2, 2)])
+def test_fas_vcycle_matches_oracle(C, dims, R, nlev):
+    from paper_1111_6091_amd import api, drivers
+    say(f"fas vcycle dims={dims} R={R} levels={nlev}")
+    Z, _ = synth.collinear_tensor(dims, R, 0.5, 0.01, 0.0, seed=10)
+    A0, _ = cp.als(Z, synth.uniform_start(dims, R, 10), max_sweeps=10, fit_tol=0.0, sort_at_end=False)
+    # weights per level (linear interpolation); modes of size <= 6 are not coarsened
+    weights, cur = [], list(dims)
+    coarsest = [max(6, R)] * len(dims)
+    for _ in range(nlev - 1):
+        wl = [synth.linear_interp_weights(d) if d > coarsest[n] else None for n, d in enumerate(cur)]
+        weights.append(wl)
+        cur = [(d + 1) // 2 if wl[n] is not None else d for n, d in enumerate(cur)]
+    levels = _oracle_levels(Z, weights, coarsest)
+    assert len(levels) == nlev
+    ref = amg.fas_vcycle(levels, amg.zeros_like_factors(A0), A0, nu1=1, nu2=1, nuc=20)
+    Zd = api.DeviceTensor.from_numpy(C, Z)
+    dlev = drivers.build_hierarchy(C, Zd, weights)
+    Ad = api.DeviceFactors.from_numpy(C, A0)
+    api.cp_fas_vcycle(C, dlev, Ad, nu1=1, nu2=1, nuc=20)
+    sync()
+    got = Ad.to_numpy()
+    for n in range(len(dims)):
+        assert rel_err(got[n], ref[n]) < 1e-9, (n, rel_err(got[n], ref[n]))
+    assert rel_err(cp.full(got), cp.full(ref)) < 1e-11
