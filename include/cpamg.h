@@ -199,6 +199,26 @@ cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat
 cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t nlevels, cp_factors* A,
                         const cp_fas_params* params, cp_prec prec);
 
+/* ---- per-kernel timing ------------------------------------------------ */
+
+/* Kernel classes reported by cp_profile_read (index into its arrays). */
+enum {
+  CP_PROF_MTTKRP_MODE0_F64 = 0, CP_PROF_MTTKRP_MODE1_F64, CP_PROF_MTTKRP_MODEN_F64,
+  CP_PROF_MTTKRP_MODE0_F32, CP_PROF_MTTKRP_MODE1_F32, CP_PROF_MTTKRP_MODEN_F32,
+  CP_PROF_UPDATE, CP_PROF_EPILOGUE_OTHER, CP_PROF_GAMMA_PREP, CP_PROF_NORMALIZE, CP_PROF_GRAM,
+  CP_PROF_OTHER, CP_PROF_CLASSES
+};
+
+/* on != 0: from now on bracket every kernel launch of this context with a pair
+ * of HIP events recorded on the context's stream (clears earlier records);
+ * on == 0: stop recording (records are kept until read).  Not for use while
+ * the stream is being captured into a graph. */
+cp_status cp_profile_enable(cp_ctx ctx, int32_t on);
+/* Synchronize the stream and return, per kernel class, the summed elapsed
+ * milliseconds and the number of launches (host arrays of CP_PROF_CLASSES
+ * entries); clears the records. */
+cp_status cp_profile_read(cp_ctx ctx, double* ms, int32_t* counts);
+
 /* Stable sort of the rank-one terms by decreasing lambda_r (remark after
  * eq. (10)); permutes the columns of every A^(n) (and shadows) in place. */
 cp_status cp_sort(cp_ctx ctx, const int64_t* dims /*host, N*/, int32_t order, cp_factors* A);

@@ -24,6 +24,10 @@ CP_MIXED = 1
 CP_SOLVE_CHOL = 0
 CP_SOLVE_GS = 1
 
+PROF_CLASSES = ["mttkrp_mode0_f64", "mttkrp_mode1_f64", "mttkrp_modeN_f64",
+                "mttkrp_mode0_f32", "mttkrp_mode1_f32", "mttkrp_modeN_f32",
+                "update", "epilogue_other", "gamma_prep", "normalize", "gram", "other"]
+
 CP_FLAG_PINV_FALLBACK = 1
 CP_FLAG_NOT_SPD = 2
 CP_FLAG_NONFINITE = 4
@@ -74,6 +78,8 @@ SIGNATURES = {
     "cp_fas_vcycle": [c_vp, ctypes.POINTER(CpLevel), c_i32, ctypes.POINTER(CpFactors),
                       ctypes.POINTER(CpFasParams), c_i32],
     "cp_sort": [c_vp, ctypes.POINTER(c_i64), c_i32, ctypes.POINTER(CpFactors)],
+    "cp_profile_enable": [c_vp, c_i32],
+    "cp_profile_read": [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i32)],
 }
 
 _lib = None

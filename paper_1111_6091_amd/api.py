@@ -55,6 +55,16 @@ class Context:
         self.check(self._lib.cp_get_status(self.handle, ctypes.byref(flags)))
         return flags.value
 
+    def profile(self, on=True):
+        self.check(self._lib.cp_profile_enable(self.handle, int(bool(on))))
+
+    def profile_read(self):
+        n = len(L.PROF_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int32 * n)()
+        self.check(self._lib.cp_profile_read(self.handle, ms, cnt))
+        return {L.PROF_CLASSES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k]}
+
     def close(self):
         if getattr(self, "handle", None):
             self._lib.cp_ctx_destroy(self.handle)

@@ -36,6 +36,11 @@ struct cp_ctx_s {
   double* chol = nullptr;
   int32_t* chol_kind = nullptr;
   double* scal = nullptr;   // 64 scratch scalars
+  // optional per-launch event timing
+  bool prof = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -62,6 +67,34 @@ cp_status hip_check(cp_ctx c, hipError_t e, const char* what) {
     cp_status _s = hip_check(ctx, (expr), #expr);           \
     if (_s != CP_OK) return _s;                             \
   } while (0)
+
+// Event pair around one launch when profiling is on.
+struct ProfScope {
+  cp_ctx ctx;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(cp_ctx c, int k) : ctx(c), cls(k) {
+    if (!ctx->prof) return;
+    a = take();
+    b = take();
+    if (a) (void)hipEventRecord(a, ctx->stream);
+  }
+  hipEvent_t take() {
+    if (!ctx->pool.empty()) {
+      hipEvent_t e = ctx->pool.back();
+      ctx->pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~ProfScope() {
+    if (!ctx->prof || !a || !b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->recs.push_back({cls, a, b});
+  }
+};
 
 // Grow the workspace to at least `bytes` (synchronizes the stream first).
 cp_status ensure_ws(cp_ctx ctx, size_t bytes) {
@@ -138,9 +171,29 @@ cp_status check_prec(cp_ctx ctx, cp_prec p) {
 cp_status enqueue_mttkrp(cp_ctx ctx, const int64_t* dims, int N, int n, int R, const void* z,
                          bool fp32, const double* const* a64, const float* const* a32,
                          const MttkrpPlan& plan, double* out) {
+  ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + (plan.kind - 1));
   HIPCHK(mttkrp_launch(plan, dims, N, n, R, z, fp32, a64, a32, out, ctx->stream));
   return CP_OK;
 }
+
+cp_status enqueue_epi(cp_ctx ctx, const EpiDesc& d) {
+  ProfScope ps(ctx, d.op == EPI_UPDATE ? CP_PROF_UPDATE : CP_PROF_EPILOGUE_OTHER);
+  HIPCHK(epi_launch(d, ctx->stream));
+  return CP_OK;
+}
+
+cp_status enqueue_gram(cp_ctx ctx, double* const* A, float* const* A32, const int64_t* dims, int N,
+                       int R, double* grams) {
+  ProfScope ps(ctx, CP_PROF_GRAM);
+  HIPCHK(gram_launch(A, A32, dims, N, R, grams, ctx->stream));
+  return CP_OK;
+}
+
+#define TRY(expr)                   \
+  do {                              \
+    cp_status _t = (expr);          \
+    if (_t != CP_OK) return _t;     \
+  } while (0)
 
 size_t max_partial(const int64_t* dims, int N, int R, std::vector<MttkrpPlan>* plans) {
   size_t mx = 0;
@@ -183,9 +236,11 @@ cp_status enqueue_sweep(cp_ctx ctx, const int64_t* dims, int N, int R, const voi
                         const std::vector<MttkrpPlan>& plans, const SweepWS& w, cp_solver solver,
                         int gs_iters, int normalize, double* f_slot, const double* norm2) {
   for (int n = 0; n < N; ++n) {
-    if (solver == CP_SOLVE_CHOL)
+    if (solver == CP_SOLVE_CHOL) {
+      ProfScope ps(ctx, CP_PROF_GAMMA_PREP);
       HIPCHK(gamma_prep_launch(w.grams, N, n, R, ctx->chol, ctx->chol_kind, ctx->flags, solver,
                                ctx->stream));
+    }
     cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
                                  (const float* const*)A32, plans[n], w.partial);
     if (s != CP_OK) return s;
@@ -212,9 +267,12 @@ cp_status enqueue_sweep(cp_ctx ctx, const int64_t* dims, int N, int R, const voi
     d.want_obj = (f_slot && n == N - 1) ? 1 : 0;
     d.scalar_out = f_slot;
     d.norm2 = norm2;
-    HIPCHK(epi_launch(d, ctx->stream));
+    TRY(enqueue_epi(ctx, d));
   }
-  if (normalize) HIPCHK(normalize_launch(A, A32, dims, N, R, w.grams, ctx->stream));
+  if (normalize) {
+    ProfScope ps(ctx, CP_PROF_NORMALIZE);
+    HIPCHK(normalize_launch(A, A32, dims, N, R, w.grams, ctx->stream));
+  }
   return CP_OK;
 }
 
@@ -262,6 +320,11 @@ cp_status cp_ctx_create(cp_ctx* out, void* hip_stream) {
 cp_status cp_ctx_destroy(cp_ctx ctx) {
   if (!ctx) return CP_ERR_INVALID;
   (void)hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->fixed) (void)hipFree(ctx->fixed);
   delete ctx;
@@ -338,7 +401,7 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
   d.In = Z->dims[n];
   d.partial = part;
   d.outbuf = M;
-  HIPCHK(epi_launch(d, ctx->stream));
+  TRY(enqueue_epi(ctx, d));
   return CP_OK;
 }
 
@@ -376,7 +439,7 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   bool have32 = true;
   for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
-  HIPCHK(gram_launch(A->a, have32 ? a32 : nullptr, Z->dims, N, R, w.grams, ctx->stream));
+  TRY(enqueue_gram(ctx, A->a, have32 ? a32 : nullptr, Z->dims, N, R, w.grams));
   for (int k = 0; k < nsweeps; ++k) {
     s = enqueue_sweep(ctx, Z->dims, N, R, z, mixed, A->a, have32 ? A->a32 : nullptr,
                       F ? F->a : nullptr, plans, w, solver, gs_iters, normalize,
@@ -415,7 +478,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
   if (f && exact)
     HIPCHK(residual_launch(Z->z64, Z->dims, N, R, A->a, w.scal_part, ctx->counters + CNT_RES, f,
                            ctx->stream));
-  if (g || (f && !exact)) HIPCHK(gram_launch(A->a, nullptr, Z->dims, N, R, w.grams, ctx->stream));
+  if (g || (f && !exact)) TRY(enqueue_gram(ctx, A->a, nullptr, Z->dims, N, R, w.grams));
   if (g) {
     for (int n = 0; n < N; ++n) {
       if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32,
@@ -435,7 +498,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
       d.counter = ctx->counters + CNT_EPI;
       d.scalar_out = ctx->scal;
       d.accumulate = n > 0;
-      HIPCHK(epi_launch(d, ctx->stream));
+      TRY(enqueue_epi(ctx, d));
     }
     HIPCHK(finish_g_launch(ctx->scal, Z->norm2, g, ctx->stream));
   }
@@ -452,7 +515,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
     d.In = In_last;
     d.partial = w.partial;
     d.outbuf = Mlast;
-    HIPCHK(epi_launch(d, ctx->stream));
+    TRY(enqueue_epi(ctx, d));
     HIPCHK(inner_launch(A->a[N - 1], Mlast, In_last * R, w.gram_part, ctx->counters + CNT_DOT,
                         ctx->scal + 1, ctx->stream));
     HIPCHK(fused_f_launch(w.grams, N, R, ctx->scal + 1, Z->norm2, f, ctx->stream));
@@ -581,6 +644,40 @@ cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat
   return CP_OK;
 }
 
+cp_status cp_profile_enable(cp_ctx ctx, int32_t on) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (on) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (auto& r : ctx->recs) {
+      ctx->pool.push_back(r.a);
+      ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+  }
+  ctx->prof = on != 0;
+  return CP_OK;
+}
+
+cp_status cp_profile_read(cp_ctx ctx, double* ms, int32_t* counts) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!ms || !counts) return set_err(ctx, CP_ERR_INVALID, "cp_profile_read: NULL output");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < CP_PROF_CLASSES; ++k) {
+    ms[k] = 0.0;
+    counts[k] = 0;
+  }
+  for (auto& r : ctx->recs) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    counts[r.cls] += 1;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->recs.clear();
+  return CP_OK;
+}
+
 cp_status cp_sort(cp_ctx ctx, const int64_t* dims, int32_t order, cp_factors* A) {
   if (!ctx) return CP_ERR_INVALID;
   if (!dims) return set_err(ctx, CP_ERR_INVALID, "cp_sort: dims is NULL");
@@ -629,7 +726,7 @@ cp_status fas_relax(FasRun& r, int l, int times) {
   cp_ctx ctx = r.ctx;
   FasLevel& L = r.lv[l];
   if (times <= 0) return CP_OK;
-  HIPCHK(gram_launch(L.A, L.has32 ? L.A32 : nullptr, L.dims, r.N, r.R, L.grams, ctx->stream));
+  TRY(enqueue_gram(ctx, L.A, L.has32 ? L.A32 : nullptr, L.dims, r.N, r.R, L.grams));
   SweepWS w{L.grams, r.partial, r.gram_part, r.scal_part};
   for (int k = 0; k < times; ++k) {
     cp_status s = enqueue_sweep(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A,
@@ -644,7 +741,7 @@ cp_status fas_relax(FasRun& r, int l, int times) {
 cp_status fas_H(FasRun& r, int l, double* const* A, float* const* A32, double* const* Hout) {
   cp_ctx ctx = r.ctx;
   FasLevel& L = r.lv[l];
-  HIPCHK(gram_launch(A, A32, L.dims, r.N, r.R, L.grams, ctx->stream));
+  TRY(enqueue_gram(ctx, A, A32, L.dims, r.N, r.R, L.grams));
   for (int n = 0; n < r.N; ++n) {
     cp_status s = enqueue_mttkrp(ctx, L.dims, r.N, n, r.R, L.z, r.mixed, (const double* const*)A,
                                  (const float* const*)A32, L.plans[n], r.partial);
@@ -660,7 +757,7 @@ cp_status fas_H(FasRun& r, int l, double* const* A, float* const* A32, double* c
     d.A = A[n];
     d.grams = L.grams;
     d.outbuf = Hout[n];
-    HIPCHK(epi_launch(d, ctx->stream));
+    TRY(enqueue_epi(ctx, d));
   }
   return CP_OK;
 }
@@ -781,6 +878,6 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
   for (int l = 0; l < nlevels; ++l) r.lv[l].has32 = (l == 0) ? have32 : (mixed || have32);
   if ((s = fas_vcycle_rec(r, 0)) != CP_OK) return s;
   if (r.lv[0].has32)   // shadows of the finest factors follow the last correction
-    HIPCHK(gram_launch(A->a, A->a32, r.lv[0].dims, N, R, r.lv[0].grams, ctx->stream));
+    TRY(enqueue_gram(ctx, A->a, A->a32, r.lv[0].dims, N, R, r.lv[0].grams));
   return CP_OK;
 }
