@@ -104,33 +104,30 @@ def main():
     ms_fp64, wall_fp64 = timed(CP_FP64, K, W)
     log(f"fp64 sweep: {ms_fp64 * 1e3:.1f} us ({1e3 / ms_fp64:.0f} sweeps/s)")
 
-    # roofline leg: the same sweeps with an event pair around every launch
-    def profiled(prec):
+    # roofline leg: each MTTKRP kernel timed over back-to-back launches in the
+    # launch configuration the sweep uses (HIP events on the library's stream)
+    A = fresh()
+    reps = max(10, min(K, 100))
+    roof = {}
+    for prec, tag, eb in ((CP_MIXED, "f32", 4), (CP_FP64, "f64", 8)):
+        for n in range(len(dims)):
+            ms = api.cp_time_mttkrp(ctx, Zd, A, n, prec, reps)
+            b = mttkrp_bytes(dims, R, n, eb)
+            roof[f"{tag}_mode{n}"] = dict(kernel=f"mttkrp_{('mode0', 'mode1', 'modeN')[min(n, 2)]}_{tag}",
+                                          avg_us=ms * 1e3, bytes_per_launch=b,
+                                          achieved_gbs=b / (ms * 1e-3) / 1e9)
+            log(f"{tag} mode {n}: {ms * 1e3:.2f} us/launch, {b / (ms * 1e-3) / 1e9:.0f} GB/s")
+
+    # per-kernel breakdown of one sweep (event pair around every launch)
+    breakdown = {}
+    for prec, tag in ((CP_MIXED, "f32"), (CP_FP64, "f64")):
         A = fresh()
         api.cp_als_sweep(ctx, Zd, A, None, 2, CP_SOLVE_CHOL, 10, True, prec, fh)
         ctx.profile(True)
         api.cp_als_sweep(ctx, Zd, A, None, K, CP_SOLVE_CHOL, 10, True, prec, fh)
         ctx.profile(False)
-        return ctx.profile_read()
-
-    kinds = {0: "mode0", 1: "mode1", 2: "modeN"}
-    roof = {}
-    for prec, tag, eb in ((CP_MIXED, "f32", 4), (CP_FP64, "f64", 8)):
-        prof = profiled(prec)
-        for n in range(len(dims)):
-            kname = f"mttkrp_{kinds[min(n, 2)]}_{tag}"
-            ms, cnt = prof.get(kname, (0.0, 0))
-            if not cnt:
-                continue
-            per_mode = cnt // (K if n < 2 else K * (len(dims) - 2))
-            avg_us = ms / cnt * 1e3
-            b = mttkrp_bytes(dims, R, n, eb)
-            roof[f"{tag}_mode{n}"] = dict(kernel=kname, avg_us=avg_us, bytes_per_launch=b,
-                                          achieved_gbs=b / (avg_us * 1e-6) / 1e9)
-            del per_mode
-        roof[f"{tag}_breakdown_us_per_sweep"] = {k: v[0] / K * 1e3 for k, v in prof.items()}
-    for k, v in roof.items():
-        log(k, v)
+        breakdown[tag] = {k: round(v[0] / K * 1e3, 2) for k, v in ctx.profile_read().items()}
+        log(f"{tag} per-sweep breakdown (us, event-bracketed): {breakdown[tag]}")
     mix = [v for k, v in roof.items() if k.startswith("f32_mode")]
     dom = max(mix, key=lambda v: v["avg_us"])
     roofline = {
@@ -153,13 +150,13 @@ def main():
         A = fresh()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rm = drivers.mixed_solve(ctx, Zd, A, tol32=1e-7, tol64=1e-12)
+        rm = drivers.mixed_solve(ctx, Zd, A, tol32=1e-9, tol64=1e-12)
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0
         fitm = drivers.exact_fit(ctx, Zd, A)
         log(f"mixed to 1e-12: {rm.sweeps32} FP32 + {rm.sweeps64} FP64 sweeps, {tm:.3f} s, fit {fitm:.15f}")
         equal_fit = {
-            "stop": "relative fit change <= 1e-12 (FP32 phase: <= 1e-7 per sweep)",
+            "stop": "relative fit change <= 1e-12 (FP32 phase: mean gain <= 1e-9 per sweep)",
             "fp64": {"sweeps": r64.sweeps, "seconds": round(t64, 4), "fit": fit64},
             "mixed": {"sweeps_fp32": rm.sweeps32, "sweeps_fp64": rm.sweeps64,
                       "seconds": round(tm, 4), "fit": fitm},
@@ -197,10 +194,10 @@ def main():
                    "dims": list(dims), "rank": R, "parallelism": "single GPU"},
         "fp64_sweeps_per_s": round(1e3 / ms_fp64, 2),
         "wall_seconds": {"mixed": round(wall_mixed, 4), "fp64": round(wall_fp64, 4)},
-        "mttkrp_gbs": {k: round(v["achieved_gbs"], 1) for k, v in roof.items() if "mode" in k and "breakdown" not in k},
+        "mttkrp_gbs": {k: round(v["achieved_gbs"], 1) for k, v in roof.items()},
+        "mttkrp_us": {k: round(v["avg_us"], 2) for k, v in roof.items()},
         "roofline": roofline,
-        "per_sweep_us": {k: {kk: round(vv, 2) for kk, vv in v.items()}
-                         for k, v in roof.items() if k.endswith("breakdown_us_per_sweep")},
+        "per_sweep_us_event_bracketed": breakdown,
         "equal_fit": equal_fit,
         "cpu_baseline": cpu,
     }

@@ -219,6 +219,14 @@ cp_status cp_profile_enable(cp_ctx ctx, int32_t on);
  * entries); clears the records. */
 cp_status cp_profile_read(cp_ctx ctx, double* ms, int32_t* counts);
 
+/* Measurement aid: enqueue `reps` back-to-back launches of the MTTKRP kernel
+ * of mode n, in the launch configuration cp_mttkrp and cp_als_sweep use
+ * (partial sums land in the workspace, M is not written), between two HIP
+ * events recorded on the context's stream; synchronize and return the mean
+ * milliseconds per launch in *ms (host). */
+cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
+                         cp_prec prec, int32_t reps, double* ms);
+
 /* Stable sort of the rank-one terms by decreasing lambda_r (remark after
  * eq. (10)); permutes the columns of every A^(n) (and shadows) in place. */
 cp_status cp_sort(cp_ctx ctx, const int64_t* dims /*host, N*/, int32_t order, cp_factors* A);

@@ -79,6 +79,8 @@ SIGNATURES = {
                       ctypes.POINTER(CpFasParams), c_i32],
     "cp_sort": [c_vp, ctypes.POINTER(c_i64), c_i32, ctypes.POINTER(CpFactors)],
     "cp_profile_enable": [c_vp, c_i32],
+    "cp_time_mttkrp": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_i32,
+                       c_i32, ctypes.POINTER(ctypes.c_double)],
     "cp_profile_read": [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i32)],
 }
 

@@ -253,6 +253,14 @@ def cp_fas_vcycle(ctx, levels, A, nu1=1, nu2=1, nuc=50, gs_iters=10, ic_rule=0, 
                                      ctypes.byref(prm), prec))
 
 
+def cp_time_mttkrp(ctx, Z, A, n, prec=CP_FP64, reps=20):
+    zs, fs = Z.struct(), A.struct()
+    ms = ctypes.c_double(0.0)
+    ctx.check(ctx._lib.cp_time_mttkrp(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), n, prec, reps,
+                                      ctypes.byref(ms)))
+    return ms.value
+
+
 def cp_sort(ctx, A):
     dims = (ctypes.c_int64 * L.CP_MAX_ORDER)(*A.dims)
     fs = A.struct()

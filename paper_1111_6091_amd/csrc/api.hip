@@ -170,9 +170,9 @@ cp_status check_prec(cp_ctx ctx, cp_prec p) {
 // Enqueue M^(n) partials for tensor Z (precision prec); returns the plan.
 cp_status enqueue_mttkrp(cp_ctx ctx, const int64_t* dims, int N, int n, int R, const void* z,
                          bool fp32, const double* const* a64, const float* const* a32,
-                         const MttkrpPlan& plan, double* out) {
+                         const MttkrpPlan& plan, double* out, const PrepArgs* prep = nullptr) {
   ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + (plan.kind - 1));
-  HIPCHK(mttkrp_launch(plan, dims, N, n, R, z, fp32, a64, a32, out, ctx->stream));
+  HIPCHK(mttkrp_launch(plan, dims, N, n, R, z, fp32, a64, a32, out, prep, ctx->stream));
   return CP_OK;
 }
 
@@ -195,10 +195,10 @@ cp_status enqueue_gram(cp_ctx ctx, double* const* A, float* const* A32, const in
     if (_t != CP_OK) return _t;     \
   } while (0)
 
-size_t max_partial(const int64_t* dims, int N, int R, std::vector<MttkrpPlan>* plans) {
+size_t max_partial(const int64_t* dims, int N, int R, bool fp32, std::vector<MttkrpPlan>* plans) {
   size_t mx = 0;
   for (int n = 0; n < N; ++n) {
-    MttkrpPlan p = mttkrp_plan(N, dims, n, R, kTargetWgs);
+    MttkrpPlan p = mttkrp_plan(N, dims, n, R, kTargetWgs, fp32);
     if (plans) plans->push_back(p);
     mx = std::max(mx, p.partial_doubles);
   }
@@ -235,14 +235,11 @@ cp_status enqueue_sweep(cp_ctx ctx, const int64_t* dims, int N, int R, const voi
                         double* const* A, float* const* A32, double* const* F,
                         const std::vector<MttkrpPlan>& plans, const SweepWS& w, cp_solver solver,
                         int gs_iters, int normalize, double* f_slot, const double* norm2) {
+  PrepArgs prep{w.grams, ctx->chol, ctx->chol_kind, ctx->flags};
   for (int n = 0; n < N; ++n) {
-    if (solver == CP_SOLVE_CHOL) {
-      ProfScope ps(ctx, CP_PROF_GAMMA_PREP);
-      HIPCHK(gamma_prep_launch(w.grams, N, n, R, ctx->chol, ctx->chol_kind, ctx->flags, solver,
-                               ctx->stream));
-    }
     cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
-                                 (const float* const*)A32, plans[n], w.partial);
+                                 (const float* const*)A32, plans[n], w.partial,
+                                 solver == CP_SOLVE_CHOL ? &prep : nullptr);
     if (s != CP_OK) return s;
     EpiDesc d{};
     d.op = EPI_UPDATE;
@@ -267,11 +264,15 @@ cp_status enqueue_sweep(cp_ctx ctx, const int64_t* dims, int N, int R, const voi
     d.want_obj = (f_slot && n == N - 1) ? 1 : 0;
     d.scalar_out = f_slot;
     d.norm2 = norm2;
+    if (normalize && n == N - 1) {
+      d.normalize = 1;
+      for (int m = 0; m < N; ++m) {
+        d.Aall[m] = A[m];
+        d.A32all[m] = A32 ? A32[m] : nullptr;
+        d.dims[m] = dims[m];
+      }
+    }
     TRY(enqueue_epi(ctx, d));
-  }
-  if (normalize) {
-    ProfScope ps(ctx, CP_PROF_NORMALIZE);
-    HIPCHK(normalize_launch(A, A32, dims, N, R, w.grams, ctx->stream));
   }
   return CP_OK;
 }
@@ -383,7 +384,7 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: mode %d outside [0, %d)", n, N);
   if (!M) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: M is NULL");
   const int R = A->rank;
-  MttkrpPlan plan = mttkrp_plan(N, Z->dims, n, R, kTargetWgs);
+  MttkrpPlan plan = mttkrp_plan(N, Z->dims, n, R, kTargetWgs, mixed);
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   if (plan.nsplit == 1)
     return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M);
@@ -428,7 +429,7 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   if (nsweeps == 0) return CP_OK;
   const int R = A->rank;
   std::vector<MttkrpPlan> plans;
-  const size_t part = max_partial(Z->dims, N, R, &plans);
+  const size_t part = max_partial(Z->dims, N, R, mixed, &plans);
   Sizer sz;
   SweepWS w{};
   carve_sweep(sz, N, R, part, max_dim(Z->dims, N), &w);
@@ -464,7 +465,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
     return set_err(ctx, CP_ERR_INVALID, "cp_objective: g and the fused f need Z->norm2");
   const int R = A->rank;
   std::vector<MttkrpPlan> plans;
-  const size_t part = max_partial(Z->dims, N, R, &plans);
+  const size_t part = max_partial(Z->dims, N, R, mixed, &plans);
   const int64_t In_last = Z->dims[N - 1];
   Sizer sz;
   SweepWS w{};
@@ -641,6 +642,39 @@ cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat
   cp_status s = ensure_ws(ctx, align_up(2 * Ic * sizeof(double)));
   if (s != CP_OK) return s;
   HIPCHK(transfer_build_launch(I, w, phat, (double*)ctx->ws, ctx->stream));
+  return CP_OK;
+}
+
+cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
+                         cp_prec prec, int32_t reps, double* ms) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
+  if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: bad mode %d", n);
+  if (reps < 1 || !ms) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: reps < 1 or ms NULL");
+  const int R = A->rank;
+  MttkrpPlan plan = mttkrp_plan(N, Z->dims, n, R, kTargetWgs, mixed);
+  if ((s = ensure_ws(ctx, align_up(plan.partial_doubles * sizeof(double)))) != CP_OK) return s;
+  double* part = (double*)ctx->ws;
+  const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, ctx->stream));
+  for (int k = 0; k < reps; ++k)
+    HIPCHK(mttkrp_launch(plan, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
+                         nullptr, ctx->stream));
+  HIPCHK(hipEventRecord(e1, ctx->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
   return CP_OK;
 }
 
@@ -839,7 +873,7 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
       L.phat[n] = (l + 1 < nlevels) ? levels[l].phat[n] : nullptr;
     }
     L.z = mixed ? (const void*)levels[l].z.z32 : (const void*)levels[l].z.z64;
-    maxpart = std::max(maxpart, max_partial(L.dims, N, R, &L.plans));
+    maxpart = std::max(maxpart, max_partial(L.dims, N, R, mixed, &L.plans));
     maxI = std::max(maxI, max_dim(L.dims, N));
   }
   auto carve = [&](auto& c, bool real) {

@@ -55,6 +55,20 @@ struct MttkrpDesc {
   int32_t kchunk;                 // contraction length per piece (multiple of 16)
   int32_t rgroups;                // kind 3: number of row groups over I1
   int64_t rest_count;             // kind 3: number of stripes per output value
+  // optional: an extra last workgroup factors Gamma^(n) for the update that follows
+  int32_t prep;
+  const double* grams;            // [N][R][R]
+  double* chol;                   // [R][R] output (L or pseudoinverse)
+  int32_t* chol_kind;             // 0 = L, 1 = pseudoinverse
+  uint32_t* flags;
+};
+
+// Gamma^(n) factorization request carried by an MTTKRP launch
+struct PrepArgs {
+  const double* grams;
+  double* chol;
+  int32_t* chol_kind;
+  uint32_t* flags;
 };
 
 // planner + launcher (mttkrp.hip)
@@ -66,10 +80,11 @@ struct MttkrpPlan {
   int32_t nt;               // 16-column tiles (ceil(R/16))
 };
 
-MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs);
+MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs, bool fp32);
 hipError_t mttkrp_launch(const MttkrpPlan& plan, const int64_t* dims, int N, int n, int R,
                          const void* z, bool fp32, const double* const* a64,
-                         const float* const* a32, double* out, hipStream_t st);
+                         const float* const* a32, double* out, const PrepArgs* prep,
+                         hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Mode epilogue: reduce MTTKRP partials and act on the rows
@@ -101,6 +116,11 @@ struct EpiDesc {
   uint32_t* flags;
   int32_t want_obj;           // EPI_UPDATE: write fused f into scalar_out
   int32_t accumulate;         // EPI_GRAD: add to scalar_out instead of overwrite
+  // EPI_UPDATE of the last mode: apply eq. (10) to every factor in the last block
+  int32_t normalize;
+  double* Aall[kMaxOrder];
+  float* A32all[kMaxOrder];
+  int64_t dims[kMaxOrder];
 };
 
 hipError_t epi_launch(const EpiDesc& d, hipStream_t st);

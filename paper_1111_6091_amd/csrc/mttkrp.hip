@@ -51,6 +51,21 @@ __device__ __forceinline__ typename Vec4<T>::type load4(const T* __restrict__ p,
   return v;
 }
 
+// 32 bytes per lane: VW = 4 doubles or 8 floats, as one or two 4-wide loads.
+template <typename T> struct VW_ { static constexpr int value = 32 / sizeof(T); };
+
+template <typename T, bool VEC>
+__device__ __forceinline__ void loadw(const T* __restrict__ p, int nvalid, T (&out)[VW_<T>::value]) {
+  constexpr int VW = VW_<T>::value;
+#pragma unroll
+  for (int q = 0; q < VW / 4; ++q) {
+    const int nv = nvalid - 4 * q;
+    const typename Vec4<T>::type v = load4<T, VEC>(p + 4 * q, nv < 0 ? 0 : (nv > 4 ? 4 : nv));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[4 * q + e] = v[e];
+  }
+}
+
 // Product of the stripe-mode factors at stripe s, column col (skip mode `skip`).
 __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, int col, int skip) {
   if (col >= d.R) return 0.0;
@@ -63,14 +78,28 @@ __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, 
   return w;
 }
 
+constexpr int kSmem = 4096;   // doubles of LDS per workgroup (32 KB)
+
+// The extra last workgroup of a launch factors Gamma^(n) for the R x R update
+// that follows the MTTKRP, concurrently with the streaming workgroups.
+__device__ __forceinline__ bool prep_block(const MttkrpDesc& d, double* smem) {
+  if (!d.prep || blockIdx.x != gridDim.x - 1) return false;
+  gamma_prepare(d.grams, d.N, d.n, d.R, d.chol, d.chol_kind, d.flags, smem);
+  return true;
+}
+
 // ---------------------------------------------------------------------------
-// kind 1: output mode 0.  GEMM rows = i0 (64 per wave: 4 sub-tiles of 16 with
-// row i0 = p*64 + 16*(l/16)... see below), contraction over i1, stripes weighted.
+// kind 1: output mode 0.  Each lane loads VW consecutive rows i0 at one i1;
+// sub-tile a holds rows i0 = grp*16*VW + VW*m + a (m = GEMM row).  Contraction
+// over i1 on the matrix cores, Hadamard weight per stripe in FP64.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, bool VEC>
 __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
   typedef typename Vec4<T>::type V;
-  __shared__ double red[4 * 64 * 16 * NT];
+  constexpr int VW = VW_<T>::value;
+  constexpr int PANEL = 16 * VW;
+  __shared__ double smem[kSmem];
+  if (prep_block(d, smem)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g4 = lane >> 4;
   const int grp = blockIdx.x % d.ngroups;
@@ -79,12 +108,13 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
   const T* __restrict__ ak = reinterpret_cast<const T*>(d.ak);
   const int R = d.R;
   const int64_t I0 = d.I0, I1 = d.I1;
-  const int64_t i0b = (int64_t)grp * 64 + 4 * r;     // first of this lane's 4 rows
-  const int nrow = (int)((I0 - i0b) < 4 ? ((I0 - i0b) > 0 ? (I0 - i0b) : 0) : 4);
+  const int64_t i0b = (int64_t)grp * PANEL + VW * r;   // first of this lane's VW rows
+  const int64_t left = I0 - i0b;
+  const int nrow = left <= 0 ? 0 : (left >= VW ? VW : (int)left);
 
-  double acc[4][NT][4];
+  double acc[VW][NT][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < VW; ++a)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -100,20 +130,20 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
     double w[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) w[t] = stripe_weight(d, s, t * 16 + r, -1);
-    typename Vec4<T>::type D[4][NT];
+    V D[VW][NT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < VW; ++a)
 #pragma unroll
       for (int t = 0; t < NT; ++t) D[a][t] = V{0, 0, 0, 0};
     const T* __restrict__ zs = z + (size_t)s * I0 * I1 + i0b;
     for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
-      V zv[4];
+      T zv[4][VW];
       T b[4][NT];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i1 = k0 + 4 * g4 + e;
         const bool ok = i1 < kend;
-        zv[e] = load4<T, VEC>(zs + (ok ? i1 : 0) * I0, ok ? nrow : 0);
+        loadw<T, VEC>(zs + (ok ? i1 : 0) * I0, ok ? nrow : 0, zv[e]);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const int col = t * 16 + r;
@@ -123,48 +153,57 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < VW; ++a)
 #pragma unroll
           for (int t = 0; t < NT; ++t) D[a][t] = mma(zv[e][a], b[e][t], D[a][t]);
     }
     // Hadamard-reduce with the stripe weight (FP64)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < VW; ++a)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[a][t][v] += (double)D[a][t][v] * w[t];
   }
-  // deterministic cross-wave reduction: GEMM row m holds i0 = grp*64 + 4*m + a
+  // deterministic cross-wave reduction through LDS, 4 sub-tiles x 16 columns at
+  // a time: GEMM row m of sub-tile a holds i0 = grp*PANEL + VW*m + a
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a0 = 0; a0 < VW; a0 += 4)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t) {
+      __syncthreads();
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        red[(wave * 64 + 4 * mfma_row<T>(g4, v) + a) * (16 * NT) + t * 16 + r] = acc[a][t][v];
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < 64 * 16 * NT; idx += kThreads) {
-    const int row = idx / (16 * NT), col = idx % (16 * NT);
-    const int64_t i0 = (int64_t)grp * 64 + row;
-    if (col < R && i0 < I0) {
-      const double sum = red[idx] + red[64 * 16 * NT + idx] + red[2 * 64 * 16 * NT + idx] +
-                         red[3 * 64 * 16 * NT + idx];
-      d.out[((size_t)split * d.In + i0) * R + col] = sum;
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          smem[(wave * 64 + mfma_row<T>(g4, v) * 4 + a) * 16 + r] = acc[a0 + a][t][v];
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < 64 * 16; idx += kThreads) {
+        const int q = idx / 16, c = idx % 16;   // q = 4*m + a
+        const int m = q >> 2, a = q & 3;
+        const int64_t i0 = (int64_t)grp * PANEL + VW * m + a0 + a;
+        const int col = t * 16 + c;
+        if (col < R && i0 < I0) {
+          const double sum = smem[idx] + smem[1024 + idx] + smem[2048 + idx] + smem[3072 + idx];
+          d.out[((size_t)split * d.In + i0) * R + col] = sum;
+        }
+      }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
-// kinds 2 and 3: GEMM rows = i1 (16*TW per wave), contraction over i0.
-// kind 2 (n == 1): rows are the outputs; kind 3 (n >= 2): rows are reduced
-// with A^(1)(i1, r) into output s_n.
+// kinds 2 and 3: GEMM rows = i1 (16*TW per wave), contraction over i0 with VW
+// consecutive i0 per lane.  kind 2 (n == 1): rows are the outputs; kind 3
+// (n >= 2): rows are reduced with A^(1)(i1, r) into output s_n.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int TW, bool KIND3, bool VEC>
 __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   typedef typename Vec4<T>::type V;
+  constexpr int VW = VW_<T>::value;
+  constexpr int KC = 4 * VW;   // contraction chunk per step of the loop
   constexpr int ROWS = 16 * TW;
-  __shared__ double red[KIND3 ? 4 * 16 * NT : 4 * ROWS * 16 * NT];
+  __shared__ double smem[kSmem];
+  if (prep_block(d, smem)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g4 = lane >> 4;
   const int grp = blockIdx.x % d.ngroups;
@@ -174,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   const int R = d.R;
   const int64_t I0 = d.I0, I1 = d.I1;
 
-  // kind 2: acc[tw][t][v] holds rows grp*ROWS + tw*16 + mfma_row<T>(g4, v)
+  // kind 2: acc[tw][t][v] holds row grp*ROWS + tw*16 + mfma_row<T>(g4, v)
   // kind 3: acc[0][t][0] holds the running sum for column t*16 + r
   double acc[TW][NT][4];
 #pragma unroll
@@ -186,9 +225,8 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
 
   const int64_t ubeg = (int64_t)split * d.chunk;
   const int64_t uend = min(d.units, ubeg + d.chunk);
-  int64_t stride_n = 1;
-  int jn = d.n - 2;
-  if (KIND3) stride_n = d.sst[jn];
+  const int jn = d.n - 2;
+  const int64_t stride_n = KIND3 ? d.sst[jn] : 1;
   for (int64_t u = ubeg + wave; u < uend; u += 4) {
     const int kp = (int)(u % d.ksplit);
     const int64_t uu = u / d.ksplit;
@@ -220,30 +258,29 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) D[a][t] = V{0, 0, 0, 0};
     const T* __restrict__ zs = z + (size_t)s * I0 * I1;
-    int nrowok[TW];
+    bool rowok[TW];
 #pragma unroll
-    for (int a = 0; a < TW; ++a) nrowok[a] = (rowbase + a * 16 + r) < I1;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
-      const int64_t kl = k0 + 4 * g4;
+    for (int a = 0; a < TW; ++a) rowok[a] = (rowbase + a * 16 + r) < I1;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+      const int64_t kl = k0 + VW * g4;
       const int64_t nk = kend - kl;
-      const int nval = nk >= 4 ? 4 : (nk > 0 ? (int)nk : 0);
-      V zv[TW];
+      const int nval = nk >= VW ? VW : (nk > 0 ? (int)nk : 0);
+      T zv[TW][VW];
 #pragma unroll
       for (int a = 0; a < TW; ++a) {
         const int64_t i1 = rowbase + a * 16 + r;
-        zv[a] = load4<T, VEC>(zs + (nrowok[a] ? i1 : 0) * I0 + (nval ? kl : 0),
-                              nrowok[a] ? nval : 0);
+        loadw<T, VEC>(zs + (rowok[a] ? i1 : 0) * I0 + (nval ? kl : 0), rowok[a] ? nval : 0, zv[a]);
       }
-      T b[4][NT];
+      T b[VW][NT];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < VW; ++e)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const int col = t * 16 + r;
           b[e][t] = (e < nval && col < R) ? ak[(kl + e) * R + col] : T(0);
         }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < VW; ++e)
 #pragma unroll
         for (int a = 0; a < TW; ++a)
 #pragma unroll
@@ -281,31 +318,32 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
       double x = acc[0][t][0];
       x += __shfl_xor(x, 16);
       x += __shfl_xor(x, 32);
-      if (g4 == 0) red[wave * 16 * NT + t * 16 + r] = x;
+      if (g4 == 0) smem[wave * 16 * NT + t * 16 + r] = x;
     }
     __syncthreads();
     if (threadIdx.x < 16 * NT) {
       const int col = threadIdx.x;
       if (col < R) {
-        const double sum = red[col] + red[16 * NT + col] + red[32 * NT + col] + red[48 * NT + col];
+        const double sum = smem[col] + smem[16 * NT + col] + smem[32 * NT + col] + smem[48 * NT + col];
         d.out[((size_t)split * d.In + grp) * R + col] = sum;
       }
     }
   } else {
+    static_assert(4 * ROWS * 16 * NT <= kSmem, "reduction buffer");
 #pragma unroll
     for (int a = 0; a < TW; ++a)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          red[(wave * ROWS + a * 16 + mfma_row<T>(g4, v)) * (16 * NT) + t * 16 + r] = acc[a][t][v];
+          smem[(wave * ROWS + a * 16 + mfma_row<T>(g4, v)) * (16 * NT) + t * 16 + r] = acc[a][t][v];
     __syncthreads();
     for (int idx = threadIdx.x; idx < ROWS * 16 * NT; idx += kThreads) {
       const int row = idx / (16 * NT), col = idx % (16 * NT);
       const int64_t i1 = (int64_t)grp * ROWS + row;
       if (col < R && i1 < I1) {
         const int st = ROWS * 16 * NT;
-        const double sum = red[idx] + red[st + idx] + red[2 * st + idx] + red[3 * st + idx];
+        const double sum = smem[idx] + smem[st + idx] + smem[2 * st + idx] + smem[3 * st + idx];
         d.out[((size_t)split * d.In + i1) * R + col] = sum;
       }
     }
@@ -317,41 +355,44 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
 // ---------------------------------------------------------------------------
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs) {
+MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs, bool fp32) {
   MttkrpPlan p{};
   const int64_t I0 = dims[0], I1 = dims[1];
   int64_t S = 1;
   for (int m = 2; m < N; ++m) S *= dims[m];
+  const int64_t vw = fp32 ? 8 : 4;   // elements per 32-byte lane load
   p.nt = R <= 16 ? 1 : 2;
   p.tw = 2;
   const int64_t rows = 16 * p.tw;
-  int64_t base_units;
-  int64_t K;
+  int64_t base_units, K, kgran;
   if (n == 0) {
     p.kind = 1;
-    p.ngroups = (int32_t)ceil_div(I0, 64);
+    p.ngroups = (int32_t)ceil_div(I0, 16 * vw);
     base_units = S;
     K = I1;
+    kgran = 16;
   } else if (n == 1) {
     p.kind = 2;
     p.ngroups = (int32_t)ceil_div(I1, rows);
     base_units = S;
     K = I0;
+    kgran = 4 * vw;
   } else {
     p.kind = 3;
     p.ngroups = (int32_t)dims[n];
     p.rgroups = (int32_t)ceil_div(I1, rows);
     base_units = p.rgroups * (S / dims[n]);
     K = I0;
+    kgran = 4 * vw;
   }
   // split the contraction when there are too few (group, unit) pairs for the chip
   const int64_t want_units = (int64_t)target_wgs * 4;
   int64_t ks = 1;
-  const int64_t kchunks16 = ceil_div(K, 16);
+  const int64_t kchunks = ceil_div(K, kgran);
   if ((int64_t)p.ngroups * base_units < want_units)
-    ks = std::min<int64_t>(kchunks16, ceil_div(want_units, (int64_t)p.ngroups * base_units));
+    ks = std::min<int64_t>(kchunks, ceil_div(want_units, (int64_t)p.ngroups * base_units));
   if (ks < 1) ks = 1;
-  int64_t kchunk = ceil_div(kchunks16, ks) * 16;
+  const int64_t kchunk = ceil_div(kchunks, ks) * kgran;
   ks = ceil_div(K, kchunk);
   p.ksplit = (int32_t)ks;
   p.kchunk = (int32_t)kchunk;
@@ -367,7 +408,7 @@ MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs)
 template <typename T, int NT>
 static hipError_t launch_typed(const MttkrpPlan& p, const MttkrpDesc& d, bool vec,
                                hipStream_t st) {
-  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit)), block(kThreads);
+  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
   if (p.kind == 1) {
     if (vec) hipLaunchKernelGGL((mttkrp_kind1<T, NT, true>), grid, block, 0, st, d);
     else hipLaunchKernelGGL((mttkrp_kind1<T, NT, false>), grid, block, 0, st, d);
@@ -383,8 +424,16 @@ static hipError_t launch_typed(const MttkrpPlan& p, const MttkrpDesc& d, bool ve
 
 hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
                          const void* z, bool fp32, const double* const* a64,
-                         const float* const* a32, double* out, hipStream_t st) {
+                         const float* const* a32, double* out, const PrepArgs* prep,
+                         hipStream_t st) {
   MttkrpDesc d{};
+  if (prep) {
+    d.prep = 1;
+    d.grams = prep->grams;
+    d.chol = prep->chol;
+    d.chol_kind = prep->chol_kind;
+    d.flags = prep->flags;
+  }
   d.z = z;
   d.N = N;
   d.n = n;
@@ -418,6 +467,7 @@ hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n,
   // an aligned base
   const size_t esz = fp32 ? 4 : 8;
   const bool vec = (dims[0] % 4 == 0) && (((uintptr_t)z) % (4 * esz) == 0);
+  (void)esz;
   if (fp32) {
     return p.nt == 1 ? launch_typed<float, 1>(p, d, vec, st) : launch_typed<float, 2>(p, d, vec, st);
   }

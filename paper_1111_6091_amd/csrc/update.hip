@@ -7,7 +7,7 @@
 
 namespace cpamg {
 
-constexpr int EPI_ROWS = 16;
+constexpr int EPI_ROWS = 4;
 constexpr int LDP = kMaxRank + 1;   // padded LDS row stride (doubles)
 
 int epi_rows_per_wg() { return EPI_ROWS; }
@@ -42,15 +42,108 @@ __device__ inline bool arrive_last(int32_t* counter, int* s_flag) {
   return last;
 }
 
+// Sum p[k * stride] for k = k0, k0 + step, ... < count in increasing k, with
+// 16 independent (predicated) loads in flight per round; the additions stay in
+// order, and the padding adds exact zeros.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int k0, int count,
+                                              int step, size_t stride) {
+  double s = 0.0;
+  for (int k = k0; k < count; k += 16 * step) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int kk = k + q * step;
+      v[q] = kk < count ? p[(size_t)kk * stride] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += v[q];
+  }
+  return s;
+}
+
+// Sum the MTTKRP partials of this block's rows in a fixed order.  The
+// (row, column) pairs are spread over thread groups that each take every G-th
+// split; group sums are then added in group order.
+__device__ inline void reduce_partials(const EpiDesc& d, int64_t row0, int nrows, double* sM,
+                                       double* sT) {
+  const int R = d.R;
+  const int pairs = nrows * R;
+  const int G = pairs > 0 ? max(1, min(kThreads / pairs, 16)) : 1;
+  const int tid = threadIdx.x;
+  if (tid < pairs * G) {
+    const int pr = tid % pairs, g = tid / pairs;
+    const int row = pr / R, col = pr % R;
+    sT[g * (EPI_ROWS * kMaxRank) + pr] =
+        strided_sum(d.partial + (row0 + row) * R + col, g, d.nsplit, G, (size_t)d.In * R);
+  }
+  __syncthreads();
+  if (tid < pairs) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += sT[g * (EPI_ROWS * kMaxRank) + tid];
+    sM[(tid / R) * LDP + tid % R] = s;
+  }
+  __syncthreads();
+}
+
+// Solve one row x Gamma = b on one wavefront: lane j < R holds b_j, returns x_j.
+// kind 0: G holds L with Gamma = L L^T (forward, then backward substitution,
+// column by column); kind 1: G holds the pseudoinverse (x = b G).
+__device__ inline double wave_chol_solve(double b, const double* G, int R, int kind, int lane) {
+  if (kind == 1) {
+    double x = 0.0;
+    for (int i = 0; i < R; ++i) {
+      const double bi = __shfl(b, i);
+      if (lane < R) x += bi * G[i * R + lane];
+    }
+    return x;
+  }
+  // L y = b
+  double y = b;
+  for (int k = 0; k < R; ++k) {
+    const double yk = __shfl(y, k) / G[k * R + k];
+    if (lane == k) y = yk;
+    else if (lane > k && lane < R) y -= G[lane * R + k] * yk;
+  }
+  // L^T x = y
+  double x = y;
+  for (int k = R - 1; k >= 0; --k) {
+    const double xk = __shfl(x, k) / G[k * R + k];
+    if (lane == k) x = xk;
+    else if (lane < k) x -= G[k * R + lane] * xk;
+  }
+  return x;
+}
+
+// Gauss-Seidel on one row x Gamma = b (Gamma in G), r = 0..R-1 in order, warm
+// start x0; lane j < R holds b_j and x_j.
+__device__ inline double wave_gs(double b, double x, const double* G, int R, int iters, int lane) {
+  for (int it = 0; it < iters; ++it) {
+    for (int r = 0; r < R; ++r) {
+      const double dg = G[r * R + r];
+      if (dg == 0.0) continue;
+      double t = (lane < R) ? x * G[lane * R + r] : 0.0;
+      for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off);
+      t = __shfl(t, 0);   // lanes 0..31 hold the sum over the R <= 32 terms
+      const double br = __shfl(b, r);
+      const double xr = __shfl(x, r);
+      const double v = (br - t + xr * dg) / dg;
+      if (lane == r) x = v;
+    }
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
   __shared__ double sG[kMaxRank * kMaxRank];
   __shared__ double sM[EPI_ROWS * LDP];
   __shared__ double sX[EPI_ROWS * LDP];
+  __shared__ double sT[16 * EPI_ROWS * kMaxRank];
   __shared__ double sU[kMaxRank * kMaxRank];
+  __shared__ double sc[kMaxOrder * kMaxRank];
   __shared__ double sred[8];
   __shared__ int s_flag;
   const int R = d.R;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * EPI_ROWS;
   const int nrows = (int)std::min<int64_t>(EPI_ROWS, d.In - row0);
   const bool chol = (d.op == EPI_UPDATE && d.solver == CP_SOLVE_CHOL);
@@ -64,16 +157,7 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
       hadamard_gamma(d.grams, d.N, d.n, R, sG);
     }
   }
-  // reduce the MTTKRP partials in a fixed order
-  for (int idx = tid; idx < nrows * R; idx += kThreads) {
-    const int row = idx / R, col = idx % R;
-    const double* p = d.partial + (row0 + row) * R + col;
-    const size_t stride = (size_t)d.In * R;
-    double s = 0.0;
-    for (int c = 0; c < d.nsplit; ++c) s += p[c * stride];
-    sM[row * LDP + col] = s;
-  }
-  __syncthreads();
+  reduce_partials(d, row0, nrows, sM, sT);
 
   if (d.op == EPI_STORE_M) {
     for (int idx = tid; idx < nrows * R; idx += kThreads) {
@@ -85,118 +169,161 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
 
   if (d.op == EPI_H || d.op == EPI_GRAD) {
     double sq = 0.0;
-    if (tid < nrows) {
-      const double* a = d.A + (row0 + tid) * R;
-      for (int j = 0; j < R; ++j) {
-        double h = 0.0;
-        for (int k = 0; k < R; ++k) h += a[k] * sG[k * R + j];
-        h -= sM[tid * LDP + j];
-        if (d.op == EPI_H) d.outbuf[(row0 + tid) * R + j] = h;
-        sq += h * h;
-      }
+    if (tid < nrows * R) {
+      const int row = tid / R, j = tid % R;
+      const double* a = d.A + (row0 + row) * R;
+      double h = 0.0;
+      for (int k = 0; k < R; ++k) h += a[k] * sG[k * R + j];
+      h -= sM[row * LDP + j];
+      if (d.op == EPI_H) d.outbuf[(row0 + row) * R + j] = h;
+      sq = h * h;
     }
     if (d.op == EPI_H) return;
     const double tot = block_sum(sq, sred);
     if (tid == 0) d.scal_part[blockIdx.x] = tot;
     if (arrive_last(d.counter, &s_flag)) {
+      double acc = 0.0;
+      for (int b = tid; b < (int)gridDim.x; b += kThreads) acc += d.scal_part[b];
+      const double tot2 = block_sum(acc, sred);
       if (tid == 0) {
-        double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += d.scal_part[b];
-        *d.scalar_out = d.accumulate ? (*d.scalar_out + s) : s;
+        *d.scalar_out = d.accumulate ? (*d.scalar_out + tot2) : tot2;
         atomicExch(d.counter, 0);
       }
     }
     return;
   }
 
-  // ---- EPI_UPDATE ---------------------------------------------------------
-  if (tid < nrows) {
-    double* x = sX + tid * LDP;
-    const double* m = sM + tid * LDP;
-    const double* f = d.F ? d.F + (row0 + tid) * R : nullptr;
-    bool finite = true;
+  // ---- EPI_UPDATE: wave w solves row w ------------------------------------
+  if (wave < nrows) {
+    const int64_t row = row0 + wave;
+    const double b = (lane < R) ? sM[wave * LDP + lane] + (d.F ? d.F[row * R + lane] : 0.0) : 0.0;
+    double x;
     if (chol) {
-      if (kind == 0) {
-        // X Gamma = B with Gamma = L L^T:  L y = b, then L^T x = y (per row)
-        for (int i = 0; i < R; ++i) {
-          double y = m[i] + (f ? f[i] : 0.0);
-          for (int k = 0; k < i; ++k) y -= sG[i * R + k] * x[k];
-          x[i] = y / sG[i * R + i];
-        }
-        for (int i = R - 1; i >= 0; --i) {
-          double y = x[i];
-          for (int k = i + 1; k < R; ++k) y -= sG[k * R + i] * x[k];
-          x[i] = y / sG[i * R + i];
-        }
-      } else {
-        // pseudoinverse (symmetric): x = b P
-        double b[kMaxRank];
-        for (int i = 0; i < R; ++i) b[i] = m[i] + (f ? f[i] : 0.0);
-        for (int j = 0; j < R; ++j) {
-          double acc = 0.0;
-          for (int i = 0; i < R; ++i) acc += b[i] * sG[i * R + j];
-          x[j] = acc;
-        }
-      }
+      x = wave_chol_solve(b, sG, R, kind, lane);
     } else {
-      // Gauss-Seidel, warm start from the current row, r = 0..R-1 in order
-      const double* a = d.A + (row0 + tid) * R;
-      for (int j = 0; j < R; ++j) x[j] = a[j];
-      for (int it = 0; it < d.gs_iters; ++it) {
-        for (int r = 0; r < R; ++r) {
-          const double dg = sG[r * R + r];
-          if (dg == 0.0) continue;
-          double s = 0.0;
-          for (int k = 0; k < R; ++k) s += x[k] * sG[k * R + r];
-          s = (m[r] + (f ? f[r] : 0.0)) - s + x[r] * dg;
-          x[r] = s / dg;
-        }
-      }
+      const double x0 = (lane < R) ? d.A[row * R + lane] : 0.0;
+      x = wave_gs(b, x0, sG, R, d.gs_iters, lane);
     }
-    for (int j = 0; j < R; ++j) finite = finite && isfinite(x[j]);
-    if (!finite) atomicOr(d.flags, CP_FLAG_NONFINITE);
+    if (lane < R) {
+      if (!isfinite(x)) atomicOr(d.flags, CP_FLAG_NONFINITE);
+      sX[wave * LDP + lane] = x;
+      d.A[row * R + lane] = x;
+      if (d.A32) d.A32[row * R + lane] = (float)x;
+    }
   }
   __syncthreads();
-  for (int idx = tid; idx < nrows * R; idx += kThreads) {
-    const int row = idx / R, col = idx % R;
-    const double v = sX[row * LDP + col];
-    d.A[(row0 + row) * R + col] = v;
-    if (d.A32) d.A32[(row0 + row) * R + col] = (float)v;
-  }
-  // Gram partial of this block's rows and <A, M> partial
-  for (int idx = tid; idx < R * R; idx += kThreads) {
-    const int a = idx / R, b = idx % R;
-    double s = 0.0;
-    for (int row = 0; row < nrows; ++row) s += sX[row * LDP + a] * sX[row * LDP + b];
-    d.gram_part[(size_t)blockIdx.x * R * R + idx] = s;
-  }
   double ip = 0.0;
-  if (d.want_obj && tid < nrows)
-    for (int j = 0; j < R; ++j) ip += sX[tid * LDP + j] * sM[tid * LDP + j];
+  if (d.want_obj && tid < nrows * R) ip = sX[(tid / R) * LDP + tid % R] * sM[(tid / R) * LDP + tid % R];
   const double ipb = block_sum(ip, sred);
   if (tid == 0) d.scal_part[blockIdx.x] = ipb;
-  if (arrive_last(d.counter, &s_flag)) {
-    const int nwg = gridDim.x;
-    for (int idx = tid; idx < R * R; idx += kThreads) {
-      double s = 0.0;
-      for (int b = 0; b < nwg; ++b) s += d.gram_part[(size_t)b * R * R + idx];
-      sU[idx] = s;
-      d.grams[(size_t)d.n * R * R + idx] = s;
+  if (!arrive_last(d.counter, &s_flag)) return;
+
+  // ---- last block: Upsilon^(n) = A^T A from the finished factor, fused
+  // objective, normalization -------------------------------------------------
+  const int nwg = gridDim.x;
+  {
+    const int RR = R * R;
+    constexpr int TILE = 2048;   // doubles of A staged per round (in sT)
+    const int trows = TILE / R;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = 0; i0 < d.In; i0 += trows) {
+      const int rows = (int)std::min<int64_t>(trows, d.In - i0);
+      const int cnt = rows * R;
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = tid + q * kThreads;
+        v[q] = idx < cnt ? d.A[i0 * R + idx] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = tid + q * kThreads;
+        if (idx < cnt) sT[idx] = v[q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + q * kThreads;
+        if (idx < RR) {
+          const int a = idx / R, b = idx % R;
+          double s = acc[q];
+          for (int rr = 0; rr < rows; ++rr) s += sT[rr * R + a] * sT[rr * R + b];
+          acc[q] = s;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * kThreads;
+      if (idx < RR) sU[idx] = acc[q];
     }
     __syncthreads();
-    if (d.want_obj && tid == 0) {
-      double inner = 0.0;
-      for (int b = 0; b < nwg; ++b) inner += d.scal_part[b];
-      double nrm = 0.0;
-      for (int idx = 0; idx < R * R; ++idx) {
-        double h = 1.0;
-        for (int m = 0; m < d.N; ++m) h *= (m == d.n) ? sU[idx] : d.grams[(size_t)m * R * R + idx];
-        nrm += h;
-      }
-      *d.scalar_out = 0.5 * (*d.norm2 - 2.0 * inner + nrm);
-    }
-    if (tid == 0) atomicExch(d.counter, 0);
   }
+  if (d.want_obj) {
+    // f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1)
+    double ip2 = 0.0;
+    for (int b = tid; b < nwg; b += kThreads) ip2 += d.scal_part[b];
+    double h = 0.0;
+    for (int idx = tid; idx < R * R; idx += kThreads) {
+      double hh = 1.0;
+      for (int m = 0; m < d.N; ++m) hh *= (m == d.n) ? sU[idx] : d.grams[(size_t)m * R * R + idx];
+      h += hh;
+    }
+    const double inner = block_sum(ip2, sred);
+    const double nrm = block_sum(h, sred);
+    if (tid == 0) *d.scalar_out = 0.5 * (*d.norm2 - 2.0 * inner + nrm);
+  }
+  if (!d.normalize) {
+    for (int idx = tid; idx < R * R; idx += kThreads) d.grams[(size_t)d.n * R * R + idx] = sU[idx];
+  } else {
+    // eq. (10): lambda_r = (prod_m ||a_r^(m)||)^(1/N), norms from diag(Upsilon);
+    // a component with a zero column is left unchanged
+    if (tid < R) {
+      const int r = tid;
+      double nr[kMaxOrder];
+      bool ok = true;
+      double prod = 1.0;
+      for (int m = 0; m < d.N; ++m) {
+        const double g = (m == d.n) ? sU[r * R + r] : d.grams[(size_t)m * R * R + r * R + r];
+        nr[m] = sqrt(g);
+        ok = ok && (nr[m] > 0.0);
+        prod *= nr[m];
+      }
+      const double lam = pow(prod, 1.0 / d.N);
+      for (int m = 0; m < d.N; ++m) sc[m * kMaxRank + r] = ok ? lam / nr[m] : 1.0;
+    }
+    __syncthreads();
+    for (int m = 0; m < d.N; ++m) {
+      double* Am = d.Aall[m];
+      float* A32m = d.A32all[m];
+      const double* scm = sc + m * kMaxRank;
+      const int64_t cnt = d.dims[m] * R;
+      for (int64_t base = 0; base < cnt; base += 8 * kThreads) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t idx = base + tid + q * kThreads;
+          v[q] = idx < cnt ? Am[idx] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t idx = base + tid + q * kThreads;
+          if (idx < cnt) {
+            const double w = v[q] * scm[idx % R];
+            Am[idx] = w;
+            if (A32m) A32m[idx] = (float)w;
+          }
+        }
+      }
+      for (int idx = tid; idx < R * R; idx += kThreads) {
+        const int a = idx / R, b = idx % R;
+        const double g = (m == d.n) ? sU[idx] : d.grams[(size_t)m * R * R + idx];
+        d.grams[(size_t)m * R * R + idx] = g * scm[a] * scm[b];
+      }
+    }
+  }
+  if (tid == 0) atomicExch(d.counter, 0);
 }
 
 hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {

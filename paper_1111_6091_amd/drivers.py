@@ -7,8 +7,8 @@ Stopping rules (Section 6 of the paper uses the gradient measure g < 1e-10 with
 caps of 1e4 ALS iterations and 500 multilevel iterations; the workloads here
 stop on the relative fit change):
   * ALS / FP64 phase: |fit_k - fit_{k-1}| <= fit_tol * fit_k, fit = 1 - ||Z-[[A]]||/||Z||
-  * mixed form: FP32 sweeps until the exact fit changes by <= tol32 * fit per
-    sweep (checked every ``check`` sweeps), then FP64 sweeps as above.
+  * mixed form: FP32 sweeps until the mean per-sweep fit gain over a chunk of
+    sweeps is <= tol32 * fit, then FP64 sweeps as above.
 """
 from __future__ import annotations
 
@@ -77,19 +77,27 @@ def exact_fit(ctx, Z, A):
     return fit_from_f(float(f.item()), float(Z.norm2.item()))
 
 
-def mixed_solve(ctx, Z, A, tol32=1e-7, tol64=1e-12, check=4, max_sweeps=10000, chunk64=16):
-    """Mixed form: FP32-contraction sweeps, then FP64 refinement sweeps."""
+def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000, chunk64=16):
+    """Mixed form: FP32-contraction sweeps, then FP64 refinement sweeps.
+
+    The FP32 phase runs in chunks of ``chunk32`` sweeps and ends when the mean
+    per-sweep gain of the fused objective over a chunk is <= tol32 * fit (a
+    negative gain means the FP32 contractions have reached their noise floor).
+    The FP64 phase then runs until the per-sweep fit change is <= tol64 * fit.
+    """
+    torch = _torch()
+    norm2 = float(Z.norm2.item())
+    fh = torch.zeros(chunk32, dtype=torch.float64, device=Z.z64.device)
     res = SolveResult()
-    prev = exact_fit(ctx, Z, A)
     while res.sweeps < max_sweeps:
-        api.cp_als_sweep(ctx, Z, A, None, check, CP_SOLVE_CHOL, 10, True, CP_MIXED, None)
-        res.sweeps += check
-        res.sweeps32 += check
-        fit = exact_fit(ctx, Z, A)
-        res.fits.append(fit)
-        if abs(fit - prev) <= tol32 * check * abs(fit):
+        k = min(chunk32, max_sweeps - res.sweeps)
+        api.cp_als_sweep(ctx, Z, A, None, k, CP_SOLVE_CHOL, 10, True, CP_MIXED, fh)
+        fits = [fit_from_f(float(x), norm2) for x in fh[:k].cpu().numpy()]
+        res.fits.extend(fits)
+        res.sweeps += k
+        res.sweeps32 += k
+        if k >= 2 and (fits[-1] - fits[0]) / (k - 1) <= tol32 * abs(fits[-1]):
             break
-        prev = fit
     r64 = als_solve(ctx, Z, A, max_sweeps=max(1, max_sweeps - res.sweeps), fit_tol=tol64,
                     chunk=chunk64, prec=CP_FP64)
     res.sweeps64 = r64.sweeps

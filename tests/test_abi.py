@@ -64,6 +64,10 @@ def test_null_context_is_rejected_without_touching_the_gpu():
     assert lib.cp_sort(None, None, 3, ctypes.byref(f)) == INVALID
     assert lib.cp_norm2(None, ctypes.byref(z), None) == INVALID
     assert lib.cp_cast_f32(None, None, None, 0) == INVALID
+    ms = ctypes.c_double()
+    assert lib.cp_time_mttkrp(None, ctypes.byref(z), ctypes.byref(f), 0, 0, 1, ctypes.byref(ms)) == INVALID
+    assert lib.cp_profile_enable(None, 1) == INVALID
+    assert lib.cp_profile_read(None, None, None) == INVALID
     flags = ctypes.c_int32()
     assert lib.cp_get_status(None, ctypes.byref(flags)) == INVALID
     assert lib.cp_ctx_destroy(None) == INVALID
