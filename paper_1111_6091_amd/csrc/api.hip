@@ -33,7 +33,7 @@ struct cp_ctx_s {
   char* fixed = nullptr;
   int32_t* counters = nullptr;
   uint32_t* flags = nullptr;
-  double* chol = nullptr;
+  double* prep_out = nullptr;   // Gamma factor + column scales for the next update
   int32_t* chol_kind = nullptr;
   double* scal = nullptr;   // 64 scratch scalars
   // optional per-launch event timing
@@ -183,9 +183,9 @@ cp_status enqueue_epi(cp_ctx ctx, const EpiDesc& d) {
 }
 
 cp_status enqueue_gram(cp_ctx ctx, double* const* A, float* const* A32, const int64_t* dims, int N,
-                       int R, double* grams) {
+                       int R, double* grams, double* sigma = nullptr) {
   ProfScope ps(ctx, CP_PROF_GRAM);
-  HIPCHK(gram_launch(A, A32, dims, N, R, grams, ctx->stream));
+  HIPCHK(gram_launch(A, A32, dims, N, R, grams, ctx->stream, sigma));
   return CP_OK;
 }
 
@@ -216,6 +216,7 @@ int64_t epi_blocks(int64_t In) { return (In + epi_rows_per_wg() - 1) / epi_rows_
 // Everything one BNGS/ALS sweep needs, carved from the workspace.
 struct SweepWS {
   double* grams;
+  double* sigma;
   double* partial;
   double* gram_part;
   double* scal_part;
@@ -225,55 +226,91 @@ template <typename Carver>
 void carve_sweep(Carver& c, int N, int R, size_t partial, int64_t maxI, SweepWS* out) {
   const int64_t nwg = epi_blocks(maxI);
   out->grams = c.template take<double>((size_t)N * R * R);
+  out->sigma = c.template take<double>((size_t)N * R);
   out->partial = c.template take<double>(partial);
   out->gram_part = c.template take<double>((size_t)nwg * R * R);
   out->scal_part = c.template take<double>((size_t)std::max<int64_t>(nwg, 2048));
 }
 
-// One BNGS sweep over all modes (grams must hold Upsilon of the current A).
-cp_status enqueue_sweep(cp_ctx ctx, const int64_t* dims, int N, int R, const void* z, bool fp32,
-                        double* const* A, float* const* A32, double* const* F,
-                        const std::vector<MttkrpPlan>& plans, const SweepWS& w, cp_solver solver,
-                        int gs_iters, int normalize, double* f_slot, const double* norm2) {
-  PrepArgs prep{w.grams, ctx->chol, ctx->chol_kind, ctx->flags};
-  for (int n = 0; n < N; ++n) {
-    cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
-                                 (const float* const*)A32, plans[n], w.partial,
-                                 solver == CP_SOLVE_CHOL ? &prep : nullptr);
-    if (s != CP_OK) return s;
-    EpiDesc d{};
-    d.op = EPI_UPDATE;
-    d.solver = solver;
-    d.gs_iters = gs_iters;
-    d.R = R;
-    d.N = N;
-    d.n = n;
-    d.nsplit = plans[n].nsplit;
-    d.In = dims[n];
-    d.partial = w.partial;
-    d.F = F ? F[n] : nullptr;
-    d.A = A[n];
-    d.A32 = A32 ? A32[n] : nullptr;
-    d.grams = w.grams;
-    d.chol = ctx->chol;
-    d.chol_kind = ctx->chol_kind;
-    d.gram_part = w.gram_part;
-    d.scal_part = w.scal_part;
-    d.counter = ctx->counters + CNT_EPI;
-    d.flags = ctx->flags;
-    d.want_obj = (f_slot && n == N - 1) ? 1 : 0;
-    d.scalar_out = f_slot;
-    d.norm2 = norm2;
-    if (normalize && n == N - 1) {
-      d.normalize = 1;
-      for (int m = 0; m < N; ++m) {
-        d.Aall[m] = A[m];
-        d.A32all[m] = A32 ? A32[m] : nullptr;
-        d.dims[m] = dims[m];
+// `nsweeps` BNGS sweeps over all modes starting from the stored factors A.
+// Enqueues: Grams of A, then per mode an MTTKRP launch (whose workgroup 0 does
+// the sweep bookkeeping for the update) and the update, then one finalize.
+cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const void* z, bool fp32,
+                         double* const* A, float* const* A32, double* const* F,
+                         const std::vector<MttkrpPlan>& plans, const SweepWS& w, cp_solver solver,
+                         int gs_iters, int normalize, int nsweeps, double* f_hist,
+                         const double* norm2) {
+  if (nsweeps <= 0) return CP_OK;
+  TRY(enqueue_gram(ctx, A, A32, dims, N, R, w.grams, w.sigma));
+  auto base_args = [&](int n) {
+    PrepArgs pa{};
+    pa.N = N;
+    pa.n = n;
+    pa.R = R;
+    pa.grams = w.grams;
+    pa.sigma = w.sigma;
+    pa.out = ctx->prep_out;
+    pa.kind = ctx->chol_kind;
+    pa.flags = ctx->flags;
+    pa.solver = solver;
+    pa.normalize = normalize;
+    pa.norm2 = norm2;
+    pa.inner_part = w.scal_part;
+    pa.inner_count = (int32_t)epi_blocks(dims[N - 1]);
+    return pa;
+  };
+  for (int k = 0; k < nsweeps; ++k) {
+    for (int n = 0; n < N; ++n) {
+      PrepArgs pa = base_args(n);
+      if (k == 0 && n == 0) {
+        pa.p = -1;
+      } else {
+        pa.p = (n + N - 1) % N;
+        pa.Ap = A[pa.p];
+        pa.Ip = dims[pa.p];
       }
+      if (n == 0 && k > 0) {
+        pa.boundary = 1;
+        pa.f_slot = f_hist ? f_hist + (k - 1) : nullptr;
+      }
+      cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
+                                   (const float* const*)A32, plans[n], w.partial, &pa);
+      if (s != CP_OK) return s;
+      EpiDesc d{};
+      d.op = EPI_UPDATE;
+      d.solver = solver;
+      d.gs_iters = gs_iters;
+      d.R = R;
+      d.N = N;
+      d.n = n;
+      d.nsplit = plans[n].nsplit;
+      d.In = dims[n];
+      d.partial = w.partial;
+      d.F = F ? F[n] : nullptr;
+      d.A = A[n];
+      d.A32 = A32 ? A32[n] : nullptr;
+      d.grams = w.grams;
+      d.prep_out = ctx->prep_out;
+      d.kind = ctx->chol_kind;
+      d.scal_part = w.scal_part;
+      d.flags = ctx->flags;
+      d.want_obj = (f_hist && n == N - 1) ? 1 : 0;
+      TRY(enqueue_epi(ctx, d));
     }
-    TRY(enqueue_epi(ctx, d));
   }
+  PrepArgs fa = base_args(0);
+  fa.p = N - 1;
+  fa.Ap = A[N - 1];
+  fa.Ip = dims[N - 1];
+  fa.boundary = 1;
+  fa.f_slot = f_hist ? f_hist + (nsweeps - 1) : nullptr;
+  for (int m = 0; m < N; ++m) {
+    fa.A[m] = A[m];
+    fa.A32[m] = A32 ? A32[m] : nullptr;
+    fa.dims[m] = dims[m];
+  }
+  ProfScope ps(ctx, CP_PROF_NORMALIZE);
+  HIPCHK(finalize_launch(fa, ctx->stream));
   return CP_OK;
 }
 
@@ -294,7 +331,8 @@ cp_status cp_ctx_create(cp_ctx* out, void* hip_stream) {
     return CP_ERR_HIP;
   }
   const size_t fixed_bytes = align_up(kNumCounters * sizeof(int32_t)) + align_up(64) +
-                             align_up(kMaxRank * kMaxRank * sizeof(double)) + align_up(64) +
+                             align_up((kMaxRank * kMaxRank + 2 * kMaxRank) * sizeof(double)) +
+                             align_up(64) +
                              align_up(64 * sizeof(double));
   e = hipMalloc((void**)&ctx->fixed, fixed_bytes);
   if (e != hipSuccess) {
@@ -311,7 +349,7 @@ cp_status cp_ctx_create(cp_ctx* out, void* hip_stream) {
   Arena a(ctx->fixed);
   ctx->counters = a.take<int32_t>(kNumCounters);
   ctx->flags = a.take<uint32_t>(16);
-  ctx->chol = a.take<double>(kMaxRank * kMaxRank);
+  ctx->prep_out = a.take<double>(kMaxRank * kMaxRank + 2 * kMaxRank);
   ctx->chol_kind = a.take<int32_t>(16);
   ctx->scal = a.take<double>(64);
   *out = ctx;
@@ -436,18 +474,12 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
   Arena ar(ctx->ws);
   carve_sweep(ar, N, R, part, max_dim(Z->dims, N), &w);
-  float* const* a32 = A->a32;
   bool have32 = true;
   for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
-  TRY(enqueue_gram(ctx, A->a, have32 ? a32 : nullptr, Z->dims, N, R, w.grams));
-  for (int k = 0; k < nsweeps; ++k) {
-    s = enqueue_sweep(ctx, Z->dims, N, R, z, mixed, A->a, have32 ? A->a32 : nullptr,
-                      F ? F->a : nullptr, plans, w, solver, gs_iters, normalize,
-                      f_hist ? f_hist + k : nullptr, Z->norm2);
-    if (s != CP_OK) return s;
-  }
-  return CP_OK;
+  return enqueue_sweeps(ctx, Z->dims, N, R, z, mixed, A->a, have32 ? A->a32 : nullptr,
+                        F ? F->a : nullptr, plans, w, solver, gs_iters, normalize, nsweeps, f_hist,
+                        Z->norm2);
 }
 
 cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t exact,
@@ -754,21 +786,16 @@ struct FasRun {
   double* partial;
   double* gram_part;
   double* scal_part;
+  double* sigma;
 };
 
 cp_status fas_relax(FasRun& r, int l, int times) {
   cp_ctx ctx = r.ctx;
   FasLevel& L = r.lv[l];
-  if (times <= 0) return CP_OK;
-  TRY(enqueue_gram(ctx, L.A, L.has32 ? L.A32 : nullptr, L.dims, r.N, r.R, L.grams));
-  SweepWS w{L.grams, r.partial, r.gram_part, r.scal_part};
-  for (int k = 0; k < times; ++k) {
-    cp_status s = enqueue_sweep(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A,
-                                L.has32 ? L.A32 : nullptr, l == 0 ? nullptr : L.F, L.plans, w,
-                                CP_SOLVE_GS, r.p.gs_iters, l == 0 ? 1 : 0, nullptr, nullptr);
-    if (s != CP_OK) return s;
-  }
-  return CP_OK;
+  SweepWS w{L.grams, r.sigma, r.partial, r.gram_part, r.scal_part};
+  return enqueue_sweeps(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A, L.has32 ? L.A32 : nullptr,
+                        l == 0 ? nullptr : L.F, L.plans, w, CP_SOLVE_GS, r.p.gs_iters,
+                        l == 0 ? 1 : 0, times, nullptr, nullptr);
 }
 
 // H^(n)(A) = A^(n) Gamma^(n) - Z_(n) Phi^(n) for every mode of level l.
@@ -861,7 +888,8 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
       (p.ic_rule != 0 && p.ic_rule != 1))
     return set_err(ctx, CP_ERR_INVALID, "cp_fas_vcycle: bad parameters");
   const int R = A->rank;
-  FasRun r{ctx, N, R, nlevels, mixed, p, std::vector<FasLevel>(nlevels), nullptr, nullptr, nullptr};
+  FasRun r{ctx, N, R, nlevels, mixed, p, std::vector<FasLevel>(nlevels), nullptr, nullptr, nullptr,
+           nullptr};
   bool have32 = true;
   for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
   size_t maxpart = 0;
@@ -898,7 +926,8 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
     const int64_t nwg = epi_blocks(maxI);
     double* gp = c.template take<double>((size_t)nwg * R * R);
     double* sp = c.template take<double>((size_t)std::max<int64_t>(nwg, 2048));
-    if (real) { r.partial = part; r.gram_part = gp; r.scal_part = sp; }
+    double* sg = c.template take<double>((size_t)N * R);
+    if (real) { r.partial = part; r.gram_part = gp; r.scal_part = sp; r.sigma = sg; }
   };
   Sizer sz;
   carve(sz, false);

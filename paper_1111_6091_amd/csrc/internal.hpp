@@ -32,6 +32,30 @@ template <> __device__ __forceinline__ constexpr int mfma_row<float>(int g, int 
 //   kind 2 (n == 1): GEMM rows = i1, contraction over i0, Hadamard weight per stripe
 //   kind 3 (n >= 2): GEMM rows = i1, contraction over i0, Hadamard-reduce of the
 //                    rows with A^(1) and the stripe weight into output row s_n
+// Per-mode bookkeeping done by the extra first workgroup of an MTTKRP launch
+// (or by the finalize kernel at the end of a call); see sweep.hpp.
+struct PrepArgs {
+  int32_t N, n, R;
+  double* grams;            // [N][R][R] Grams of the stored factors
+  double* sigma;            // [N][R] pending column scales: normalized = sigma (.) stored
+  double* out;              // [R*R + 2R]: factor / pseudoinverse / Gamma, column scale, sigma^(n)
+  int32_t* kind;            // 0 Cholesky factor, 1 pseudoinverse, 2 Gamma (Gauss-Seidel)
+  uint32_t* flags;
+  int32_t solver;
+  int32_t p;                // mode whose Gram is recomputed from its factor (-1: none)
+  const double* Ap;
+  int64_t Ip;
+  int32_t boundary;         // a sweep has just ended: fused objective + normalization scales
+  int32_t normalize;
+  double* f_slot;           // where that sweep's f goes (NULL: not requested)
+  const double* norm2;
+  const double* inner_part; // per-block <A^(N), M^(N)> of the last update
+  int32_t inner_count;
+  double* A[kMaxOrder];     // finalize: factors to scale
+  float* A32[kMaxOrder];
+  int64_t dims[kMaxOrder];
+};
+
 struct MttkrpDesc {
   const void* z;                  // tensor (T*)
   const void* ak;                 // factor of the contracted mode, in T (B operand)
@@ -55,20 +79,8 @@ struct MttkrpDesc {
   int32_t kchunk;                 // contraction length per piece (multiple of 16)
   int32_t rgroups;                // kind 3: number of row groups over I1
   int64_t rest_count;             // kind 3: number of stripes per output value
-  // optional: an extra last workgroup factors Gamma^(n) for the update that follows
-  int32_t prep;
-  const double* grams;            // [N][R][R]
-  double* chol;                   // [R][R] output (L or pseudoinverse)
-  int32_t* chol_kind;             // 0 = L, 1 = pseudoinverse
-  uint32_t* flags;
-};
-
-// Gamma^(n) factorization request carried by an MTTKRP launch
-struct PrepArgs {
-  const double* grams;
-  double* chol;
-  int32_t* chol_kind;
-  uint32_t* flags;
+  int32_t prep;                   // 1: workgroup 0 runs sweep_prep(pa) instead of streaming
+  PrepArgs pa;
 };
 
 // planner + launcher (mttkrp.hip)
@@ -106,38 +118,29 @@ struct EpiDesc {
   float* A32;                 // optional shadow
   double* outbuf;             // EPI_STORE_M / EPI_H target
   double* grams;              // [N][R][R]  (Upsilon of each mode)
-  const double* chol;         // [R][R] factor of Gamma^(n) (written by prep kernel) or pinv
-  const int32_t* chol_kind;   // 0 = Cholesky L, 1 = pseudoinverse matrix, 2 = unusable
-  double* gram_part;          // [nwg][R][R] workspace
+  const double* prep_out;     // EPI_UPDATE: [R*R + 2R] from sweep_prep
+  const int32_t* kind;        // EPI_UPDATE: 0 Cholesky factor, 1 pseudoinverse, 2 Gamma (GS)
   double* scal_part;          // [nwg] workspace
   int32_t* counter;           // last-block counter (zero between launches)
   double* scalar_out;         // objective: f_hist slot; grad: accumulator
   const double* norm2;        // ||Z||^2 (device)
   uint32_t* flags;
-  int32_t want_obj;           // EPI_UPDATE: write fused f into scalar_out
+  int32_t want_obj;           // EPI_UPDATE: per-block <A^(n), M^(n)> into scal_part
   int32_t accumulate;         // EPI_GRAD: add to scalar_out instead of overwrite
-  // EPI_UPDATE of the last mode: apply eq. (10) to every factor in the last block
-  int32_t normalize;
-  double* Aall[kMaxOrder];
-  float* A32all[kMaxOrder];
-  int64_t dims[kMaxOrder];
 };
 
 hipError_t epi_launch(const EpiDesc& d, hipStream_t st);
 int epi_rows_per_wg();
 
-// Gamma^(n) factorization for the next update (one workgroup)
-hipError_t gamma_prep_launch(const double* grams, int N, int n, int R, double* chol,
-                             int32_t* chol_kind, uint32_t* flags, int32_t solver,
-                             hipStream_t st);
+// End of a sweep sequence: Gram of the last mode, fused objective, and the
+// pending normalization applied to the stored factors (one workgroup).
+hipError_t finalize_launch(const PrepArgs& a, hipStream_t st);
 
-// Grams of every mode at fixed A; optionally refresh FP32 shadows
+// Grams of every mode at fixed A; optionally refresh FP32 shadows and reset the
+// pending normalization scales (sigma, N x R) to 1
 hipError_t gram_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
-                       double* grams, hipStream_t st);
+                       double* grams, hipStream_t st, double* sigma = nullptr);
 
-// Normalization eq. (10) using the diagonals of the Grams; rescales Grams too
-hipError_t normalize_launch(double* const* A, float* const* A32, const int64_t* dims, int N,
-                            int R, double* grams, hipStream_t st);
 
 // exact residual ||Z - [[A]]||^2 / 2
 hipError_t residual_launch(const double* z, const int64_t* dims, int N, int R,

@@ -14,6 +14,7 @@
 //   D[m = mfma_row<T>(l/16, v)][n = l%16], v = 0..3 (see internal.hpp).
 #include "internal.hpp"
 #include "smallla.hpp"
+#include "sweep.hpp"
 
 namespace cpamg {
 
@@ -78,13 +79,15 @@ __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, 
   return w;
 }
 
-constexpr int kSmem = 4096;   // doubles of LDS per workgroup (32 KB)
+constexpr int kSmem = kPrepSmem;   // doubles of LDS per workgroup (40 KB)
+static_assert(kSmem >= 4096, "reduction buffers need 4096 doubles");
 
-// The extra last workgroup of a launch factors Gamma^(n) for the R x R update
-// that follows the MTTKRP, concurrently with the streaming workgroups.
+// Workgroup 0 of a launch with prep set does the sweep bookkeeping for the
+// update that follows (sweep.hpp), concurrently with the streaming workgroups;
+// it is dispatched first, so it is resident from the start.
 __device__ __forceinline__ bool prep_block(const MttkrpDesc& d, double* smem) {
-  if (!d.prep || blockIdx.x != gridDim.x - 1) return false;
-  gamma_prepare(d.grams, d.N, d.n, d.R, d.chol, d.chol_kind, d.flags, smem);
+  if (!d.prep || blockIdx.x != 0) return false;
+  sweep_prep(d.pa, smem, false);
   return true;
 }
 
@@ -102,8 +105,9 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
   if (prep_block(d, smem)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g4 = lane >> 4;
-  const int grp = blockIdx.x % d.ngroups;
-  const int split = blockIdx.x / d.ngroups;
+  const int bid = blockIdx.x - d.prep;
+  const int grp = bid % d.ngroups;
+  const int split = bid / d.ngroups;
   const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
   const T* __restrict__ ak = reinterpret_cast<const T*>(d.ak);
   const int R = d.R;
@@ -206,8 +210,9 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   if (prep_block(d, smem)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, g4 = lane >> 4;
-  const int grp = blockIdx.x % d.ngroups;
-  const int split = blockIdx.x / d.ngroups;
+  const int bid = blockIdx.x - d.prep;
+  const int grp = bid % d.ngroups;
+  const int split = bid / d.ngroups;
   const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
   const T* __restrict__ ak = reinterpret_cast<const T*>(d.ak);
   const int R = d.R;
@@ -429,10 +434,7 @@ hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n,
   MttkrpDesc d{};
   if (prep) {
     d.prep = 1;
-    d.grams = prep->grams;
-    d.chol = prep->chol;
-    d.chol_kind = prep->chol_kind;
-    d.flags = prep->flags;
+    d.pa = *prep;
   }
   d.z = z;
   d.N = N;

@@ -1,0 +1,219 @@
+// Per-mode bookkeeping of an ALS / BNGS sweep, done by one workgroup.
+//
+// Normalization eq. (10) is carried lazily: the library keeps, per mode m, a
+// column scale sigma^(m) with  (normalized factor) = sigma^(m) (.) (stored
+// factor), and every update works in normalized coordinates.  This workgroup
+// (the extra first workgroup of each MTTKRP launch, hidden under the tensor
+// stream, or the finalize kernel at the end of a call) refreshes the Gram of
+// the factor updated last, closes a sweep (fused objective, new normalization
+// scales) and prepares Gamma^(n) (Cholesky factor, pseudoinverse, or Gamma
+// itself for Gauss-Seidel) together with the column scales of the update.
+#pragma once
+
+#include "internal.hpp"
+#include "smallla.hpp"
+
+namespace cpamg {
+
+constexpr int kPrepSmem = 5 * kMaxRank * kMaxRank;   // doubles of LDS needed
+
+// Block-wide sum of one double per thread; result valid in every thread.
+__device__ inline double wg_sum(double v, double* sred) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) / 64;
+  for (int w = 0; w < nw; ++w) s += sred[w];
+  return s;
+}
+
+// U (LDS, R*R) = A^T A for A (I x R, global), staged through `tile` (2048 doubles).
+__device__ inline void gram_into(const double* __restrict__ A, int64_t I, int R, double* U,
+                                 double* tile) {
+  constexpr int TILE = 2048;
+  const int tid = threadIdx.x;
+  const int trows = TILE / R;
+  const int RR = R * R;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = 0; i0 < I; i0 += trows) {
+    const int rows = (int)((I - i0) < trows ? (I - i0) : trows);
+    const int cnt = rows * R;
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + q * kThreads;
+      v[q] = idx < cnt ? A[i0 * R + idx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + q * kThreads;
+      if (idx < cnt) tile[idx] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * kThreads;
+      if (idx < RR) {
+        const int a = idx / R, b = idx % R;
+        double s = acc[q];
+        for (int rr = 0; rr < rows; ++rr) s += tile[rr * R + a] * tile[rr * R + b];
+        acc[q] = s;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + q * kThreads;
+    if (idx < RR) U[idx] = acc[q];
+  }
+  __syncthreads();
+}
+
+// Factor Gamma (in G, LDS) for the ALS update: L (kind 0) or the pseudoinverse
+// (kind 1) is written to out[0..R*R).  S, V, P: LDS scratch of R*R each.
+__device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind, uint32_t* flags,
+                                    double* S, double* V, double* P) {
+  for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) P[idx] = G[idx];
+  __syncthreads();
+  const int fail = wg_cholesky(G, R);
+  __syncthreads();
+  if (!fail) {
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = G[idx];
+    if (threadIdx.x == 0) *kind = 0;
+  } else {
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) G[idx] = P[idx];
+    __syncthreads();
+    const int zero = wg_pinv(G, R, S, V, P);
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = P[idx];
+    if (threadIdx.x == 0) {
+      *kind = 1;
+      atomicOr(flags, zero ? (CP_FLAG_PINV_FALLBACK | CP_FLAG_NOT_SPD) : CP_FLAG_PINV_FALLBACK);
+    }
+  }
+  __syncthreads();
+}
+
+// The bookkeeping step; smem: kPrepSmem doubles of LDS.  With finalize set,
+// the pending scales are applied to the stored factors and reset instead of
+// preparing an update.
+__device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
+  __shared__ double sred[8];
+  const int R = a.R, N = a.N, n = a.n, RR = R * R, tid = threadIdx.x;
+  double* G = smem;
+  double* S = smem + kMaxRank * kMaxRank;
+  double* V = smem + 2 * kMaxRank * kMaxRank;
+  double* P = smem + 3 * kMaxRank * kMaxRank;
+  double* U = smem + 4 * kMaxRank * kMaxRank;
+  double* sS = S;   // sigma (N x R) lives in S until the factorization needs S
+  double* tile = V; // 2048 doubles spanning V and P
+  for (int idx = tid; idx < N * R; idx += kThreads) sS[idx] = a.sigma[idx];
+  if (a.p >= 0) gram_into(a.Ap, a.Ip, R, U, tile);
+  __syncthreads();
+  if (a.p >= 0 && tid < R) sS[a.p * R + tid] = 1.0;   // the updated factor is normalized
+  __syncthreads();
+  auto ups = [&](int m, int idx) -> double {
+    return m == a.p ? U[idx] : a.grams[(size_t)m * RR + idx];
+  };
+  if (a.boundary) {
+    if (a.f_slot) {
+      // f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1), normalized coordinates
+      double ip = 0.0;
+      for (int b = tid; b < a.inner_count; b += kThreads) ip += a.inner_part[b];
+      double h = 0.0;
+      for (int idx = tid; idx < RR; idx += kThreads) {
+        const int r = idx / R, c = idx % R;
+        double hh = 1.0;
+        for (int m = 0; m < N; ++m) hh *= sS[m * R + r] * sS[m * R + c] * ups(m, idx);
+        h += hh;
+      }
+      const double inner = wg_sum(ip, sred);
+      const double nrm = wg_sum(h, sred);
+      if (tid == 0) *a.f_slot = 0.5 * (*a.norm2 - 2.0 * inner + nrm);
+    }
+    if (a.normalize) {
+      // eq. (10): lambda_r = (prod_m ||a_r^(m)||)^(1/N); a component with a
+      // zero column is left unchanged
+      __syncthreads();
+      if (tid < R) {
+        const int r = tid;
+        double nr[kMaxOrder];
+        bool ok = true;
+        double prod = 1.0;
+        for (int m = 0; m < N; ++m) {
+          nr[m] = sS[m * R + r] * sqrt(ups(m, r * R + r));
+          ok = ok && (nr[m] > 0.0);
+          prod *= nr[m];
+        }
+        const double lam = pow(prod, 1.0 / N);
+        if (ok)
+          for (int m = 0; m < N; ++m) sS[m * R + r] *= lam / nr[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (finalize) {
+    // apply the scales to the stored factors (and shadows) and to the Grams
+    for (int m = 0; m < N; ++m) {
+      double* Am = a.A[m];
+      float* A32m = a.A32[m];
+      const double* sm = sS + m * R;
+      const int64_t cnt = a.dims[m] * R;
+      for (int64_t base = 0; base < cnt; base += 8 * kThreads) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t idx = base + tid + q * kThreads;
+          v[q] = idx < cnt ? Am[idx] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t idx = base + tid + q * kThreads;
+          if (idx < cnt && sm[idx % R] != 1.0) {
+            const double w = v[q] * sm[idx % R];
+            Am[idx] = w;
+            if (A32m) A32m[idx] = (float)w;
+          }
+        }
+      }
+      for (int idx = tid; idx < RR; idx += kThreads) {
+        const int r = idx / R, c = idx % R;
+        a.grams[(size_t)m * RR + idx] = sm[r] * sm[c] * ups(m, idx);
+      }
+    }
+    for (int idx = tid; idx < N * R; idx += kThreads) a.sigma[idx] = 1.0;
+    return;
+  }
+  if (a.p >= 0)
+    for (int idx = tid; idx < RR; idx += kThreads) a.grams[(size_t)a.p * RR + idx] = U[idx];
+  for (int idx = tid; idx < N * R; idx += kThreads) a.sigma[idx] = sS[idx];
+  // Gamma^(n) in normalized coordinates, column scale of M^(n), sigma^(n)
+  for (int idx = tid; idx < RR; idx += kThreads) {
+    const int r = idx / R, c = idx % R;
+    double g = 1.0;
+    for (int m = 0; m < N; ++m)
+      if (m != n) g *= sS[m * R + r] * sS[m * R + c] * ups(m, idx);
+    G[idx] = g;
+  }
+  if (tid < R) {
+    double c = 1.0;
+    for (int m = 0; m < N; ++m)
+      if (m != n) c *= sS[m * R + tid];
+    a.out[RR + tid] = c;
+    a.out[RR + R + tid] = sS[n * R + tid];
+  }
+  __syncthreads();
+  if (a.solver == CP_SOLVE_GS) {
+    for (int idx = tid; idx < RR; idx += kThreads) a.out[idx] = G[idx];
+    if (tid == 0) *a.kind = 2;
+    __syncthreads();
+    return;
+  }
+  gamma_factor(G, R, a.out, a.kind, a.flags, S, V, P);
+}
+
+}  // namespace cpamg

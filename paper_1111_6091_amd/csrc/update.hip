@@ -4,6 +4,7 @@
 
 #include "internal.hpp"
 #include "smallla.hpp"
+#include "sweep.hpp"
 
 namespace cpamg {
 
@@ -136,26 +137,26 @@ __device__ inline double wave_gs(double b, double x, const double* G, int R, int
 __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
   __shared__ double sG[kMaxRank * kMaxRank];
   __shared__ double sM[EPI_ROWS * LDP];
-  __shared__ double sX[EPI_ROWS * LDP];
   __shared__ double sT[16 * EPI_ROWS * kMaxRank];
-  __shared__ double sU[kMaxRank * kMaxRank];
-  __shared__ double sc[kMaxOrder * kMaxRank];
+  __shared__ double sC[2 * kMaxRank];
   __shared__ double sred[8];
   __shared__ int s_flag;
   const int R = d.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * EPI_ROWS;
   const int nrows = (int)std::min<int64_t>(EPI_ROWS, d.In - row0);
-  const bool chol = (d.op == EPI_UPDATE && d.solver == CP_SOLVE_CHOL);
   int kind = 0;
-  if (d.op != EPI_STORE_M) {
-    if (chol) {
-      for (int idx = tid; idx < R * R; idx += kThreads) sG[idx] = d.chol[idx];
-      kind = *d.chol_kind;
-      __syncthreads();
-    } else {
-      hadamard_gamma(d.grams, d.N, d.n, R, sG);
+  if (d.op == EPI_UPDATE) {
+    // Gamma^(n) prepared by the MTTKRP launch: factor / pseudoinverse / Gamma,
+    // then the column scale of M^(n) and sigma^(n) (normalized coordinates)
+    for (int idx = tid; idx < R * R + 2 * R; idx += kThreads) {
+      const double v = d.prep_out[idx];
+      if (idx < R * R) sG[idx] = v;
+      else sC[idx - R * R] = v;
     }
+    kind = *d.kind;
+  } else if (d.op != EPI_STORE_M) {
+    hadamard_gamma(d.grams, d.N, d.n, R, sG);
   }
   reduce_partials(d, row0, nrows, sM, sT);
 
@@ -193,137 +194,30 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
     return;
   }
 
-  // ---- EPI_UPDATE: wave w solves row w ------------------------------------
+  // ---- EPI_UPDATE: wave w solves row w in normalized coordinates -----------
+  double ip = 0.0;
   if (wave < nrows) {
     const int64_t row = row0 + wave;
-    const double b = (lane < R) ? sM[wave * LDP + lane] + (d.F ? d.F[row * R + lane] : 0.0) : 0.0;
+    const double m = (lane < R) ? sC[lane] * sM[wave * LDP + lane] : 0.0;
+    const double b = (lane < R) ? m + (d.F ? d.F[row * R + lane] : 0.0) : 0.0;
     double x;
-    if (chol) {
+    if (kind != 2) {
       x = wave_chol_solve(b, sG, R, kind, lane);
     } else {
-      const double x0 = (lane < R) ? d.A[row * R + lane] : 0.0;
+      const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
       x = wave_gs(b, x0, sG, R, d.gs_iters, lane);
     }
     if (lane < R) {
       if (!isfinite(x)) atomicOr(d.flags, CP_FLAG_NONFINITE);
-      sX[wave * LDP + lane] = x;
       d.A[row * R + lane] = x;
       if (d.A32) d.A32[row * R + lane] = (float)x;
+      ip = x * m;
     }
-  }
-  __syncthreads();
-  double ip = 0.0;
-  if (d.want_obj && tid < nrows * R) ip = sX[(tid / R) * LDP + tid % R] * sM[(tid / R) * LDP + tid % R];
-  const double ipb = block_sum(ip, sred);
-  if (tid == 0) d.scal_part[blockIdx.x] = ipb;
-  if (!arrive_last(d.counter, &s_flag)) return;
-
-  // ---- last block: Upsilon^(n) = A^T A from the finished factor, fused
-  // objective, normalization -------------------------------------------------
-  const int nwg = gridDim.x;
-  {
-    const int RR = R * R;
-    constexpr int TILE = 2048;   // doubles of A staged per round (in sT)
-    const int trows = TILE / R;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i0 = 0; i0 < d.In; i0 += trows) {
-      const int rows = (int)std::min<int64_t>(trows, d.In - i0);
-      const int cnt = rows * R;
-      double v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = tid + q * kThreads;
-        v[q] = idx < cnt ? d.A[i0 * R + idx] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = tid + q * kThreads;
-        if (idx < cnt) sT[idx] = v[q];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int idx = tid + q * kThreads;
-        if (idx < RR) {
-          const int a = idx / R, b = idx % R;
-          double s = acc[q];
-          for (int rr = 0; rr < rows; ++rr) s += sT[rr * R + a] * sT[rr * R + b];
-          acc[q] = s;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * kThreads;
-      if (idx < RR) sU[idx] = acc[q];
-    }
-    __syncthreads();
   }
   if (d.want_obj) {
-    // f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1)
-    double ip2 = 0.0;
-    for (int b = tid; b < nwg; b += kThreads) ip2 += d.scal_part[b];
-    double h = 0.0;
-    for (int idx = tid; idx < R * R; idx += kThreads) {
-      double hh = 1.0;
-      for (int m = 0; m < d.N; ++m) hh *= (m == d.n) ? sU[idx] : d.grams[(size_t)m * R * R + idx];
-      h += hh;
-    }
-    const double inner = block_sum(ip2, sred);
-    const double nrm = block_sum(h, sred);
-    if (tid == 0) *d.scalar_out = 0.5 * (*d.norm2 - 2.0 * inner + nrm);
+    const double ipb = block_sum(ip, sred);
+    if (tid == 0) d.scal_part[blockIdx.x] = ipb;
   }
-  if (!d.normalize) {
-    for (int idx = tid; idx < R * R; idx += kThreads) d.grams[(size_t)d.n * R * R + idx] = sU[idx];
-  } else {
-    // eq. (10): lambda_r = (prod_m ||a_r^(m)||)^(1/N), norms from diag(Upsilon);
-    // a component with a zero column is left unchanged
-    if (tid < R) {
-      const int r = tid;
-      double nr[kMaxOrder];
-      bool ok = true;
-      double prod = 1.0;
-      for (int m = 0; m < d.N; ++m) {
-        const double g = (m == d.n) ? sU[r * R + r] : d.grams[(size_t)m * R * R + r * R + r];
-        nr[m] = sqrt(g);
-        ok = ok && (nr[m] > 0.0);
-        prod *= nr[m];
-      }
-      const double lam = pow(prod, 1.0 / d.N);
-      for (int m = 0; m < d.N; ++m) sc[m * kMaxRank + r] = ok ? lam / nr[m] : 1.0;
-    }
-    __syncthreads();
-    for (int m = 0; m < d.N; ++m) {
-      double* Am = d.Aall[m];
-      float* A32m = d.A32all[m];
-      const double* scm = sc + m * kMaxRank;
-      const int64_t cnt = d.dims[m] * R;
-      for (int64_t base = 0; base < cnt; base += 8 * kThreads) {
-        double v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int64_t idx = base + tid + q * kThreads;
-          v[q] = idx < cnt ? Am[idx] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int64_t idx = base + tid + q * kThreads;
-          if (idx < cnt) {
-            const double w = v[q] * scm[idx % R];
-            Am[idx] = w;
-            if (A32m) A32m[idx] = (float)w;
-          }
-        }
-      }
-      for (int idx = tid; idx < R * R; idx += kThreads) {
-        const int a = idx / R, b = idx % R;
-        const double g = (m == d.n) ? sU[idx] : d.grams[(size_t)m * R * R + idx];
-        d.grams[(size_t)m * R * R + idx] = g * scm[a] * scm[b];
-      }
-    }
-  }
-  if (tid == 0) atomicExch(d.counter, 0);
 }
 
 hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {
@@ -333,19 +227,13 @@ hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void gamma_prep_kernel(const double* grams, int N, int n,
-                                                               int R, double* chol,
-                                                               int32_t* kind, uint32_t* flags) {
-  __shared__ double lds[4 * kMaxRank * kMaxRank];
-  gamma_prepare(grams, N, n, R, chol, kind, flags, lds);
+__global__ __launch_bounds__(kThreads) void finalize_kernel(PrepArgs a) {
+  __shared__ double smem[kPrepSmem];
+  sweep_prep(a, smem, true);
 }
 
-hipError_t gamma_prep_launch(const double* grams, int N, int n, int R, double* chol,
-                             int32_t* chol_kind, uint32_t* flags, int32_t solver,
-                             hipStream_t st) {
-  (void)solver;
-  hipLaunchKernelGGL(gamma_prep_kernel, dim3(1), dim3(kThreads), 0, st, grams, N, n, R, chol,
-                     chol_kind, flags);
+hipError_t finalize_launch(const PrepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
@@ -357,7 +245,8 @@ struct GramArgs {
   int64_t dims[kMaxOrder];
 };
 
-__global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, double* grams) {
+__global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, double* grams,
+                                                        double* sigma) {
   __shared__ double tile[64 * LDP];
   const int m = blockIdx.x;
   const double* A = g.A[m];
@@ -387,63 +276,18 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, doubl
     const int idx = threadIdx.x + q * kThreads;
     if (idx < R * R) grams[(size_t)m * R * R + idx] = acc[q];
   }
+  if (sigma && threadIdx.x < R) sigma[m * R + threadIdx.x] = 1.0;
 }
 
 hipError_t gram_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
-                       double* grams, hipStream_t st) {
+                       double* grams, hipStream_t st, double* sigma) {
   GramArgs g{};
   for (int m = 0; m < N; ++m) {
     g.A[m] = A[m];
     g.A32[m] = A32 ? A32[m] : nullptr;
     g.dims[m] = dims[m];
   }
-  hipLaunchKernelGGL(gram_kernel, dim3(N), dim3(kThreads), 0, st, g, R, grams);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Normalization eq. (10): lambda_r = (prod_n ||a_r^(n)||)^(1/N) with the column
-// norms taken from diag(Upsilon^(n)); components with a zero column are kept.
-__global__ __launch_bounds__(kThreads) void normalize_kernel(GramArgs g, int N, int R,
-                                                             double* grams) {
-  __shared__ double sc[kMaxOrder * kMaxRank];
-  if (threadIdx.x < R) {
-    const int r = threadIdx.x;
-    double nr[kMaxOrder];
-    bool ok = true;
-    double prod = 1.0;
-    for (int m = 0; m < N; ++m) {
-      nr[m] = sqrt(grams[(size_t)m * R * R + r * R + r]);
-      ok = ok && (nr[m] > 0.0);
-      prod *= nr[m];
-    }
-    const double lam = pow(prod, 1.0 / N);
-    for (int m = 0; m < N; ++m) sc[m * kMaxRank + r] = ok ? lam / nr[m] : 1.0;
-  }
-  __syncthreads();
-  for (int m = 0; m < N; ++m) {
-    const int64_t cnt = g.dims[m] * R;
-    for (int64_t idx = threadIdx.x; idx < cnt; idx += kThreads) {
-      const double v = g.A[m][idx] * sc[m * kMaxRank + (int)(idx % R)];
-      g.A[m][idx] = v;
-      if (g.A32[m]) g.A32[m][idx] = (float)v;
-    }
-    for (int idx = threadIdx.x; idx < R * R; idx += kThreads) {
-      const int a = idx / R, b = idx % R;
-      grams[(size_t)m * R * R + idx] *= sc[m * kMaxRank + a] * sc[m * kMaxRank + b];
-    }
-  }
-}
-
-hipError_t normalize_launch(double* const* A, float* const* A32, const int64_t* dims, int N,
-                            int R, double* grams, hipStream_t st) {
-  GramArgs g{};
-  for (int m = 0; m < N; ++m) {
-    g.A[m] = A[m];
-    g.A32[m] = A32 ? A32[m] : nullptr;
-    g.dims[m] = dims[m];
-  }
-  hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(kThreads), 0, st, g, N, R, grams);
+  hipLaunchKernelGGL(gram_kernel, dim3(N), dim3(kThreads), 0, st, g, R, grams, sigma);
   return hipGetLastError();
 }
 
