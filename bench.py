@@ -46,6 +46,7 @@ def parse():
     p.add_argument("--no-equal-fit", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-tune", action="store_true")
     return p.parse_args()
 
 
@@ -83,6 +84,17 @@ def main():
         return api.DeviceFactors.from_numpy(ctx, A0, fp32=True)
 
     fh = torch.zeros(max(K, W, 1), dtype=torch.float64, device="cuda")
+
+    # launch-configuration autotuner (before any timed region)
+    plans = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        At = fresh()
+        for prec in (CP_MIXED, CP_FP64):
+            api.cp_autotune(ctx, Zd, At, prec, 10)
+        torch.cuda.synchronize()
+        plans = api.cp_plans_export(ctx)
+        log(f"autotune {time.perf_counter() - t0:.2f} s:\n{plans}")
 
     def timed(prec, steps, warm):
         A = fresh()
@@ -199,6 +211,7 @@ def main():
         "roofline": roofline,
         "per_sweep_us_event_bracketed": breakdown,
         "equal_fit": equal_fit,
+        "tuned_plans": plans.strip().splitlines() if plans else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

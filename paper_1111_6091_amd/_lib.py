@@ -79,6 +79,8 @@ SIGNATURES = {
                       ctypes.POINTER(CpFasParams), c_i32],
     "cp_sort": [c_vp, ctypes.POINTER(c_i64), c_i32, ctypes.POINTER(CpFactors)],
     "cp_profile_enable": [c_vp, c_i32],
+    "cp_autotune": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_i32],
+    "cp_plans_import": [c_vp, ctypes.c_char_p],
     "cp_time_mttkrp": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_i32,
                        c_i32, ctypes.POINTER(ctypes.c_double)],
     "cp_profile_read": [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i32)],
@@ -103,9 +105,11 @@ def load(path: str = LIB_PATH):
         fn.restype = c_i32
     lib.cp_last_error.argtypes = [c_vp]
     lib.cp_last_error.restype = ctypes.c_char_p
+    lib.cp_plans_export.argtypes = [c_vp]
+    lib.cp_plans_export.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
 
 def exported_names():
-    return list(SIGNATURES) + ["cp_last_error"]
+    return list(SIGNATURES) + ["cp_last_error", "cp_plans_export"]

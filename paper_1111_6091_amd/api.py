@@ -261,6 +261,19 @@ def cp_time_mttkrp(ctx, Z, A, n, prec=CP_FP64, reps=20):
     return ms.value
 
 
+def cp_autotune(ctx, Z, A, prec=CP_FP64, reps=20):
+    zs, fs = Z.struct(), A.struct()
+    ctx.check(ctx._lib.cp_autotune(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), prec, reps))
+
+
+def cp_plans_export(ctx):
+    return ctx._lib.cp_plans_export(ctx.handle).decode()
+
+
+def cp_plans_import(ctx, text):
+    ctx.check(ctx._lib.cp_plans_import(ctx.handle, text.encode()))
+
+
 def cp_sort(ctx, A):
     dims = (ctypes.c_int64 * L.CP_MAX_ORDER)(*A.dims)
     fs = A.struct()

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -36,6 +38,10 @@ struct cp_ctx_s {
   double* prep_out = nullptr;   // Gamma factor + column scales for the next update
   int32_t* chol_kind = nullptr;
   double* scal = nullptr;   // 64 scratch scalars
+  // launch configurations of the MTTKRP kernels: tuned options and plan cache
+  std::map<std::string, PlanOpts> tuned;
+  std::map<std::string, MttkrpPlan> plans;
+  std::string plans_text;
   // optional per-launch event timing
   bool prof = false;
   struct Rec { int cls; hipEvent_t a, b; };
@@ -195,10 +201,40 @@ cp_status enqueue_gram(cp_ctx ctx, double* const* A, float* const* A32, const in
     if (_t != CP_OK) return _t;     \
   } while (0)
 
-size_t max_partial(const int64_t* dims, int N, int R, bool fp32, std::vector<MttkrpPlan>* plans) {
+std::string plan_key(int N, const int64_t* dims, int n, int R, bool fp32) {
+  std::ostringstream o;
+  o << "N=" << N << ";dims=";
+  for (int m = 0; m < N; ++m) o << (m ? "," : "") << dims[m];
+  o << ";n=" << n << ";R=" << R << ";prec=" << (fp32 ? "mixed" : "fp64");
+  return o.str();
+}
+
+// Launch configuration for the MTTKRP of mode n: the tuned options when the
+// autotuner (or an imported plan set) has seen this shape, otherwise as many
+// streaming workgroups as stay resident next to the bookkeeping workgroup.
+MttkrpPlan get_plan(cp_ctx ctx, int N, const int64_t* dims, int n, int R, bool fp32) {
+  const std::string key = plan_key(N, dims, n, R, fp32);
+  auto hit = ctx->plans.find(key);
+  if (hit != ctx->plans.end()) return hit->second;
+  MttkrpPlan p;
+  auto t = ctx->tuned.find(key);
+  if (t != ctx->tuned.end()) {
+    p = mttkrp_plan(N, dims, n, R, fp32, t->second);
+  } else {
+    PlanOpts o{kTargetWgs, 0, 2, 4};
+    const int cap = mttkrp_capacity(mttkrp_plan(N, dims, n, R, fp32, o), fp32);
+    o.target_wgs = std::max(1, cap - 1);
+    p = mttkrp_plan(N, dims, n, R, fp32, o);
+  }
+  ctx->plans[key] = p;
+  return p;
+}
+
+size_t max_partial(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32,
+                   std::vector<MttkrpPlan>* plans) {
   size_t mx = 0;
   for (int n = 0; n < N; ++n) {
-    MttkrpPlan p = mttkrp_plan(N, dims, n, R, kTargetWgs, fp32);
+    MttkrpPlan p = get_plan(ctx, N, dims, n, R, fp32);
     if (plans) plans->push_back(p);
     mx = std::max(mx, p.partial_doubles);
   }
@@ -422,7 +458,7 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: mode %d outside [0, %d)", n, N);
   if (!M) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: M is NULL");
   const int R = A->rank;
-  MttkrpPlan plan = mttkrp_plan(N, Z->dims, n, R, kTargetWgs, mixed);
+  MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, R, mixed);
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   if (plan.nsplit == 1)
     return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M);
@@ -467,7 +503,7 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   if (nsweeps == 0) return CP_OK;
   const int R = A->rank;
   std::vector<MttkrpPlan> plans;
-  const size_t part = max_partial(Z->dims, N, R, mixed, &plans);
+  const size_t part = max_partial(ctx, Z->dims, N, R, mixed, &plans);
   Sizer sz;
   SweepWS w{};
   carve_sweep(sz, N, R, part, max_dim(Z->dims, N), &w);
@@ -497,7 +533,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
     return set_err(ctx, CP_ERR_INVALID, "cp_objective: g and the fused f need Z->norm2");
   const int R = A->rank;
   std::vector<MttkrpPlan> plans;
-  const size_t part = max_partial(Z->dims, N, R, mixed, &plans);
+  const size_t part = max_partial(ctx, Z->dims, N, R, mixed, &plans);
   const int64_t In_last = Z->dims[N - 1];
   Sizer sz;
   SweepWS w{};
@@ -689,7 +725,7 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: bad mode %d", n);
   if (reps < 1 || !ms) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: reps < 1 or ms NULL");
   const int R = A->rank;
-  MttkrpPlan plan = mttkrp_plan(N, Z->dims, n, R, kTargetWgs, mixed);
+  MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, R, mixed);
   if ((s = ensure_ws(ctx, align_up(plan.partial_doubles * sizeof(double)))) != CP_OK) return s;
   double* part = (double*)ctx->ws;
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
@@ -707,6 +743,139 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
+  return CP_OK;
+}
+
+cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_prec prec,
+                      int32_t reps) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
+  if (reps < 1 || reps > 10000) return set_err(ctx, CP_ERR_INVALID, "cp_autotune: reps outside [1, 10000]");
+  const int R = A->rank;
+  const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  // candidate options per mode
+  std::vector<std::vector<PlanOpts>> cands(N);
+  size_t maxpart = 0;
+  for (int n = 0; n < N; ++n) {
+    const MttkrpPlan p0 = mttkrp_plan(N, Z->dims, n, R, mixed, PlanOpts{kTargetWgs, 0, 2, 4});
+    const int kss[] = {0, 1, 2, 4, 8, 16};
+    const int tws1[] = {2};
+    const int tws23[] = {2, 4};
+    const int* tws = p0.kind == 1 ? tws1 : tws23;
+    const int ntw = p0.kind == 1 ? 1 : (p0.nt == 1 ? 2 : 1);
+    for (int pf = 0; pf < (mixed ? 2 : 1); ++pf) {   // pf: FP32 lane width 4 or 8
+      const int vwo = pf ? 8 : 4;
+      const int cap = mttkrp_capacity(mttkrp_plan(N, Z->dims, n, R, mixed, PlanOpts{kTargetWgs, 0, 2, vwo}), mixed);
+      const int targets[] = {cap - 1, cap / 2 - 1, 2 * cap - 1, (3 * cap) / 4 - 1, cap / 4 - 1};
+      for (int t : targets) {
+        if (t < 1) continue;
+        for (int ks : kss)
+          for (int q = 0; q < ntw; ++q) {
+            PlanOpts o{t, ks, tws[q], vwo};
+            const MttkrpPlan p = mttkrp_plan(N, Z->dims, n, R, mixed, o);
+            if (p.ksplit != ks && ks != 0) continue;   // clamped duplicate
+            cands[n].push_back(o);
+            maxpart = std::max(maxpart, p.partial_doubles);
+          }
+      }
+    }
+  }
+  Sizer sz;
+  sz.take<double>((size_t)N * R * R);
+  sz.take<double>((size_t)N * R);
+  sz.take<double>(maxpart);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  double* grams = ar.take<double>((size_t)N * R * R);
+  double* sigma = ar.take<double>((size_t)N * R);
+  double* part = ar.take<double>(maxpart);
+  HIPCHK(gram_launch(A->a, nullptr, Z->dims, N, R, grams, ctx->stream, sigma));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::ostringstream report;
+  for (int n = 0; n < N; ++n) {
+    // the bookkeeping workgroup as in a sweep (sweep boundary on mode 0)
+    PrepArgs pa{};
+    pa.N = N;
+    pa.n = n;
+    pa.R = R;
+    pa.grams = grams;
+    pa.sigma = sigma;
+    pa.out = ctx->prep_out;
+    pa.kind = ctx->chol_kind;
+    pa.flags = ctx->flags;
+    pa.solver = CP_SOLVE_CHOL;
+    pa.p = (n + N - 1) % N;
+    pa.Ap = A->a[pa.p];
+    pa.Ip = Z->dims[pa.p];
+    pa.boundary = n == 0;
+    pa.normalize = 1;
+    double best = 1e30;
+    PlanOpts bo{};
+    for (const PlanOpts& o : cands[n]) {
+      const MttkrpPlan p = mttkrp_plan(N, Z->dims, n, R, mixed, o);
+      for (int w = 0; w < 2; ++w)
+        HIPCHK(mttkrp_launch(p, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
+                             &pa, ctx->stream));
+      HIPCHK(hipEventRecord(e0, ctx->stream));
+      for (int k = 0; k < reps; ++k)
+        HIPCHK(mttkrp_launch(p, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
+                             &pa, ctx->stream));
+      HIPCHK(hipEventRecord(e1, ctx->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      const double us = 1e3 * t / reps;
+      if (us < best) {
+        best = us;
+        bo = o;
+      }
+    }
+    const std::string key = plan_key(N, Z->dims, n, R, mixed);
+    ctx->tuned[key] = bo;
+    ctx->plans.erase(key);
+    report << key << " " << bo.target_wgs << " " << bo.ksplit << " " << bo.tw << " " << bo.vw
+           << " " << best << "\n";
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return CP_OK;
+}
+
+const char* cp_plans_export(cp_ctx ctx) {
+  if (!ctx) return "";
+  std::ostringstream o;
+  for (const auto& kv : ctx->tuned)
+    o << kv.first << " " << kv.second.target_wgs << " " << kv.second.ksplit << " " << kv.second.tw
+      << " " << kv.second.vw << "\n";
+  ctx->plans_text = o.str();
+  return ctx->plans_text.c_str();
+}
+
+cp_status cp_plans_import(cp_ctx ctx, const char* text) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!text) return set_err(ctx, CP_ERR_INVALID, "cp_plans_import: NULL text");
+  std::istringstream in(text);
+  std::string line;
+  int count = 0;
+  while (std::getline(in, line)) {
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    std::string key;
+    PlanOpts o{};
+    if (!(ls >> key >> o.target_wgs >> o.ksplit >> o.tw >> o.vw) || o.target_wgs < 1 ||
+        o.ksplit < 0 || (o.tw != 2 && o.tw != 4) || (o.vw != 4 && o.vw != 8))
+      return set_err(ctx, CP_ERR_INVALID, "cp_plans_import: bad line '%s'", line.c_str());
+    ctx->tuned[key] = o;
+    ctx->plans.erase(key);
+    ++count;
+  }
   return CP_OK;
 }
 
@@ -901,7 +1070,7 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
       L.phat[n] = (l + 1 < nlevels) ? levels[l].phat[n] : nullptr;
     }
     L.z = mixed ? (const void*)levels[l].z.z32 : (const void*)levels[l].z.z64;
-    maxpart = std::max(maxpart, max_partial(L.dims, N, R, mixed, &L.plans));
+    maxpart = std::max(maxpart, max_partial(ctx, L.dims, N, R, mixed, &L.plans));
     maxI = std::max(maxI, max_dim(L.dims, N));
   }
   auto carve = [&](auto& c, bool real) {

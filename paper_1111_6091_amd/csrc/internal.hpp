@@ -84,15 +84,28 @@ struct MttkrpDesc {
 };
 
 // planner + launcher (mttkrp.hip)
+struct PlanOpts {
+  int32_t target_wgs;   // streaming workgroups to aim for
+  int32_t ksplit;       // pieces of the contraction range (0: automatic)
+  int32_t tw;           // 16-row tiles per wave, kinds 2/3 (0: 2)
+  int32_t vw;           // FP32: tensor entries per lane load, 4 (16 B) or 8 (32 B)
+};
+
 struct MttkrpPlan {
   int32_t kind, nsplit, ngroups, ksplit, kchunk, rgroups;
   int64_t chunk, units;
   size_t partial_doubles;   // nsplit * I_n * R
   int32_t tw;               // row tiles per wave (kind 2/3)
   int32_t nt;               // 16-column tiles (ceil(R/16))
+  int32_t vw;               // tensor entries per lane load
+  int32_t bl;               // 1: the contracted factor is staged in LDS
+  int64_t bstage_doubles;   // its LDS footprint (doubles) when bl
+  PlanOpts opts;            // options the plan was made from
 };
 
-MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs, bool fp32);
+MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, bool fp32, const PlanOpts& o);
+// resident workgroups of the plan's kernel on the whole device
+int mttkrp_capacity(const MttkrpPlan& p, bool fp32);
 hipError_t mttkrp_launch(const MttkrpPlan& plan, const int64_t* dims, int N, int n, int R,
                          const void* z, bool fp32, const double* const* a64,
                          const float* const* a32, double* out, const PrepArgs* prep,

@@ -32,39 +32,120 @@ __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Load 4 consecutive entries p[0..3]; entries at index >= nvalid read as 0.
-template <typename T, bool VEC>
-__device__ __forceinline__ typename Vec4<T>::type load4(const T* __restrict__ p, int nvalid) {
+template <typename T, bool NTH>
+__device__ __forceinline__ T ld(const T* p) {
+  if (NTH) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
+// Load 4 consecutive entries p[0..3] (VEC: one 4-wide load).  Branch-free: an
+// invalid entry (index >= nvalid) is loaded from `safe` (any valid, 16-byte
+// aligned address); the consumer zeroes it with the validity mask, after the
+// loads of the next step have been issued.
+// NTH: non-temporal hint.  The tensor is streamed once per launch, but the
+// hint only pays when one load instruction covers whole 128-byte lines; when a
+// line is split over two instructions of a wave it is fetched twice.
+template <typename T, bool VEC, bool NTH>
+__device__ __forceinline__ typename Vec4<T>::type load4(const T* p, const T* __restrict__ safe,
+                                                        int nvalid) {
   typedef typename Vec4<T>::type V;
   V v;
   if (VEC) {
-    if (nvalid >= 4) {
-      v = *reinterpret_cast<const V*>(p);
-    } else {
-      v = V{0, 0, 0, 0};
-    }
+    v = ld<V, NTH>(reinterpret_cast<const V*>(nvalid >= 4 ? p : safe));
   } else {
-    v[0] = nvalid > 0 ? p[0] : T(0);
-    v[1] = nvalid > 1 ? p[1] : T(0);
-    v[2] = nvalid > 2 ? p[2] : T(0);
-    v[3] = nvalid > 3 ? p[3] : T(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = ld<T, NTH>(nvalid > e ? p + e : safe);
   }
   return v;
 }
 
-// 32 bytes per lane: VW = 4 doubles or 8 floats, as one or two 4-wide loads.
-template <typename T> struct VW_ { static constexpr int value = 32 / sizeof(T); };
+// validity bits of one 4-wide load: bit e set when entry e is valid
+template <bool VEC>
+__device__ __forceinline__ uint32_t valid4(int nvalid) {
+  if (VEC) return nvalid >= 4 ? 0xFu : 0u;
+  return (1u << (nvalid < 0 ? 0 : (nvalid > 4 ? 4 : nvalid))) - 1u;
+}
 
-template <typename T, bool VEC>
-__device__ __forceinline__ void loadw(const T* __restrict__ p, int nvalid, T (&out)[VW_<T>::value]) {
-  constexpr int VW = VW_<T>::value;
+// VW consecutive entries (VW = 4 or 8) as one or two 4-wide loads; returns
+// VW validity bits.
+template <typename T, int VW, bool VEC, bool NTH>
+__device__ __forceinline__ uint32_t loadw(const T* p, const T* __restrict__ safe, int nvalid,
+                                          T (&out)[VW]) {
+  uint32_t m = 0;
 #pragma unroll
   for (int q = 0; q < VW / 4; ++q) {
     const int nv = nvalid - 4 * q;
-    const typename Vec4<T>::type v = load4<T, VEC>(p + 4 * q, nv < 0 ? 0 : (nv > 4 ? 4 : nv));
+    const int nq = nv < 0 ? 0 : (nv > 4 ? 4 : nv);
+    const typename Vec4<T>::type v = load4<T, VEC, NTH>(p + 4 * q, safe, nq);
+    m |= valid4<VEC>(nq) << (4 * q);
 #pragma unroll
     for (int e = 0; e < 4; ++e) out[4 * q + e] = v[e];
   }
+  return m;
+}
+
+// The GEMM B operand (the contracted mode's factor, I x R) can be staged in
+// LDS once per workgroup, transposed to Bs[c * ldb + i] for the 16*NT padded
+// columns c; reads are then 4 consecutive i of one column per lane.  ldb pads
+// the column stride so that the 16 columns read by one instruction fall into
+// distinct banks; pad entries and columns c >= R hold zeros, and the last 4
+// entries of every column are pad (a finite operand for masked lanes).
+template <typename T> constexpr int64_t bstage_ld(int64_t I) {
+  return (I + 3) / 4 * 4 + (sizeof(T) == 4 ? 4 : 6);
+}
+template <typename T> constexpr int64_t bstage_doubles(int64_t I, int NT) {
+  return (16 * NT * bstage_ld<T>(I) * (int64_t)sizeof(T) + 7) / 8;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void stage_b(const T* __restrict__ ak, int I, int R, T* Bs) {
+  constexpr int NC = 16 * NT;
+  const int ldb = (int)bstage_ld<T>(I);
+  // zeros: columns c >= R and the pad rows i >= I
+  for (int i = threadIdx.x; i < ldb; i += kThreads) {
+    const bool padrow = i >= I;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c >= R || padrow) Bs[c * ldb + i] = T(0);
+  }
+  // the factor is contiguous (I x R): coalesced loads, 8 in flight per thread
+  const int total = I * R;
+  for (int base = 0; base < total; base += 8 * kThreads) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int idx = base + j * kThreads + (int)threadIdx.x;
+      v[j] = ak[idx < total ? idx : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int idx = base + j * kThreads + (int)threadIdx.x;
+      if (idx < total) {
+        const int i = idx / R, c = idx - i * R;
+        Bs[c * ldb + i] = v[j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+// 4 consecutive entries of Bs (16-byte aligned)
+__device__ __forceinline__ void lds4(const float* p, float (&o)[4]) {
+  const f4 v = *reinterpret_cast<const f4*>(p);
+  o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+__device__ __forceinline__ void lds4(const double* p, double (&o)[4]) {
+  const d2 v0 = *reinterpret_cast<const d2*>(p);
+  const d2 v1 = *reinterpret_cast<const d2*>(p + 2);
+  o[0] = v0[0]; o[1] = v0[1]; o[2] = v1[0]; o[3] = v1[1];
+}
+
+// One factor entry (GEMM B operand), 0 when !ok.
+template <typename T>
+__device__ __forceinline__ T loadb(const T* __restrict__ ak, int64_t idx, bool ok) {
+  const T x = ak[ok ? idx : 0];
+  return ok ? x : T(0);
 }
 
 // Product of the stripe-mode factors at stripe s, column col (skip mode `skip`).
@@ -79,9 +160,6 @@ __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, 
   return w;
 }
 
-constexpr int kSmem = kPrepSmem;   // doubles of LDS per workgroup (40 KB)
-static_assert(kSmem >= 4096, "reduction buffers need 4096 doubles");
-
 // Workgroup 0 of a launch with prep set does the sweep bookkeeping for the
 // update that follows (sweep.hpp), concurrently with the streaming workgroups;
 // it is dispatched first, so it is resident from the start.
@@ -91,19 +169,25 @@ __device__ __forceinline__ bool prep_block(const MttkrpDesc& d, double* smem) {
   return true;
 }
 
+// LDS (doubles) of the streaming workgroups of each kernel
+constexpr int kind1_smem() { return 4 * 16 * 2 * 16; }
+constexpr int kind23_smem(int TW, int NT, bool k3) { return k3 ? 4 * 16 * NT : 4 * 16 * TW * 16 * NT; }
+
 // ---------------------------------------------------------------------------
 // kind 1: output mode 0.  Each lane loads VW consecutive rows i0 at one i1;
 // sub-tile a holds rows i0 = grp*16*VW + VW*m + a (m = GEMM row).  Contraction
 // over i1 on the matrix cores, Hadamard weight per stripe in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, bool VEC>
+template <typename T, int NT, int VW, bool VEC, bool BL>
 __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
   typedef typename Vec4<T>::type V;
-  constexpr int VW = VW_<T>::value;
   constexpr int PANEL = 16 * VW;
-  __shared__ double smem[kSmem];
+  // 16 lanes x 16 bytes cover two whole lines only for 4-wide FP32 loads
+  constexpr bool NTH = sizeof(T) == 4 && VW == 4;
+  extern __shared__ double smem[];
   if (prep_block(d, smem)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
   const int bid = blockIdx.x - d.prep;
   const int grp = bid % d.ngroups;
@@ -115,6 +199,9 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
   const int64_t i0b = (int64_t)grp * PANEL + VW * r;   // first of this lane's VW rows
   const int64_t left = I0 - i0b;
   const int nrow = left <= 0 ? 0 : (left >= VW ? VW : (int)left);
+  T* Bs = reinterpret_cast<T*>(smem);
+  const int ldb = (int)bstage_ld<T>(I1);
+  if (BL) stage_b<T, NT>(ak, (int)I1, R, Bs);
 
   double acc[VW][NT][4];
 #pragma unroll
@@ -139,28 +226,66 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
     for (int a = 0; a < VW; ++a)
 #pragma unroll
       for (int t = 0; t < NT; ++t) D[a][t] = V{0, 0, 0, 0};
-    const T* __restrict__ zs = z + (size_t)s * I0 * I1 + i0b;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
-      T zv[4][VW];
-      T b[4][NT];
+    const T* zs = z + (size_t)s * I0 * I1 + i0b;
+    // one step: 16 consecutive i1 (4 per lane group), VW rows per lane;
+    // bit e*VW + a of the mask is set when zv[e][a] is a valid entry
+    auto fetch = [&](int64_t k0, T (&zv)[4][VW], T (&b)[4][NT], uint32_t& mask) {
+      mask = 0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i1 = k0 + 4 * g4 + e;
         const bool ok = i1 < kend;
-        loadw<T, VEC>(zs + (ok ? i1 : 0) * I0, ok ? nrow : 0, zv[e]);
+        mask |= loadw<T, VW, VEC, NTH>(zs + i1 * I0, z, ok ? nrow : 0, zv[e]) << (e * VW);
+        if (!BL) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const int col = t * 16 + r;
-          b[e][t] = (ok && col < R) ? ak[i1 * R + col] : T(0);
+          for (int t = 0; t < NT; ++t) {
+            const int col = t * 16 + r;
+            b[e][t] = loadb(ak, i1 * R + col, ok && col < R);
+          }
         }
       }
+      if (BL) {
+        // rows past kend read the zero pad at the end of the column
+        const int64_t i1b = k0 + 4 * g4;
+        const int boff = i1b < kend ? (int)i1b : ldb - 4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          T b4[4];
+          lds4(Bs + (t * 16 + r) * ldb + boff, b4);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) b[e][t] = b4[e];
+        }
+      }
+    };
+    auto compute = [&](const T (&zv)[4][VW], const T (&b)[4][NT], uint32_t mask) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int a = 0; a < VW; ++a)
+        for (int a = 0; a < VW; ++a) {
+          const T x = (mask >> (e * VW + a)) & 1u ? zv[e][a] : T(0);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) D[a][t] = mma(zv[e][a], b[e][t], D[a][t]);
+          for (int t = 0; t < NT; ++t) D[a][t] = mma(x, b[e][t], D[a][t]);
+        }
+    };
+    // two register buffers: the loads of the next step are in flight while
+    // the matrix cores work on the current one (the scheduling barriers keep
+    // each phase's loads ahead of the other buffer's matrix instructions)
+    T zA[4][VW], zB[4][VW];
+    T bA[4][NT], bB[4][NT];
+    uint32_t mA, mB;
+    fetch(kbeg, zA, bA, mA);
+    int64_t k0 = kbeg;
+    for (; k0 + 16 < kend; k0 += 32) {
+      fetch(k0 + 16, zB, bB, mB);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(zA, bA, mA);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(k0 + 32, zA, bA, mA);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(zB, bB, mB);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (k0 < kend) compute(zA, bA, mA);
     // Hadamard-reduce with the stripe weight (FP64)
 #pragma unroll
     for (int a = 0; a < VW; ++a)
@@ -169,26 +294,26 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[a][t][v] += (double)D[a][t][v] * w[t];
   }
-  // deterministic cross-wave reduction through LDS, 4 sub-tiles x 16 columns at
-  // a time: GEMM row m of sub-tile a holds i0 = grp*PANEL + VW*m + a
+  // deterministic cross-wave reduction through LDS, 2 sub-tiles x 16 columns
+  // at a time: GEMM row m of sub-tile a holds i0 = grp*PANEL + VW*m + a
 #pragma unroll
-  for (int a0 = 0; a0 < VW; a0 += 4)
+  for (int a0 = 0; a0 < VW; a0 += 2)
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       __syncthreads();
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          smem[(wave * 64 + mfma_row<T>(g4, v) * 4 + a) * 16 + r] = acc[a0 + a][t][v];
+          smem[((wave * 16 + mfma_row<T>(g4, v)) * 2 + a) * 16 + r] = acc[a0 + a][t][v];
       __syncthreads();
-      for (int idx = threadIdx.x; idx < 64 * 16; idx += kThreads) {
-        const int q = idx / 16, c = idx % 16;   // q = 4*m + a
-        const int m = q >> 2, a = q & 3;
+      for (int idx = threadIdx.x; idx < 16 * 2 * 16; idx += kThreads) {
+        const int q = idx / 16, c = idx % 16;   // q = 2*m + a
+        const int m = q >> 1, a = q & 1;
         const int64_t i0 = (int64_t)grp * PANEL + VW * m + a0 + a;
         const int col = t * 16 + c;
         if (col < R && i0 < I0) {
-          const double sum = smem[idx] + smem[1024 + idx] + smem[2048 + idx] + smem[3072 + idx];
+          const double sum = smem[idx] + smem[512 + idx] + smem[1024 + idx] + smem[1536 + idx];
           d.out[((size_t)split * d.In + i0) * R + col] = sum;
         }
       }
@@ -200,15 +325,15 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
 // consecutive i0 per lane.  kind 2 (n == 1): rows are the outputs; kind 3
 // (n >= 2): rows are reduced with A^(1)(i1, r) into output s_n.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int TW, bool KIND3, bool VEC>
+template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL>
 __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   typedef typename Vec4<T>::type V;
-  constexpr int VW = VW_<T>::value;
   constexpr int KC = 4 * VW;   // contraction chunk per step of the loop
   constexpr int ROWS = 16 * TW;
-  __shared__ double smem[kSmem];
+  extern __shared__ double smem[];
   if (prep_block(d, smem)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
   const int bid = blockIdx.x - d.prep;
   const int grp = bid % d.ngroups;
@@ -217,6 +342,9 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   const T* __restrict__ ak = reinterpret_cast<const T*>(d.ak);
   const int R = d.R;
   const int64_t I0 = d.I0, I1 = d.I1;
+  T* Bs = reinterpret_cast<T*>(smem);
+  const int ldb = (int)bstage_ld<T>(I0);
+  if (BL) stage_b<T, NT>(ak, (int)I0, R, Bs);
 
   // kind 2: acc[tw][t][v] holds row grp*ROWS + tw*16 + mfma_row<T>(g4, v)
   // kind 3: acc[0][t][0] holds the running sum for column t*16 + r
@@ -257,55 +385,103 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
     double w[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) w[t] = stripe_weight(d, s, t * 16 + r, KIND3 ? d.n : -1);
+    // stage-2 operands are loaded before the contraction loop so that their
+    // latency overlaps the tensor stream
+    double a1w[KIND3 ? TW : 1][KIND3 ? NT : 1][4];
+    if (KIND3) {
+#pragma unroll
+      for (int a = 0; a < TW; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t i1 = rowbase + a * 16 + mfma_row<T>(g4, v);
+            const int col = t * 16 + r;
+            a1w[a][t][v] = (i1 < I1 && col < R) ? d.a64[1][i1 * R + col] * w[t] : 0.0;
+          }
+    }
     V D[TW][NT];
 #pragma unroll
     for (int a = 0; a < TW; ++a)
 #pragma unroll
       for (int t = 0; t < NT; ++t) D[a][t] = V{0, 0, 0, 0};
-    const T* __restrict__ zs = z + (size_t)s * I0 * I1;
+    const T* zs = z + (size_t)s * I0 * I1;
+    int64_t rowoff[TW];
     bool rowok[TW];
 #pragma unroll
-    for (int a = 0; a < TW; ++a) rowok[a] = (rowbase + a * 16 + r) < I1;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    for (int a = 0; a < TW; ++a) {
+      const int64_t i1 = rowbase + a * 16 + r;
+      rowok[a] = i1 < I1;
+      rowoff[a] = (rowok[a] ? i1 : 0) * I0;
+    }
+    // one step: KC consecutive i0 (VW per lane group) for 16*TW rows i1;
+    // bit a*VW + e of the mask is set when zv[a][e] is a valid entry
+    auto fetch = [&](int64_t k0, T (&zv)[TW][VW], T (&b)[VW][NT], uint32_t& mask) {
       const int64_t kl = k0 + VW * g4;
       const int64_t nk = kend - kl;
       const int nval = nk >= VW ? VW : (nk > 0 ? (int)nk : 0);
-      T zv[TW][VW];
+      mask = 0;
 #pragma unroll
-      for (int a = 0; a < TW; ++a) {
-        const int64_t i1 = rowbase + a * 16 + r;
-        loadw<T, VEC>(zs + (rowok[a] ? i1 : 0) * I0 + (nval ? kl : 0), rowok[a] ? nval : 0, zv[a]);
+      for (int a = 0; a < TW; ++a)
+        mask |= loadw<T, VW, VEC, false>(zs + rowoff[a] + kl, z, rowok[a] ? nval : 0, zv[a]) << (a * VW);
+      if (BL) {
+        // entries past kend read the zero pad at the end of the column
+        const int boff = nval ? (int)kl : ldb - 4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < VW / 4; ++q) {
+            T b4[4];
+            lds4(Bs + (t * 16 + r) * ldb + (nval > 4 * q ? boff + 4 * q : ldb - 4), b4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) b[4 * q + e][t] = b4[e];
+          }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const int col = t * 16 + r;
+            b[e][t] = loadb(ak, (kl + e) * R + col, e < nval && col < R);
+          }
       }
-      T b[VW][NT];
+    };
+    auto compute = [&](const T (&zv)[TW][VW], const T (&b)[VW][NT], uint32_t mask) {
 #pragma unroll
       for (int e = 0; e < VW; ++e)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const int col = t * 16 + r;
-          b[e][t] = (e < nval && col < R) ? ak[(kl + e) * R + col] : T(0);
+        for (int a = 0; a < TW; ++a) {
+          const T x = (mask >> (a * VW + e)) & 1u ? zv[a][e] : T(0);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) D[a][t] = mma(x, b[e][t], D[a][t]);
         }
-#pragma unroll
-      for (int e = 0; e < VW; ++e)
-#pragma unroll
-        for (int a = 0; a < TW; ++a)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) D[a][t] = mma(zv[a][e], b[e][t], D[a][t]);
+    };
+    T zA[TW][VW], zB[TW][VW];
+    T bA[VW][NT], bB[VW][NT];
+    uint32_t mA, mB;
+    fetch(kbeg, zA, bA, mA);
+    int64_t k0 = kbeg;
+    for (; k0 + KC < kend; k0 += 2 * KC) {
+      fetch(k0 + KC, zB, bB, mB);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(zA, bA, mA);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(k0 + 2 * KC, zA, bA, mA);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(zB, bB, mB);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (k0 < kend) compute(zA, bA, mA);
     // Hadamard-reduce (FP64)
     if (KIND3) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const int col = t * 16 + r;
         double part = 0.0;
 #pragma unroll
         for (int a = 0; a < TW; ++a)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t i1 = rowbase + a * 16 + mfma_row<T>(g4, v);
-            const double a1 = (i1 < I1 && col < R) ? d.a64[1][i1 * R + col] : 0.0;
-            part += (double)D[a][t][v] * a1;
-          }
-        acc[0][t][0] += part * w[t];
+          for (int v = 0; v < 4; ++v) part += (double)D[a][t][v] * a1w[a][t][v];
+        acc[0][t][0] += part;
       }
     } else {
 #pragma unroll
@@ -316,6 +492,7 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
           for (int v = 0; v < 4; ++v) acc[a][t][v] += (double)D[a][t][v] * w[t];
     }
   }
+  __syncthreads();   // smem aliases the staged B operand
   if (KIND3) {
     // reduce over the 4 lane groups (rows), then over waves in fixed order
 #pragma unroll
@@ -334,7 +511,6 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
       }
     }
   } else {
-    static_assert(4 * ROWS * 16 * NT <= kSmem, "reduction buffer");
 #pragma unroll
     for (int a = 0; a < TW; ++a)
 #pragma unroll
@@ -360,15 +536,18 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
 // ---------------------------------------------------------------------------
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs, bool fp32) {
+MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, bool fp32, const PlanOpts& o) {
   MttkrpPlan p{};
   const int64_t I0 = dims[0], I1 = dims[1];
   int64_t S = 1;
   for (int m = 2; m < N; ++m) S *= dims[m];
-  const int64_t vw = fp32 ? 8 : 4;   // elements per 32-byte lane load
+  // consecutive tensor entries per lane load: 4 (FP64: 32 bytes), 4 or 8 (FP32)
+  const int64_t vw = (fp32 && o.vw == 8) ? 8 : 4;
+  p.vw = (int32_t)vw;
   p.nt = R <= 16 ? 1 : 2;
-  p.tw = 2;
+  p.tw = (o.tw == 4 && p.nt == 1) ? 4 : 2;
   const int64_t rows = 16 * p.tw;
+  const int64_t target = std::max<int64_t>(1, o.target_wgs);
   int64_t base_units, K, kgran;
   if (n == 0) {
     p.kind = 1;
@@ -390,41 +569,89 @@ MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, int target_wgs,
     K = I0;
     kgran = 4 * vw;
   }
-  // split the contraction when there are too few (group, unit) pairs for the chip
-  const int64_t want_units = (int64_t)target_wgs * 4;
-  int64_t ks = 1;
+  // split the contraction when there are too few (group, unit) pairs: aim for
+  // four units (one per wave) in each of `target` workgroups
   const int64_t kchunks = ceil_div(K, kgran);
-  if ((int64_t)p.ngroups * base_units < want_units)
-    ks = std::min<int64_t>(kchunks, ceil_div(want_units, (int64_t)p.ngroups * base_units));
-  if (ks < 1) ks = 1;
+  int64_t ks = o.ksplit;
+  if (ks <= 0) {
+    ks = 1;
+    if ((int64_t)p.ngroups * base_units < target * 4)
+      ks = ceil_div(target * 4, (int64_t)p.ngroups * base_units);
+  }
+  ks = std::max<int64_t>(1, std::min<int64_t>(ks, kchunks));
   const int64_t kchunk = ceil_div(kchunks, ks) * kgran;
   ks = ceil_div(K, kchunk);
   p.ksplit = (int32_t)ks;
   p.kchunk = (int32_t)kchunk;
   p.units = base_units * ks;
-  int64_t nsplit = std::max<int64_t>(1, target_wgs / p.ngroups);
-  nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, ceil_div(p.units, 4)));
-  p.chunk = ceil_div(p.units, nsplit);
+  // units per workgroup: a multiple of 4 so the four waves stay balanced
+  const int64_t nsplit_max = std::max<int64_t>(1, target / p.ngroups);
+  int64_t chunk = ceil_div(p.units, nsplit_max);
+  // a multiple of 4 units keeps the four waves of a workgroup balanced; it is
+  // used when it keeps at least 3/4 of the workgroups
+  if (p.units >= 4) {
+    const int64_t c4 = ceil_div(chunk, 4) * 4;
+    if (4 * ceil_div(p.units, c4) >= 3 * ceil_div(p.units, chunk)) chunk = c4;
+  }
+  p.chunk = chunk;
   p.nsplit = (int32_t)ceil_div(p.units, p.chunk);
   p.partial_doubles = (size_t)p.nsplit * dims[n] * R;
+  // stage the contracted factor (I1 x R for kind 1, I0 x R otherwise) in LDS
+  // when it takes at most 64 KB
+  const int64_t Ik = p.kind == 1 ? I1 : I0;
+  p.bstage_doubles = fp32 ? bstage_doubles<float>(Ik, p.nt) : bstage_doubles<double>(Ik, p.nt);
+  p.bl = p.bstage_doubles * 8 <= 64 * 1024 ? 1 : 0;
+  if (!p.bl) p.bstage_doubles = 0;
+  p.opts = o;
   return p;
 }
 
-template <typename T, int NT>
-static hipError_t launch_typed(const MttkrpPlan& p, const MttkrpDesc& d, bool vec,
-                               hipStream_t st) {
-  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
-  if (p.kind == 1) {
-    if (vec) hipLaunchKernelGGL((mttkrp_kind1<T, NT, true>), grid, block, 0, st, d);
-    else hipLaunchKernelGGL((mttkrp_kind1<T, NT, false>), grid, block, 0, st, d);
-  } else if (p.kind == 2) {
-    if (vec) hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, false, true>), grid, block, 0, st, d);
-    else hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, false, false>), grid, block, 0, st, d);
-  } else {
-    if (vec) hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, true, true>), grid, block, 0, st, d);
-    else hipLaunchKernelGGL((mttkrp_kind23<T, NT, 2, true, false>), grid, block, 0, st, d);
+template <typename T, int NT, int VW, bool BL>
+static const void* kernel_ptr(int kind, int tw, bool vec) {
+  if (kind == 1)
+    return vec ? (const void*)mttkrp_kind1<T, NT, VW, true, BL> : (const void*)mttkrp_kind1<T, NT, VW, false, BL>;
+  const bool k3 = kind == 3;
+  if (tw == 4 && NT == 1) {
+    if (k3) return vec ? (const void*)mttkrp_kind23<T, 1, 4, true, VW, true, BL> : (const void*)mttkrp_kind23<T, 1, 4, true, VW, false, BL>;
+    return vec ? (const void*)mttkrp_kind23<T, 1, 4, false, VW, true, BL> : (const void*)mttkrp_kind23<T, 1, 4, false, VW, false, BL>;
   }
-  return hipGetLastError();
+  if (k3) return vec ? (const void*)mttkrp_kind23<T, NT, 2, true, VW, true, BL> : (const void*)mttkrp_kind23<T, NT, 2, true, VW, false, BL>;
+  return vec ? (const void*)mttkrp_kind23<T, NT, 2, false, VW, true, BL> : (const void*)mttkrp_kind23<T, NT, 2, false, VW, false, BL>;
+}
+
+template <typename T, int VW>
+static const void* kernel_ptr_nt(const MttkrpPlan& p, bool vec) {
+  if (p.bl) return p.nt == 1 ? kernel_ptr<T, 1, VW, true>(p.kind, p.tw, vec) : kernel_ptr<T, 2, VW, true>(p.kind, p.tw, vec);
+  return p.nt == 1 ? kernel_ptr<T, 1, VW, false>(p.kind, p.tw, vec) : kernel_ptr<T, 2, VW, false>(p.kind, p.tw, vec);
+}
+
+static const void* select_kernel(const MttkrpPlan& p, bool fp32, bool vec) {
+  if (fp32) return p.vw == 8 ? kernel_ptr_nt<float, 8>(p, vec) : kernel_ptr_nt<float, 4>(p, vec);
+  return kernel_ptr_nt<double, 4>(p, vec);
+}
+
+// dynamic LDS bytes of a launch
+size_t mttkrp_smem_bytes(const MttkrpPlan& p, int N, int R, bool prep) {
+  int64_t d = p.kind == 1 ? kind1_smem() : kind23_smem(p.tw, p.nt, p.kind == 3);
+  if (p.bl) d = std::max<int64_t>(d, p.bstage_doubles);
+  if (prep) d = std::max<int64_t>(d, prep_smem_doubles(N, R));
+  return sizeof(double) * (size_t)d;
+}
+
+int mttkrp_capacity(const MttkrpPlan& p, bool fp32) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+  }
+  const void* k = select_kernel(p, fp32, true);
+  int nb = 0;
+  const size_t smem = mttkrp_smem_bytes(p, 8, kMaxRank, false);
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, smem) != hipSuccess || nb < 1)
+    nb = 1;
+  return nb * cus;
 }
 
 hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
@@ -470,10 +697,11 @@ hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n,
   const size_t esz = fp32 ? 4 : 8;
   const bool vec = (dims[0] % 4 == 0) && (((uintptr_t)z) % (4 * esz) == 0);
   (void)esz;
-  if (fp32) {
-    return p.nt == 1 ? launch_typed<float, 1>(p, d, vec, st) : launch_typed<float, 2>(p, d, vec, st);
-  }
-  return p.nt == 1 ? launch_typed<double, 1>(p, d, vec, st) : launch_typed<double, 2>(p, d, vec, st);
+  const void* k = select_kernel(p, fp32, vec);
+  if (!k) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
+  void* args[] = {&d};
+  return hipLaunchKernel(k, grid, block, args, mttkrp_smem_bytes(p, N, R, d.prep != 0), st);
 }
 
 }  // namespace cpamg

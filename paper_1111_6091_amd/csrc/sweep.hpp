@@ -15,7 +15,12 @@
 
 namespace cpamg {
 
-constexpr int kPrepSmem = 5 * kMaxRank * kMaxRank;   // doubles of LDS needed
+constexpr int kGramTile = 512;   // doubles of a factor staged per round by gram_into
+
+// Doubles of LDS the bookkeeping step needs for order N and rank R.
+__host__ __device__ constexpr int prep_smem_doubles(int N, int R) {
+  return 5 * R * R + N * R + kGramTile;
+}
 
 // Block-wide sum of one double per thread; result valid in every thread.
 __device__ inline double wg_sum(double v, double* sred) {
@@ -30,10 +35,11 @@ __device__ inline double wg_sum(double v, double* sred) {
   return s;
 }
 
-// U (LDS, R*R) = A^T A for A (I x R, global), staged through `tile` (2048 doubles).
+// U (LDS, R*R) = A^T A for A (I x R, global), staged through `tile` (kGramTile doubles).
 __device__ inline void gram_into(const double* __restrict__ A, int64_t I, int R, double* U,
                                  double* tile) {
-  constexpr int TILE = 2048;
+  constexpr int TILE = kGramTile;
+  constexpr int PER = TILE / kThreads;
   const int tid = threadIdx.x;
   const int trows = TILE / R;
   const int RR = R * R;
@@ -41,15 +47,15 @@ __device__ inline void gram_into(const double* __restrict__ A, int64_t I, int R,
   for (int64_t i0 = 0; i0 < I; i0 += trows) {
     const int rows = (int)((I - i0) < trows ? (I - i0) : trows);
     const int cnt = rows * R;
-    double v[8];
+    double v[PER];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * kThreads;
       v[q] = idx < cnt ? A[i0 * R + idx] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * kThreads;
       if (idx < cnt) tile[idx] = v[q];
     }
@@ -98,19 +104,19 @@ __device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind
   __syncthreads();
 }
 
-// The bookkeeping step; smem: kPrepSmem doubles of LDS.  With finalize set,
+// The bookkeeping step; smem: prep_smem_doubles(N, R) doubles of LDS.  With finalize set,
 // the pending scales are applied to the stored factors and reset instead of
 // preparing an update.
 __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
   __shared__ double sred[8];
   const int R = a.R, N = a.N, n = a.n, RR = R * R, tid = threadIdx.x;
   double* G = smem;
-  double* S = smem + kMaxRank * kMaxRank;
-  double* V = smem + 2 * kMaxRank * kMaxRank;
-  double* P = smem + 3 * kMaxRank * kMaxRank;
-  double* U = smem + 4 * kMaxRank * kMaxRank;
-  double* sS = S;   // sigma (N x R) lives in S until the factorization needs S
-  double* tile = V; // 2048 doubles spanning V and P
+  double* S = G + RR;
+  double* V = S + RR;
+  double* P = V + RR;
+  double* U = P + RR;
+  double* sS = U + RR;       // sigma, N x R
+  double* tile = sS + N * R; // kGramTile doubles
   for (int idx = tid; idx < N * R; idx += kThreads) sS[idx] = a.sigma[idx];
   if (a.p >= 0) gram_into(a.Ap, a.Ip, R, U, tile);
   __syncthreads();

@@ -228,12 +228,13 @@ hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void finalize_kernel(PrepArgs a) {
-  __shared__ double smem[kPrepSmem];
-  sweep_prep(a, smem, true);
+  extern __shared__ double dsmem[];
+  sweep_prep(a, dsmem, true);
 }
 
 hipError_t finalize_launch(const PrepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, st, a);
+  const size_t bytes = sizeof(double) * prep_smem_doubles(a.N, a.R);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), bytes, st, a);
   return hipGetLastError();
 }
 

@@ -68,6 +68,9 @@ def test_null_context_is_rejected_without_touching_the_gpu():
     assert lib.cp_time_mttkrp(None, ctypes.byref(z), ctypes.byref(f), 0, 0, 1, ctypes.byref(ms)) == INVALID
     assert lib.cp_profile_enable(None, 1) == INVALID
     assert lib.cp_profile_read(None, None, None) == INVALID
+    assert lib.cp_autotune(None, ctypes.byref(z), ctypes.byref(f), 0, 5) == INVALID
+    assert lib.cp_plans_import(None, b"") == INVALID
+    assert lib.cp_plans_export(None) == b""
     flags = ctypes.c_int32()
     assert lib.cp_get_status(None, ctypes.byref(flags)) == INVALID
     assert lib.cp_ctx_destroy(None) == INVALID
