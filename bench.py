@@ -31,6 +31,32 @@ if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(HERE, "profiles", "mttkrp_256cube_r10_pmc.md")
+KERNEL_SOURCES = ["mttkrp.hip", "sweep.hpp", "internal.hpp", "smallla.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_1111_6091_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none or the kernel sources changed after the counters were taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("traffic_json:"):
+                t = json.loads(line.split(":", 1)[1])
+                if t.get("source_hash") != kernel_source_hash():
+                    return None
+                return t.get("bytes_per_launch", {}).get(kernel)
+    return None
 
 
 def log(*a):
@@ -47,6 +73,12 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-tune", action="store_true")
+    p.add_argument("--plans-file", default=None,
+                   help="import launch plans from this file instead of autotuning")
+    p.add_argument("--save-plans", default=None, help="write the tuned launch plans to this file")
+    p.add_argument("--mttkrp-only", action="store_true",
+                   help="launch each MTTKRP kernel --steps times and a 64 MiB device copy "
+                        "(byte-counter calibration), then exit; for profiler runs")
     return p.parse_args()
 
 
@@ -87,7 +119,12 @@ def main():
 
     # launch-configuration autotuner (before any timed region)
     plans = None
-    if not args.no_tune:
+    if args.plans_file:
+        with open(args.plans_file) as f:
+            api.cp_plans_import(ctx, f.read())
+        plans = api.cp_plans_export(ctx)
+        log(f"plans imported from {args.plans_file}")
+    elif not args.no_tune:
         t0 = time.perf_counter()
         At = fresh()
         for prec in (CP_MIXED, CP_FP64):
@@ -95,6 +132,23 @@ def main():
         torch.cuda.synchronize()
         plans = api.cp_plans_export(ctx)
         log(f"autotune {time.perf_counter() - t0:.2f} s:\n{plans}")
+    if args.save_plans and plans:
+        with open(args.save_plans, "w") as f:
+            f.write(plans)
+
+    if args.mttkrp_only:
+        A = fresh()
+        for prec in (CP_MIXED, CP_FP64):
+            for n in range(len(dims)):
+                api.cp_time_mttkrp(ctx, Zd, A, n, prec, K)
+        src = torch.empty(64 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(K):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"mttkrp-only: {K} launches of each MTTKRP (mixed, fp64 x {len(dims)} modes) and of a "
+            f"64 MiB copy; kernel source hash {kernel_source_hash()}")
+        return
 
     def timed(prec, steps, warm):
         A = fresh()
@@ -145,7 +199,7 @@ def main():
     roofline = {
         "bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["achieved_gbs"], 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
-        "traffic": None, "bytes_per_launch": dom["bytes_per_launch"],
+        "traffic": measured_traffic(dom["kernel"]), "bytes_per_launch": dom["bytes_per_launch"],
         "avg_launch_us": round(dom["avg_us"], 2),
     }
 

@@ -220,10 +220,11 @@ cp_status cp_profile_enable(cp_ctx ctx, int32_t on);
 cp_status cp_profile_read(cp_ctx ctx, double* ms, int32_t* counts);
 
 /* Measurement aid: enqueue `reps` back-to-back launches of the MTTKRP kernel
- * of mode n, in the launch configuration cp_mttkrp and cp_als_sweep use
- * (partial sums land in the workspace, M is not written), between two HIP
- * events recorded on the context's stream; synchronize and return the mean
- * milliseconds per launch in *ms (host). */
+ * of mode n exactly as cp_als_sweep launches it (same launch configuration,
+ * with the sweep-bookkeeping workgroup working on scratch Grams and scales;
+ * partial sums land in the workspace, neither M nor A is written), between two
+ * HIP events recorded on the context's stream; synchronize and return the
+ * mean milliseconds per launch in *ms (host). */
 cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
                          cp_prec prec, int32_t reps, double* ms);
 

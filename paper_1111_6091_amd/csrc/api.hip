@@ -713,6 +713,31 @@ cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat
   return CP_OK;
 }
 
+// The bookkeeping workgroup of mode n's launch inside an ALS sweep (the sweep
+// boundary falls on mode 0), on scratch Grams and column scales: timed launches
+// then have the same configuration and work as the launches of a sweep.  It
+// writes only the scratch arrays and the context's own prep/flag words.
+static PrepArgs timing_prep(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int n,
+                            double* grams, double* sigma) {
+  const int N = Z->order;
+  PrepArgs pa{};
+  pa.N = N;
+  pa.n = n;
+  pa.R = A->rank;
+  pa.grams = grams;
+  pa.sigma = sigma;
+  pa.out = ctx->prep_out;
+  pa.kind = ctx->chol_kind;
+  pa.flags = ctx->flags;
+  pa.solver = CP_SOLVE_CHOL;
+  pa.p = (n + N - 1) % N;
+  pa.Ap = A->a[pa.p];
+  pa.Ip = Z->dims[pa.p];
+  pa.boundary = n == 0;
+  pa.normalize = 1;
+  return pa;
+}
+
 cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
                          cp_prec prec, int32_t reps, double* ms) {
   if (!ctx) return CP_ERR_INVALID;
@@ -726,8 +751,17 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   if (reps < 1 || !ms) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: reps < 1 or ms NULL");
   const int R = A->rank;
   MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, R, mixed);
-  if ((s = ensure_ws(ctx, align_up(plan.partial_doubles * sizeof(double)))) != CP_OK) return s;
-  double* part = (double*)ctx->ws;
+  Sizer sz;
+  sz.take<double>((size_t)N * R * R);
+  sz.take<double>((size_t)N * R);
+  sz.take<double>(plan.partial_doubles);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  double* grams = ar.take<double>((size_t)N * R * R);
+  double* sigma = ar.take<double>((size_t)N * R);
+  double* part = ar.take<double>(plan.partial_doubles);
+  HIPCHK(gram_launch(A->a, nullptr, Z->dims, N, R, grams, ctx->stream, sigma));
+  const PrepArgs pa = timing_prep(ctx, Z, A, n, grams, sigma);
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -735,7 +769,7 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   HIPCHK(hipEventRecord(e0, ctx->stream));
   for (int k = 0; k < reps; ++k)
     HIPCHK(mttkrp_launch(plan, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
-                         nullptr, ctx->stream));
+                         &pa, ctx->stream));
   HIPCHK(hipEventRecord(e1, ctx->stream));
   HIPCHK(hipEventSynchronize(e1));
   float t = 0.f;
@@ -800,22 +834,7 @@ cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_pr
   HIPCHK(hipEventCreate(&e1));
   std::ostringstream report;
   for (int n = 0; n < N; ++n) {
-    // the bookkeeping workgroup as in a sweep (sweep boundary on mode 0)
-    PrepArgs pa{};
-    pa.N = N;
-    pa.n = n;
-    pa.R = R;
-    pa.grams = grams;
-    pa.sigma = sigma;
-    pa.out = ctx->prep_out;
-    pa.kind = ctx->chol_kind;
-    pa.flags = ctx->flags;
-    pa.solver = CP_SOLVE_CHOL;
-    pa.p = (n + N - 1) % N;
-    pa.Ap = A->a[pa.p];
-    pa.Ip = Z->dims[pa.p];
-    pa.boundary = n == 0;
-    pa.normalize = 1;
+    const PrepArgs pa = timing_prep(ctx, Z, A, n, grams, sigma);
     double best = 1e30;
     PlanOpts bo{};
     for (const PlanOpts& o : cands[n]) {
