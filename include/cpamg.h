@@ -248,6 +248,53 @@ cp_status cp_plans_import(cp_ctx ctx, const char* text);
  * eq. (10)); permutes the columns of every A^(n) (and shadows) in place. */
 cp_status cp_sort(cp_ctx ctx, const int64_t* dims /*host, N*/, int32_t order, cp_factors* A);
 
+/* ---- batched solves ------------------------------------------------------ */
+
+#define CP_MAX_RESTARTS 8
+
+/* One problem of a batch: its tensor (z64; z32 too for CP_MIXED; norm2 set,
+ * e.g. by cp_norm2) and one factor set of rank restarts * R holding every
+ * restart side by side: restart k owns columns [k R, (k + 1) R) of each A^(n)
+ * (FP64, plus FP32 shadows for CP_MIXED), initialised by the caller. */
+typedef struct {
+  cp_tensor z;
+  cp_factors a;
+} cp_batch_problem;
+
+/* Stopping rules of a batched solve, applied per restart after every sweep
+ * (fit = 1 - sqrt(2 f / ||Z||^2) from the fused objective of the sweep):
+ *   CP_MIXED: FP32-contraction sweeps in windows of `window32` sweeps until
+ *   (fit_last - fit_first) / (window32 - 1) <= tol32 * fit_last over a window,
+ *   then FP64 sweeps (all restarts of the problem together) until
+ *   |fit_k - fit_{k-1}| <= tol64 * fit_k;  CP_FP64: the FP64 phase only.
+ * A restart stops after max_sweeps sweeps over both phases (at least one FP64
+ * sweep runs in the mixed form).  `chunk` sweeps are enqueued between two host
+ * checks of whether any restart still runs. */
+typedef struct {
+  int32_t restarts;   /* 1..CP_MAX_RESTARTS, restarts * R <= CP_MAX_RANK */
+  cp_prec prec;
+  int32_t window32;   /* >= 2 */
+  double tol32;
+  double tol64;
+  int32_t max_sweeps; /* >= 1 */
+  int32_t chunk;      /* >= 1 */
+} cp_batch_params;
+
+/* Batched form of the ALS solve (Section 3, stopping as in cp_batch_params):
+ * `nprob` independent problems (host array of descriptors with device
+ * pointers), each with `restarts` starts that share every pass over their
+ * tensor: the MTTKRP of a problem runs at rank restarts * R and Gamma is kept
+ * block-diagonal, so the restarts never couple.  One launch per mode covers
+ * every problem.  The factor sets are updated in place (normalized as in
+ * eq. (10), not sorted).  Outputs (device, optional): fits[b * restarts + k],
+ * the fit after the last sweep of restart k of problem b (fused objective);
+ * sweeps[(b * restarts + k) * 2 + phase], sweeps run in the FP32 (0) and FP64
+ * (1) phases.  Blocks until every restart has stopped.  Errors: invalid
+ * descriptors or parameters (nothing enqueued), a contracted mode too large
+ * to stage in LDS (CP_ERR_UNSUPPORTED). */
+cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, int32_t nprob,
+                         const cp_batch_params* params, double* fits, int32_t* sweeps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,6 +9,7 @@ import os
 
 CP_MAX_ORDER = 8
 CP_MAX_RANK = 32
+CP_MAX_RESTARTS = 8
 
 CP_OK = 0
 CP_ERR_INVALID = -1
@@ -57,6 +58,15 @@ class CpFasParams(ctypes.Structure):
                 ("ic_rule", c_i32)]
 
 
+class CpBatchProblem(ctypes.Structure):
+    _fields_ = [("z", CpTensor), ("a", CpFactors)]
+
+
+class CpBatchParams(ctypes.Structure):
+    _fields_ = [("restarts", c_i32), ("prec", c_i32), ("window32", c_i32), ("tol32", ctypes.c_double),
+                ("tol64", ctypes.c_double), ("max_sweeps", c_i32), ("chunk", c_i32)]
+
+
 # name -> (argtypes)
 SIGNATURES = {
     "cp_ctx_create": [ctypes.POINTER(c_vp), c_vp],
@@ -84,6 +94,8 @@ SIGNATURES = {
     "cp_time_mttkrp": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_i32,
                        c_i32, ctypes.POINTER(ctypes.c_double)],
     "cp_profile_read": [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i32)],
+    "cp_als_batched": [c_vp, ctypes.POINTER(CpBatchProblem), c_i32, ctypes.POINTER(CpBatchParams),
+                       c_vp, c_vp],
 }
 
 _lib = None

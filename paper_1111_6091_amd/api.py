@@ -11,8 +11,8 @@ import ctypes
 import numpy as np
 
 from . import _lib as L
-from ._lib import (CP_FP64, CP_MIXED, CP_SOLVE_CHOL, CP_SOLVE_GS, CpFactors, CpFasParams,
-                   CpLevel, CpTensor)
+from ._lib import (CP_FP64, CP_MIXED, CP_SOLVE_CHOL, CP_SOLVE_GS, CpBatchParams, CpBatchProblem,
+                   CpFactors, CpFasParams, CpLevel, CpTensor)
 
 
 class CpError(RuntimeError):
@@ -278,3 +278,22 @@ def cp_sort(ctx, A):
     dims = (ctypes.c_int64 * L.CP_MAX_ORDER)(*A.dims)
     fs = A.struct()
     ctx.check(ctx._lib.cp_sort(ctx.handle, dims, len(A.mats), ctypes.byref(fs)))
+
+
+def cp_als_batched(ctx, problems, restarts, prec=CP_MIXED, window32=16, tol32=1e-9, tol64=1e-12,
+                   max_sweeps=10000, chunk=16):
+    """Batched ALS solves: ``problems`` is a list of (DeviceTensor, DeviceFactors) where the
+    factors have rank restarts * R (restart k in columns k*R..(k+1)*R-1).  Returns device
+    tensors (fits [nprob, restarts], sweeps [nprob, restarts, 2])."""
+    torch = _torch()
+    n = len(problems)
+    arr = (CpBatchProblem * n)()
+    for i, (Z, A) in enumerate(problems):
+        arr[i].z = Z.struct()
+        arr[i].a = A.struct()
+    prm = CpBatchParams(restarts, prec, window32, tol32, tol64, max_sweeps, chunk)
+    dev = problems[0][0].z64.device
+    fits = torch.empty((n, restarts), dtype=torch.float64, device=dev)
+    sweeps = torch.empty((n, restarts, 2), dtype=torch.int32, device=dev)
+    ctx.check(ctx._lib.cp_als_batched(ctx.handle, arr, n, ctypes.byref(prm), _ptr(fits), _ptr(sweeps)))
+    return fits, sweeps

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <limits>
 #include <map>
 #include <sstream>
 #include <string>
@@ -1130,5 +1131,376 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
   if ((s = fas_vcycle_rec(r, 0)) != CP_OK) return s;
   if (r.lv[0].has32)   // shadows of the finest factors follow the last correction
     TRY(enqueue_gram(ctx, A->a, A->a32, r.lv[0].dims, N, R, r.lv[0].grams));
+  return CP_OK;
+}
+
+// ===========================================================================
+// Batched solves
+// ===========================================================================
+namespace {
+
+// Tensor bytes one streaming workgroup of a batched MTTKRP aims to cover.
+constexpr int64_t kBatchBytesPerWg = 192 * 1024;
+
+struct BatchPhase {           // device arrays of one phase (FP32 or FP64 contractions)
+  MttkrpDesc* md = nullptr;   // [(N + 1) * nprob]: set 0 = first sweep of a chunk, mode 0;
+                              // set 1 + n = mode n of the other sweeps
+  EpiDesc* ed = nullptr;      // [N * nprob]
+  PrepArgs* fin = nullptr;    // [nprob]
+  std::vector<std::vector<int2*>> mtiles;   // [set][nt-1]
+  std::vector<std::vector<int>> mcount;
+  std::vector<std::vector<size_t>> msmem;
+  std::vector<int2*> etiles;                // [n]
+  std::vector<int> ecount;
+};
+
+}  // namespace
+
+extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, int32_t nprob,
+                                    const cp_batch_params* prm, double* fits, int32_t* sweeps) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (!probs || nprob < 1) return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: no problems");
+  if (!prm) return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: params NULL");
+  cp_status s = check_prec(ctx, prm->prec);
+  if (s != CP_OK) return s;
+  const int G = prm->restarts;
+  if (G < 1 || G > CP_MAX_RESTARTS || G > kMaxGroups)
+    return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: restarts %d outside [1, %d]", G, CP_MAX_RESTARTS);
+  if (prm->window32 < 2 || prm->max_sweeps < 1 || prm->chunk < 1 || !(prm->tol32 >= 0.0) ||
+      !(prm->tol64 >= 0.0))
+    return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: window32 >= 2, max_sweeps >= 1, chunk >= 1 "
+                                        "and non-negative tolerances required");
+  const bool mixed = prm->prec == CP_MIXED;
+  int N = 0;
+  for (int b = 0; b < nprob; ++b) {
+    const cp_batch_problem& pb = probs[b];
+    if ((s = check_tensor(ctx, &pb.z, true, mixed, "problem tensor")) != CP_OK) return s;
+    if (b == 0) N = pb.z.order;
+    if (pb.z.order != N)
+      return set_err(ctx, CP_ERR_SHAPE, "cp_als_batched: problem %d has order %d, problem 0 has %d", b,
+                     pb.z.order, N);
+    if (!pb.z.norm2) return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: problem %d: norm2 NULL", b);
+    if ((s = check_factors(ctx, &pb.a, N, mixed, "problem factors")) != CP_OK) return s;
+    if (pb.a.rank % G != 0)
+      return set_err(ctx, CP_ERR_SHAPE, "cp_als_batched: problem %d: rank %d is not a multiple of %d restarts",
+                     b, pb.a.rank, G);
+  }
+  const int nphase = mixed ? 2 : 1;
+  const int nsets = N + 1;
+
+  // ---- launch plans, per problem, mode and phase -------------------------
+  // plans[ph][b * N + n]
+  std::vector<std::vector<MttkrpPlan>> plans(nphase, std::vector<MttkrpPlan>((size_t)nprob * N));
+  std::vector<size_t> maxpart(nprob, 0);
+  for (int ph = 0; ph < nphase; ++ph) {
+    const bool fp32 = mixed && ph == 0;
+    for (int b = 0; b < nprob; ++b) {
+      const cp_batch_problem& pb = probs[b];
+      int64_t P = 1;
+      for (int m = 0; m < N; ++m) P *= pb.z.dims[m];
+      const int64_t bytes = P * (fp32 ? 4 : 8);
+      const int target = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (bytes + kBatchBytesPerWg - 1) /
+                                                                                   kBatchBytesPerWg));
+      for (int n = 0; n < N; ++n) {
+        MttkrpPlan p = mttkrp_plan(N, pb.z.dims, n, pb.a.rank, fp32, PlanOpts{target, 0, 2, 4});
+        if (!p.bl)
+          return set_err(ctx, CP_ERR_UNSUPPORTED,
+                         "cp_als_batched: problem %d: contracted mode too large to stage in LDS", b);
+        plans[ph][(size_t)b * N + n] = p;
+        maxpart[b] = std::max(maxpart[b], p.partial_doubles);
+      }
+    }
+  }
+
+  // ---- tiles (host) --------------------------------------------------------
+  struct HostPhase {
+    std::vector<std::vector<std::vector<int2>>> mt;   // [set][nt-1]
+    std::vector<std::vector<size_t>> msmem;
+    std::vector<std::vector<int2>> et;                // [n]
+  };
+  std::vector<HostPhase> hp(nphase);
+  for (int ph = 0; ph < nphase; ++ph) {
+    HostPhase& h = hp[ph];
+    h.mt.assign(nsets, std::vector<std::vector<int2>>(2));
+    h.msmem.assign(nsets, std::vector<size_t>(2, 0));
+    h.et.assign(N, {});
+    for (int set = 0; set < nsets; ++set) {
+      const int n = set == 0 ? 0 : set - 1;
+      for (int b = 0; b < nprob; ++b) {
+        const MttkrpPlan& p = plans[ph][(size_t)b * N + n];
+        const int nt = p.nt;
+        const int64_t grid = (int64_t)p.ngroups * p.nsplit + 1;
+        for (int64_t t = 0; t < grid; ++t) h.mt[set][nt - 1].push_back(int2{set * nprob + b, (int)t});
+        h.msmem[set][nt - 1] =
+            std::max(h.msmem[set][nt - 1], mttkrp_smem_bytes(p, N, probs[b].a.rank, true));
+      }
+    }
+    for (int n = 0; n < N; ++n)
+      for (int b = 0; b < nprob; ++b) {
+        const int64_t nb = epi_blocks(probs[b].z.dims[n]);
+        for (int64_t t = 0; t < nb; ++t) h.et[n].push_back(int2{n * nprob + b, (int)t});
+      }
+  }
+
+  // ---- workspace -----------------------------------------------------------
+  std::vector<double*> grams(nprob), sigma(nprob), part(nprob), scal(nprob), pout(nprob);
+  std::vector<int32_t*> ckind(nprob);
+  BatchState* states = nullptr;
+  BatchRule* rules = nullptr;
+  std::vector<BatchPhase> dp(nphase);
+  GramJob* jobs = nullptr;
+  int smem_fin = 0;
+  auto carve = [&](auto& c, bool real) {
+    for (int b = 0; b < nprob; ++b) {
+      const int R = probs[b].a.rank;
+      double* g = c.template take<double>((size_t)N * R * R);
+      double* sg = c.template take<double>((size_t)N * R);
+      double* pt = c.template take<double>(maxpart[b]);
+      double* sc = c.template take<double>((size_t)epi_blocks(probs[b].z.dims[N - 1]) * G);
+      double* po = c.template take<double>((size_t)R * R + 2 * R);
+      int32_t* ck = c.template take<int32_t>(1);
+      if (real) { grams[b] = g; sigma[b] = sg; part[b] = pt; scal[b] = sc; pout[b] = po; ckind[b] = ck; }
+    }
+    BatchState* stp = c.template take<BatchState>((size_t)nprob);
+    BatchRule* ru = c.template take<BatchRule>(2);
+    GramJob* jb = c.template take<GramJob>((size_t)nprob * N);
+    if (real) { states = stp; rules = ru; jobs = jb; }
+    for (int ph = 0; ph < nphase; ++ph) {
+      MttkrpDesc* md = c.template take<MttkrpDesc>((size_t)nsets * nprob);
+      EpiDesc* ed = c.template take<EpiDesc>((size_t)N * nprob);
+      PrepArgs* fin = c.template take<PrepArgs>((size_t)nprob);
+      if (real) { dp[ph].md = md; dp[ph].ed = ed; dp[ph].fin = fin; }
+      if (real) {
+        dp[ph].mtiles.assign(nsets, std::vector<int2*>(2, nullptr));
+        dp[ph].mcount.assign(nsets, std::vector<int>(2, 0));
+        dp[ph].msmem = hp[ph].msmem;
+        dp[ph].etiles.assign(N, nullptr);
+        dp[ph].ecount.assign(N, 0);
+      }
+      for (int set = 0; set < nsets; ++set)
+        for (int q = 0; q < 2; ++q) {
+          int2* t = c.template take<int2>(hp[ph].mt[set][q].size());
+          if (real) { dp[ph].mtiles[set][q] = t; dp[ph].mcount[set][q] = (int)hp[ph].mt[set][q].size(); }
+        }
+      for (int n = 0; n < N; ++n) {
+        int2* t = c.template take<int2>(hp[ph].et[n].size());
+        if (real) { dp[ph].etiles[n] = t; dp[ph].ecount[n] = (int)hp[ph].et[n].size(); }
+      }
+    }
+  };
+  Sizer sz;
+  carve(sz, false);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  carve(ar, true);
+  for (int b = 0; b < nprob; ++b) smem_fin = std::max(smem_fin, prep_smem_doubles(N, probs[b].a.rank));
+
+  // ---- descriptors (host), then one upload --------------------------------
+  BatchRule hr[2];
+  for (int ph = 0; ph < 2; ++ph) {
+    hr[ph] = BatchRule{};
+    hr[ph].phase = ph;
+    hr[ph].window = prm->window32;
+    hr[ph].tol32 = prm->tol32;
+    hr[ph].tol64 = prm->tol64;
+    hr[ph].max_sweeps = prm->max_sweeps;
+  }
+  auto phase_rule = [&](int ph) { return rules + ((mixed && ph == 0) ? 0 : 1); };
+  std::vector<GramJob> hjobs((size_t)nprob * N);
+  for (int b = 0; b < nprob; ++b)
+    for (int n = 0; n < N; ++n) {
+      const int R = probs[b].a.rank;
+      GramJob j{};
+      j.A = probs[b].a.a[n];
+      j.A32 = mixed ? probs[b].a.a32[n] : nullptr;
+      j.I = probs[b].z.dims[n];
+      j.R = R;
+      j.gram = grams[b] + (size_t)n * R * R;
+      j.sigma = sigma[b] + (size_t)n * R;
+      j.st = states + b;
+      hjobs[(size_t)b * N + n] = j;
+    }
+  std::vector<std::vector<MttkrpDesc>> hmd(nphase);
+  std::vector<std::vector<EpiDesc>> hed(nphase);
+  std::vector<std::vector<PrepArgs>> hfin(nphase);
+  for (int ph = 0; ph < nphase; ++ph) {
+    const bool fp32 = mixed && ph == 0;
+    hmd[ph].resize((size_t)nsets * nprob);
+    hed[ph].resize((size_t)N * nprob);
+    hfin[ph].resize(nprob);
+    for (int b = 0; b < nprob; ++b) {
+      const cp_batch_problem& pb = probs[b];
+      const int R = pb.a.rank;
+      auto base = [&](int n) {
+        PrepArgs pa{};
+        pa.N = N;
+        pa.n = n;
+        pa.R = R;
+        pa.grams = grams[b];
+        pa.sigma = sigma[b];
+        pa.out = pout[b];
+        pa.kind = ckind[b];
+        pa.flags = ctx->flags;
+        pa.solver = CP_SOLVE_CHOL;
+        pa.normalize = 1;
+        pa.norm2 = pb.z.norm2;
+        pa.inner_part = scal[b];
+        pa.inner_count = (int32_t)epi_blocks(pb.z.dims[N - 1]);
+        pa.groups = G;
+        pa.st = states + b;
+        pa.rule = phase_rule(ph);
+        return pa;
+      };
+      const void* z = fp32 ? (const void*)pb.z.z32 : (const void*)pb.z.z64;
+      for (int set = 0; set < nsets; ++set) {
+        const int n = set == 0 ? 0 : set - 1;
+        PrepArgs pa = base(n);
+        if (set == 0) {
+          pa.p = -1;
+        } else {
+          pa.p = (n + N - 1) % N;
+          pa.Ap = pb.a.a[pa.p];
+          pa.Ip = pb.z.dims[pa.p];
+          pa.boundary = n == 0 ? 1 : 0;
+        }
+        hmd[ph][(size_t)set * nprob + b] =
+            mttkrp_desc(plans[ph][(size_t)b * N + n], pb.z.dims, N, n, R, z, fp32, pb.a.a,
+                        (const float* const*)pb.a.a32, part[b], &pa);
+      }
+      for (int n = 0; n < N; ++n) {
+        EpiDesc d{};
+        d.op = EPI_UPDATE;
+        d.solver = CP_SOLVE_CHOL;
+        d.gs_iters = 10;
+        d.R = R;
+        d.N = N;
+        d.n = n;
+        d.nsplit = plans[ph][(size_t)b * N + n].nsplit;
+        d.In = pb.z.dims[n];
+        d.partial = part[b];
+        d.A = pb.a.a[n];
+        d.A32 = mixed ? pb.a.a32[n] : nullptr;
+        d.grams = grams[b];
+        d.prep_out = pout[b];
+        d.kind = ckind[b];
+        d.scal_part = scal[b];
+        d.flags = ctx->flags;
+        d.want_obj = n == N - 1 ? 1 : 0;
+        d.groups = G;
+        d.st = states + b;
+        hed[ph][(size_t)n * nprob + b] = d;
+      }
+      PrepArgs fa = base(0);
+      fa.p = N - 1;
+      fa.Ap = pb.a.a[N - 1];
+      fa.Ip = pb.z.dims[N - 1];
+      fa.boundary = 1;
+      for (int m = 0; m < N; ++m) {
+        fa.A[m] = pb.a.a[m];
+        fa.A32[m] = mixed ? pb.a.a32[m] : nullptr;
+        fa.dims[m] = pb.z.dims[m];
+      }
+      hfin[ph][b] = fa;
+    }
+  }
+  std::vector<BatchState> hst(nprob);
+  auto init_states = [&](int phase, bool first) {
+    for (int b = 0; b < nprob; ++b) {
+      BatchState& x = hst[b];
+      if (first) x = BatchState{};
+      x.active = 1;
+      x.sweep = 0;
+      for (int g = 0; g < kMaxGroups; ++g) {
+        x.frozen[g] = g < G ? 0 : 1;
+        x.fit_prev[g] = std::numeric_limits<double>::quiet_NaN();
+        if (first) x.fit[g] = x.fit_win[g] = std::numeric_limits<double>::quiet_NaN();
+      }
+    }
+    (void)phase;
+  };
+  init_states(0, true);
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipMemcpyAsync(rules, hr, sizeof(hr), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(jobs, hjobs.data(), hjobs.size() * sizeof(GramJob), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(states, hst.data(), hst.size() * sizeof(BatchState), hipMemcpyHostToDevice, st));
+  for (int ph = 0; ph < nphase; ++ph) {
+    HIPCHK(hipMemcpyAsync(dp[ph].md, hmd[ph].data(), hmd[ph].size() * sizeof(MttkrpDesc),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dp[ph].ed, hed[ph].data(), hed[ph].size() * sizeof(EpiDesc),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dp[ph].fin, hfin[ph].data(), hfin[ph].size() * sizeof(PrepArgs),
+                          hipMemcpyHostToDevice, st));
+    for (int set = 0; set < nsets; ++set)
+      for (int q = 0; q < 2; ++q)
+        if (!hp[ph].mt[set][q].empty())
+          HIPCHK(hipMemcpyAsync(dp[ph].mtiles[set][q], hp[ph].mt[set][q].data(),
+                                hp[ph].mt[set][q].size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    for (int n = 0; n < N; ++n)
+      if (!hp[ph].et[n].empty())
+        HIPCHK(hipMemcpyAsync(dp[ph].etiles[n], hp[ph].et[n].data(), hp[ph].et[n].size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));   // host arrays may go once the uploads are done
+
+  // ---- phases ------------------------------------------------------------------
+  const int kinds[3] = {1, 2, 3};
+  for (int ph = 0; ph < nphase; ++ph) {
+    const bool fp32 = mixed && ph == 0;
+    if (ph > 0) {
+      // the FP64 phase restarts every restart of every problem
+      HIPCHK(hipMemcpy(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost));
+      init_states(1, false);
+      HIPCHK(hipMemcpyAsync(states, hst.data(), hst.size() * sizeof(BatchState), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    const BatchPhase& d = dp[ph];
+    for (int done = 0; done < prm->max_sweeps;) {
+      const int K = std::min(prm->chunk, prm->max_sweeps - done);
+      {
+        ProfScope ps(ctx, CP_PROF_GRAM);
+        HIPCHK(gram_batched_launch(jobs, nprob * N, st));
+      }
+      for (int k = 0; k < K; ++k)
+        for (int n = 0; n < N; ++n) {
+          const int set = (k == 0 && n == 0) ? 0 : n + 1;
+          {
+            ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + kinds[std::min(n, 2)] - 1);
+            for (int q = 0; q < 2; ++q)
+              HIPCHK(mttkrp_batched_launch(kinds[std::min(n, 2)], fp32, q + 1, d.md, d.mtiles[set][q],
+                                           d.mcount[set][q], d.msmem[set][q], st));
+          }
+          ProfScope ps(ctx, CP_PROF_UPDATE);
+          HIPCHK(epi_batched_launch(d.ed, d.etiles[n], d.ecount[n], st));
+        }
+      {
+        ProfScope ps(ctx, CP_PROF_NORMALIZE);
+        HIPCHK(finalize_batched_launch(d.fin, nprob, smem_fin, st));
+      }
+      done += K;
+      HIPCHK(hipMemcpyAsync(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool any = false;
+      for (int b = 0; b < nprob && !any; ++b) any = hst[b].active != 0;
+      if (!any) break;
+    }
+  }
+
+  // ---- outputs -------------------------------------------------------------------
+  HIPCHK(hipMemcpy(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost));
+  if (fits) {
+    std::vector<double> hf((size_t)nprob * G);
+    for (int b = 0; b < nprob; ++b)
+      for (int g = 0; g < G; ++g) hf[(size_t)b * G + g] = hst[b].fit[g];
+    HIPCHK(hipMemcpyAsync(fits, hf.data(), hf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (sweeps) {
+    std::vector<int32_t> hs((size_t)nprob * G * 2);
+    for (int b = 0; b < nprob; ++b)
+      for (int g = 0; g < G; ++g)
+        for (int q = 0; q < 2; ++q) hs[((size_t)b * G + g) * 2 + q] = hst[b].sweeps[q][g];
+    HIPCHK(hipMemcpyAsync(sweeps, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   return CP_OK;
 }

@@ -32,6 +32,37 @@ template <> __device__ __forceinline__ constexpr int mfma_row<float>(int g, int 
 //   kind 2 (n == 1): GEMM rows = i1, contraction over i0, Hadamard weight per stripe
 //   kind 3 (n >= 2): GEMM rows = i1, contraction over i0, Hadamard-reduce of the
 //                    rows with A^(1) and the stripe weight into output row s_n
+// Batched solves: per-problem device state of the stopping rules.  A problem
+// carries `groups` independent restarts of rank R/groups side by side (their
+// factor blocks are the column groups of one rank-R factor set); Gamma is kept
+// block-diagonal over the groups, so the restarts never couple.
+constexpr int kMaxGroups = 8;
+
+struct BatchRule {
+  int32_t phase;        // 0: FP32 phase (window rule), 1: FP64 phase (per-sweep rule)
+  int32_t window;       // FP32 phase: sweeps per window
+  double tol32;         // FP32 phase: (fit_end - fit_start) / (window - 1) <= tol32 * fit_end
+  double tol64;         // FP64 phase: |fit_k - fit_{k-1}| <= tol64 * fit_k
+  int32_t max_sweeps;   // cap on the sweeps of one restart over both phases
+};
+
+struct BatchState {
+  int32_t active;                 // some group still iterates in the current phase
+  int32_t sweep;                  // sweeps completed in the current phase
+  int32_t frozen[kMaxGroups];     // group stopped in the current phase
+  int32_t sweeps[2][kMaxGroups];  // sweeps per phase and group
+  double fit[kMaxGroups];         // fit after the group's last sweep (fused objective)
+  double fit_prev[kMaxGroups];    // fit after the previous sweep (NaN: none yet)
+  double fit_win[kMaxGroups];     // FP32 phase: fit at the first sweep of the window
+};
+
+constexpr int kGramTile = 512;   // doubles of a factor staged per round by the bookkeeping Gram
+
+// Doubles of LDS the bookkeeping step (sweep.hpp) needs for order N and rank R.
+__host__ __device__ constexpr int prep_smem_doubles(int N, int R) {
+  return 5 * R * R + N * R + kGramTile;
+}
+
 // Per-mode bookkeeping done by the extra first workgroup of an MTTKRP launch
 // (or by the finalize kernel at the end of a call); see sweep.hpp.
 struct PrepArgs {
@@ -54,6 +85,9 @@ struct PrepArgs {
   double* A[kMaxOrder];     // finalize: factors to scale
   float* A32[kMaxOrder];
   int64_t dims[kMaxOrder];
+  int32_t groups;           // column groups (independent restarts); 0 or 1: one group
+  BatchState* st;           // batched solves: stopping state (NULL otherwise)
+  const BatchRule* rule;
 };
 
 struct MttkrpDesc {
@@ -80,6 +114,7 @@ struct MttkrpDesc {
   int32_t rgroups;                // kind 3: number of row groups over I1
   int64_t rest_count;             // kind 3: number of stripes per output value
   int32_t prep;                   // 1: workgroup 0 runs sweep_prep(pa) instead of streaming
+  int32_t vec;                    // 4-wide tensor loads allowed (I0 % 4 == 0, aligned base)
   PrepArgs pa;
 };
 
@@ -110,6 +145,17 @@ hipError_t mttkrp_launch(const MttkrpPlan& plan, const int64_t* dims, int N, int
                          const void* z, bool fp32, const double* const* a64,
                          const float* const* a32, double* out, const PrepArgs* prep,
                          hipStream_t st);
+// The launch descriptor mttkrp_launch would use (for batched launches).
+MttkrpDesc mttkrp_desc(const MttkrpPlan& plan, const int64_t* dims, int N, int n, int R,
+                       const void* z, bool fp32, const double* const* a64,
+                       const float* const* a32, double* out, const PrepArgs* prep);
+// dynamic LDS bytes of a launch of `plan` (with or without the bookkeeping workgroup)
+size_t mttkrp_smem_bytes(const MttkrpPlan& p, int N, int R, bool prep);
+// Batched MTTKRPs of one mode: tile t runs workgroup tiles[t].y of descs[tiles[t].x]
+// (device arrays; 16-column tiles nt = 1 or 2 for every listed problem, the
+// contracted factor staged in LDS, rows per wave 2, 4-wide lanes).
+hipError_t mttkrp_batched_launch(int kind, bool fp32, int nt, const MttkrpDesc* descs,
+                                 const int2* tiles, int ntiles, size_t smem_bytes, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Mode epilogue: reduce MTTKRP partials and act on the rows
@@ -133,7 +179,9 @@ struct EpiDesc {
   double* grams;              // [N][R][R]  (Upsilon of each mode)
   const double* prep_out;     // EPI_UPDATE: [R*R + 2R] from sweep_prep
   const int32_t* kind;        // EPI_UPDATE: 0 Cholesky factor, 1 pseudoinverse, 2 Gamma (GS)
-  double* scal_part;          // [nwg] workspace
+  double* scal_part;          // [nwg] workspace (x groups for EPI_UPDATE with want_obj)
+  int32_t groups;             // EPI_UPDATE: column groups (0 or 1: one group)
+  const BatchState* st;       // EPI_UPDATE in a batched solve: skip frozen groups
   int32_t* counter;           // last-block counter (zero between launches)
   double* scalar_out;         // objective: f_hist slot; grad: accumulator
   const double* norm2;        // ||Z||^2 (device)
@@ -144,10 +192,26 @@ struct EpiDesc {
 
 hipError_t epi_launch(const EpiDesc& d, hipStream_t st);
 int epi_rows_per_wg();
+// batched: tile t runs block tiles[t].y of the epilogue descs[tiles[t].x] (device arrays)
+hipError_t epi_batched_launch(const EpiDesc* descs, const int2* tiles, int ntiles, hipStream_t st);
+
+// Batched Gram jobs (one mode of one problem each)
+struct GramJob {
+  const double* A;
+  float* A32;           // refreshed from A when set
+  int64_t I;
+  int32_t R;
+  double* gram;         // R x R output
+  double* sigma;        // R column scales reset to 1 when set
+  const BatchState* st; // skip when the problem is inactive
+};
+hipError_t gram_batched_launch(const GramJob* jobs, int njobs, hipStream_t st);
 
 // End of a sweep sequence: Gram of the last mode, fused objective, and the
 // pending normalization applied to the stored factors (one workgroup).
 hipError_t finalize_launch(const PrepArgs& a, hipStream_t st);
+// batched: one workgroup per problem (device array of PrepArgs)
+hipError_t finalize_batched_launch(const PrepArgs* pas, int nprob, int smem_doubles, hipStream_t st);
 
 // Grams of every mode at fixed A; optionally refresh FP32 shadows and reset the
 // pending normalization scales (sigma, N x R) to 1

@@ -163,8 +163,8 @@ __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, 
 // Workgroup 0 of a launch with prep set does the sweep bookkeeping for the
 // update that follows (sweep.hpp), concurrently with the streaming workgroups;
 // it is dispatched first, so it is resident from the start.
-__device__ __forceinline__ bool prep_block(const MttkrpDesc& d, double* smem) {
-  if (!d.prep || blockIdx.x != 0) return false;
+__device__ __forceinline__ bool prep_block(const MttkrpDesc& d, int blk, double* smem) {
+  if (!d.prep || blk != 0) return false;
   sweep_prep(d.pa, smem, false);
   return true;
 }
@@ -179,17 +179,16 @@ constexpr int kind23_smem(int TW, int NT, bool k3) { return k3 ? 4 * 16 * NT : 4
 // over i1 on the matrix cores, Hadamard weight per stripe in FP64.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int VW, bool VEC, bool BL>
-__global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
+__device__ __forceinline__ void kind1_body(const MttkrpDesc& d, int blk, double* smem) {
   typedef typename Vec4<T>::type V;
   constexpr int PANEL = 16 * VW;
   // 16 lanes x 16 bytes cover two whole lines only for 4-wide FP32 loads
   constexpr bool NTH = sizeof(T) == 4 && VW == 4;
-  extern __shared__ double smem[];
-  if (prep_block(d, smem)) return;
+  if (prep_block(d, blk, smem)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
-  const int bid = blockIdx.x - d.prep;
+  const int bid = blk - d.prep;
   const int grp = bid % d.ngroups;
   const int split = bid / d.ngroups;
   const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
@@ -326,16 +325,15 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
 // (n >= 2): rows are reduced with A^(1)(i1, r) into output s_n.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL>
-__global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
+__device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double* smem) {
   typedef typename Vec4<T>::type V;
   constexpr int KC = 4 * VW;   // contraction chunk per step of the loop
   constexpr int ROWS = 16 * TW;
-  extern __shared__ double smem[];
-  if (prep_block(d, smem)) return;
+  if (prep_block(d, blk, smem)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
-  const int bid = blockIdx.x - d.prep;
+  const int bid = blk - d.prep;
   const int grp = bid % d.ngroups;
   const int split = bid / d.ngroups;
   const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
@@ -531,6 +529,38 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   }
 }
 
+template <typename T, int NT, int VW, bool VEC, bool BL>
+__global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
+  extern __shared__ double smem[];
+  kind1_body<T, NT, VW, VEC, BL>(d, blockIdx.x, smem);
+}
+
+template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL>
+__global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
+  extern __shared__ double smem[];
+  kind23_body<T, NT, TW, KIND3, VW, VEC, BL>(d, blockIdx.x, smem);
+}
+
+// Batched MTTKRPs (one mode of many problems in one launch): tile t runs
+// workgroup tiles[t].y of the launch described by descs[tiles[t].x].  Every
+// problem stages its contracted factor in LDS; 4-wide loads where the problem
+// allows them.  Tiles of problems with nothing left in the current phase exit.
+template <typename T, int NT, int KIND>
+__global__ __launch_bounds__(kThreads) void mttkrp_batched(const MttkrpDesc* __restrict__ descs,
+                                                           const int2* __restrict__ tiles) {
+  extern __shared__ double smem[];
+  const int2 t = tiles[blockIdx.x];
+  const MttkrpDesc& d = descs[t.x];
+  if (d.pa.st && !d.pa.st->active) return;
+  if (KIND == 1) {
+    if (d.vec) kind1_body<T, NT, 4, true, true>(d, t.y, smem);
+    else kind1_body<T, NT, 4, false, true>(d, t.y, smem);
+  } else {
+    if (d.vec) kind23_body<T, NT, 2, KIND == 3, 4, true, true>(d, t.y, smem);
+    else kind23_body<T, NT, 2, KIND == 3, 4, false, true>(d, t.y, smem);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side: planning and dispatch
 // ---------------------------------------------------------------------------
@@ -654,10 +684,37 @@ int mttkrp_capacity(const MttkrpPlan& p, bool fp32) {
   return nb * cus;
 }
 
+template <typename T, int NT>
+static const void* batched_ptr(int kind) {
+  if (kind == 1) return (const void*)mttkrp_batched<T, NT, 1>;
+  if (kind == 2) return (const void*)mttkrp_batched<T, NT, 2>;
+  return (const void*)mttkrp_batched<T, NT, 3>;
+}
+
+hipError_t mttkrp_batched_launch(int kind, bool fp32, int nt, const MttkrpDesc* descs,
+                                 const int2* tiles, int ntiles, size_t smem_bytes, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  const void* k = fp32 ? (nt == 1 ? batched_ptr<float, 1>(kind) : batched_ptr<float, 2>(kind))
+                       : (nt == 1 ? batched_ptr<double, 1>(kind) : batched_ptr<double, 2>(kind));
+  void* args[] = {(void*)&descs, (void*)&tiles};
+  return hipLaunchKernel(k, dim3((unsigned)ntiles), dim3(kThreads), args, smem_bytes, st);
+}
+
 hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
                          const void* z, bool fp32, const double* const* a64,
                          const float* const* a32, double* out, const PrepArgs* prep,
                          hipStream_t st) {
+  MttkrpDesc d = mttkrp_desc(p, dims, N, n, R, z, fp32, a64, a32, out, prep);
+  const void* k = select_kernel(p, fp32, d.vec != 0);
+  if (!k) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
+  void* args[] = {&d};
+  return hipLaunchKernel(k, grid, block, args, mttkrp_smem_bytes(p, N, R, d.prep != 0), st);
+}
+
+MttkrpDesc mttkrp_desc(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
+                       const void* z, bool fp32, const double* const* a64,
+                       const float* const* a32, double* out, const PrepArgs* prep) {
   MttkrpDesc d{};
   if (prep) {
     d.prep = 1;
@@ -695,13 +752,8 @@ hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n,
   // 4-wide vector loads need the contiguous extent to be a multiple of 4 and
   // an aligned base
   const size_t esz = fp32 ? 4 : 8;
-  const bool vec = (dims[0] % 4 == 0) && (((uintptr_t)z) % (4 * esz) == 0);
-  (void)esz;
-  const void* k = select_kernel(p, fp32, vec);
-  if (!k) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
-  void* args[] = {&d};
-  return hipLaunchKernel(k, grid, block, args, mttkrp_smem_bytes(p, N, R, d.prep != 0), st);
+  d.vec = ((dims[0] % 4 == 0) && (((uintptr_t)z) % (4 * esz) == 0)) ? 1 : 0;
+  return d;
 }
 
 }  // namespace cpamg

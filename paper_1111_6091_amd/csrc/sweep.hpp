@@ -15,12 +15,6 @@
 
 namespace cpamg {
 
-constexpr int kGramTile = 512;   // doubles of a factor staged per round by gram_into
-
-// Doubles of LDS the bookkeeping step needs for order N and rank R.
-__host__ __device__ constexpr int prep_smem_doubles(int N, int R) {
-  return 5 * R * R + N * R + kGramTile;
-}
 
 // Block-wide sum of one double per thread; result valid in every thread.
 __device__ inline double wg_sum(double v, double* sred) {
@@ -104,12 +98,49 @@ __device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind
   __syncthreads();
 }
 
+// Stopping rules of a batched solve, applied by thread 0 after the sweep that
+// just ended (fits[g] of each group); see BatchRule.
+__device__ inline void batch_rules(BatchState* st, const BatchRule& ru, const double* fits, int NG) {
+  const int idx = st->sweep;   // index of the sweep that just ended, within the phase
+  bool any = false;
+  for (int g = 0; g < NG; ++g) {
+    if (st->frozen[g]) continue;
+    const double fit = fits[g];
+    st->sweeps[ru.phase][g] += 1;
+    bool stop = st->sweeps[0][g] + st->sweeps[1][g] >= ru.max_sweeps;
+    if (ru.phase == 0) {
+      const int w = idx % ru.window;
+      if (w == 0) st->fit_win[g] = fit;
+      else if (w == ru.window - 1 && (fit - st->fit_win[g]) / (ru.window - 1) <= ru.tol32 * fabs(fit))
+        stop = true;
+    } else {
+      const double fp = st->fit_prev[g];
+      if (fp == fp && fabs(fit - fp) <= ru.tol64 * fabs(fit)) stop = true;
+    }
+    st->fit_prev[g] = fit;
+    st->fit[g] = fit;
+    if (stop) st->frozen[g] = 1;
+    else any = true;
+  }
+  st->sweep = idx + 1;
+  st->active = any ? 1 : 0;
+}
+
 // The bookkeeping step; smem: prep_smem_doubles(N, R) doubles of LDS.  With finalize set,
 // the pending scales are applied to the stored factors and reset instead of
-// preparing an update.
+// preparing an update.  With a.groups > 1 the R columns form independent
+// groups: Gamma is block-diagonal, f is evaluated per group, and in a batched
+// solve (a.st) frozen groups are neither renormalized nor updated.
 __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
   __shared__ double sred[8];
+  __shared__ double sfit[kMaxGroups];
   const int R = a.R, N = a.N, n = a.n, RR = R * R, tid = threadIdx.x;
+  const int NG = a.groups > 1 ? a.groups : 1;
+  const int Rg = R / NG;
+  BatchState* st = a.st;
+  const bool active = !st || st->active;
+  if (!active && !finalize) return;   // nothing left to do in this phase
+  auto col_frozen = [&](int r) -> bool { return st && st->frozen[r / Rg]; };
   double* G = smem;
   double* S = G + RR;
   double* V = S + RR;
@@ -120,32 +151,40 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   for (int idx = tid; idx < N * R; idx += kThreads) sS[idx] = a.sigma[idx];
   if (a.p >= 0) gram_into(a.Ap, a.Ip, R, U, tile);
   __syncthreads();
-  if (a.p >= 0 && tid < R) sS[a.p * R + tid] = 1.0;   // the updated factor is normalized
+  // the updated factor is normalized (frozen groups kept their columns)
+  if (a.p >= 0 && tid < R && !col_frozen(tid)) sS[a.p * R + tid] = 1.0;
   __syncthreads();
   auto ups = [&](int m, int idx) -> double {
     return m == a.p ? U[idx] : a.grams[(size_t)m * RR + idx];
   };
-  if (a.boundary) {
-    if (a.f_slot) {
-      // f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1), normalized coordinates
-      double ip = 0.0;
-      for (int b = tid; b < a.inner_count; b += kThreads) ip += a.inner_part[b];
-      double h = 0.0;
-      for (int idx = tid; idx < RR; idx += kThreads) {
-        const int r = idx / R, c = idx % R;
-        double hh = 1.0;
-        for (int m = 0; m < N; ++m) hh *= sS[m * R + r] * sS[m * R + c] * ups(m, idx);
-        h += hh;
+  if (a.boundary && active) {
+    if (a.f_slot || st) {
+      // per group: f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1),
+      // in normalized coordinates
+      for (int g = 0; g < NG; ++g) {
+        double ip = 0.0;
+        for (int b = tid; b < a.inner_count; b += kThreads) ip += a.inner_part[(size_t)b * NG + g];
+        double h = 0.0;
+        for (int idx = tid; idx < Rg * Rg; idx += kThreads) {
+          const int r = g * Rg + idx / Rg, c = g * Rg + idx % Rg;
+          double hh = 1.0;
+          for (int m = 0; m < N; ++m) hh *= sS[m * R + r] * sS[m * R + c] * ups(m, r * R + c);
+          h += hh;
+        }
+        const double inner = wg_sum(ip, sred);
+        const double nrm = wg_sum(h, sred);
+        if (tid == 0) {
+          const double f = 0.5 * (*a.norm2 - 2.0 * inner + nrm);
+          if (a.f_slot) a.f_slot[g] = f;
+          sfit[g] = 1.0 - sqrt(fmax(2.0 * f, 0.0) / *a.norm2);
+        }
       }
-      const double inner = wg_sum(ip, sred);
-      const double nrm = wg_sum(h, sred);
-      if (tid == 0) *a.f_slot = 0.5 * (*a.norm2 - 2.0 * inner + nrm);
     }
     if (a.normalize) {
       // eq. (10): lambda_r = (prod_m ||a_r^(m)||)^(1/N); a component with a
       // zero column is left unchanged
       __syncthreads();
-      if (tid < R) {
+      if (tid < R && !col_frozen(tid)) {
         const int r = tid;
         double nr[kMaxOrder];
         bool ok = true;
@@ -160,6 +199,8 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
           for (int m = 0; m < N; ++m) sS[m * R + r] *= lam / nr[m];
       }
     }
+    __syncthreads();
+    if (st && tid == 0) batch_rules(st, *a.rule, sfit, NG);
   }
   __syncthreads();
   if (finalize) {
@@ -200,9 +241,12 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   // Gamma^(n) in normalized coordinates, column scale of M^(n), sigma^(n)
   for (int idx = tid; idx < RR; idx += kThreads) {
     const int r = idx / R, c = idx % R;
-    double g = 1.0;
-    for (int m = 0; m < N; ++m)
-      if (m != n) g *= sS[m * R + r] * sS[m * R + c] * ups(m, idx);
+    double g = 0.0;
+    if (r / Rg == c / Rg) {   // groups never couple
+      g = 1.0;
+      for (int m = 0; m < N; ++m)
+        if (m != n) g *= sS[m * R + r] * sS[m * R + c] * ups(m, idx);
+    }
     G[idx] = g;
   }
   if (tid < R) {

@@ -30,12 +30,12 @@ __device__ inline double block_sum(double v, double* sred) {
 
 // Last-block detection: every thread publishes its writes; returns true in all
 // threads of the block that arrives last.  The counter is reset by that block.
-__device__ inline bool arrive_last(int32_t* counter, int* s_flag) {
+__device__ inline bool arrive_last(int32_t* counter, int nblk, int* s_flag) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     const int prev = atomicAdd(counter, 1);
-    *s_flag = (prev == (int)gridDim.x - 1) ? 1 : 0;
+    *s_flag = (prev == nblk - 1) ? 1 : 0;
   }
   __syncthreads();
   const bool last = *s_flag != 0;
@@ -134,16 +134,19 @@ __device__ inline double wave_gs(double b, double x, const double* G, int R, int
   return x;
 }
 
-__global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
+// One block of rows of a mode epilogue; blk / nblk: this block's index and the
+// number of blocks of the epilogue (blk * EPI_ROWS is its first row).
+__device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
   __shared__ double sG[kMaxRank * kMaxRank];
   __shared__ double sM[EPI_ROWS * LDP];
   __shared__ double sT[16 * EPI_ROWS * kMaxRank];
   __shared__ double sC[2 * kMaxRank];
   __shared__ double sred[8];
   __shared__ int s_flag;
+  if (d.st && !d.st->active) return;   // batched solve: nothing left in this phase
   const int R = d.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * EPI_ROWS;
+  const int64_t row0 = (int64_t)blk * EPI_ROWS;
   const int nrows = (int)std::min<int64_t>(EPI_ROWS, d.In - row0);
   int kind = 0;
   if (d.op == EPI_UPDATE) {
@@ -181,10 +184,10 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
     }
     if (d.op == EPI_H) return;
     const double tot = block_sum(sq, sred);
-    if (tid == 0) d.scal_part[blockIdx.x] = tot;
-    if (arrive_last(d.counter, &s_flag)) {
+    if (tid == 0) d.scal_part[blk] = tot;
+    if (arrive_last(d.counter, nblk, &s_flag)) {
       double acc = 0.0;
-      for (int b = tid; b < (int)gridDim.x; b += kThreads) acc += d.scal_part[b];
+      for (int b = tid; b < nblk; b += kThreads) acc += d.scal_part[b];
       const double tot2 = block_sum(acc, sred);
       if (tid == 0) {
         *d.scalar_out = d.accumulate ? (*d.scalar_out + tot2) : tot2;
@@ -195,6 +198,10 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
   }
 
   // ---- EPI_UPDATE: wave w solves row w in normalized coordinates -----------
+  // Gamma is block-diagonal over the column groups, so one solve of all R
+  // columns solves every group; frozen groups (batched solve) keep their rows.
+  const int NG = d.groups > 1 ? d.groups : 1;
+  const int Rg = R / NG;
   double ip = 0.0;
   if (wave < nrows) {
     const int64_t row = row0 + wave;
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
       const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
       x = wave_gs(b, x0, sG, R, d.gs_iters, lane);
     }
-    if (lane < R) {
+    if (lane < R && !(d.st && d.st->frozen[lane / Rg])) {
       if (!isfinite(x)) atomicOr(d.flags, CP_FLAG_NONFINITE);
       d.A[row * R + lane] = x;
       if (d.A32) d.A32[row * R + lane] = (float)x;
@@ -215,9 +222,29 @@ __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
     }
   }
   if (d.want_obj) {
-    const double ipb = block_sum(ip, sred);
-    if (tid == 0) d.scal_part[blockIdx.x] = ipb;
+    for (int g = 0; g < NG; ++g) {
+      const double ipb = block_sum((lane < R && lane / Rg == g) ? ip : 0.0, sred);
+      if (tid == 0) d.scal_part[(size_t)blk * NG + g] = ipb;
+    }
   }
+}
+
+__global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
+  epi_body(d, blockIdx.x, gridDim.x);
+}
+
+// Batched epilogues: tile t runs block tiles[t].y of the epilogue descs[tiles[t].x].
+__global__ __launch_bounds__(kThreads) void epi_batched_kernel(const EpiDesc* __restrict__ descs,
+                                                               const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  const EpiDesc& d = descs[t.x];
+  epi_body(d, t.y, (int)((d.In + EPI_ROWS - 1) / EPI_ROWS));
+}
+
+hipError_t epi_batched_launch(const EpiDesc* descs, const int2* tiles, int ntiles, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(epi_batched_kernel, dim3(ntiles), dim3(kThreads), 0, st, descs, tiles);
+  return hipGetLastError();
 }
 
 hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {
@@ -238,6 +265,20 @@ hipError_t finalize_launch(const PrepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Batched: workgroup b finalizes problem b (pas[b]); smem_doubles covers the
+// largest problem.
+__global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const PrepArgs* __restrict__ pas) {
+  extern __shared__ double dsmem[];
+  sweep_prep(pas[blockIdx.x], dsmem, true);
+}
+
+hipError_t finalize_batched_launch(const PrepArgs* pas, int nprob, int smem_doubles, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_batched_kernel, dim3(nprob), dim3(kThreads),
+                     sizeof(double) * (size_t)smem_doubles, st, pas);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Grams of every mode (one workgroup per mode), optional FP32 shadow refresh.
 struct GramArgs {
@@ -246,13 +287,11 @@ struct GramArgs {
   int64_t dims[kMaxOrder];
 };
 
-__global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, double* grams,
-                                                        double* sigma) {
+// Gram U = A^T A of one I x R factor into gram_out (R x R); refreshes the FP32
+// shadow when A32 is set and resets the column scales when sigma_out is set.
+__device__ __forceinline__ void gram_body(const double* __restrict__ A, float* A32, int64_t I, int R,
+                                          double* gram_out, double* sigma_out) {
   __shared__ double tile[64 * LDP];
-  const int m = blockIdx.x;
-  const double* A = g.A[m];
-  float* A32 = g.A32[m];
-  const int64_t I = g.dims[m];
   double acc[4] = {0, 0, 0, 0};
   for (int64_t i0 = 0; i0 < I; i0 += 64) {
     const int rows = (int)std::min<int64_t>(64, I - i0);
@@ -275,9 +314,30 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, doubl
   }
   for (int q = 0; q < 4; ++q) {
     const int idx = threadIdx.x + q * kThreads;
-    if (idx < R * R) grams[(size_t)m * R * R + idx] = acc[q];
+    if (idx < R * R) gram_out[idx] = acc[q];
   }
-  if (sigma && threadIdx.x < R) sigma[m * R + threadIdx.x] = 1.0;
+  if (sigma_out && threadIdx.x < R) sigma_out[threadIdx.x] = 1.0;
+}
+
+__global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, double* grams,
+                                                        double* sigma) {
+  const int m = blockIdx.x;
+  gram_body(g.A[m], g.A32[m], g.dims[m], R, grams + (size_t)m * R * R,
+            sigma ? sigma + (size_t)m * R : nullptr);
+}
+
+// Batched: workgroup j computes jobs[j] (one mode of one problem); problems
+// with nothing left in the current phase are skipped.
+__global__ __launch_bounds__(kThreads) void gram_batched_kernel(const GramJob* __restrict__ jobs) {
+  const GramJob& j = jobs[blockIdx.x];
+  if (j.st && !j.st->active) return;
+  gram_body(j.A, j.A32, j.I, j.R, j.gram, j.sigma);
+}
+
+hipError_t gram_batched_launch(const GramJob* jobs, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gram_batched_kernel, dim3(njobs), dim3(kThreads), 0, st, jobs);
+  return hipGetLastError();
 }
 
 hipError_t gram_launch(double* const* A, float* const* A32, const int64_t* dims, int N, int R,
@@ -335,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double* __rest
   }
   const double tot = block_sum(acc, sred);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
-  if (arrive_last(counter, &s_flag)) {
+  if (arrive_last(counter, (int)gridDim.x, &s_flag)) {
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) s += part[b];
@@ -380,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict_
     acc += a[i] * (b ? b[i] : a[i]);
   const double tot = block_sum(acc, sred);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
-  if (arrive_last(counter, &s_flag)) {
+  if (arrive_last(counter, (int)gridDim.x, &s_flag)) {
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int k = 0; k < (int)gridDim.x; ++k) s += part[k];

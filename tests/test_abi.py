@@ -71,6 +71,8 @@ def test_null_context_is_rejected_without_touching_the_gpu():
     assert lib.cp_autotune(None, ctypes.byref(z), ctypes.byref(f), 0, 5) == INVALID
     assert lib.cp_plans_import(None, b"") == INVALID
     assert lib.cp_plans_export(None) == b""
+    prm = _lib.CpBatchParams(2, 0, 16, 1e-9, 1e-12, 100, 16)
+    assert lib.cp_als_batched(None, None, 0, ctypes.byref(prm), None, None) == INVALID
     flags = ctypes.c_int32()
     assert lib.cp_get_status(None, ctypes.byref(flags)) == INVALID
     assert lib.cp_ctx_destroy(None) == INVALID

@@ -1,0 +1,123 @@
+"""Batched ALS solves (cp_als_batched) against the oracle, through the C ABI.
+
+Every restart of every problem must follow the oracle's ALS trajectory from the
+same start: the restarts of a problem share each pass over the tensor but
+never couple (block-diagonal Gamma).
+"""
+import numpy as np
+import pytest
+
+from oracle import cp
+from paper_1111_6091_amd import synth
+from tests.gpu_util import ctx as make_ctx, rel_err, say, sync
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(C, probs, restarts, mixed):
+    from paper_1111_6091_amd import api
+    dev = []
+    for p in probs:
+        Zd = api.DeviceTensor.from_numpy(C, p["Z"], fp32=mixed)
+        cat = [np.hstack([p["starts"][k][n] for k in range(restarts)]) for n in range(3)]
+        dev.append((Zd, api.DeviceFactors.from_numpy(C, cat, fp32=mixed)))
+    return dev
+
+
+def _restart(A, k, R):
+    return [a[:, k * R:(k + 1) * R] for a in A]
+
+
+@pytest.mark.parametrize("count,restarts,rmax", [(6, 3, 4), (5, 4, 8)])
+def test_batched_fixed_sweeps_match_oracle(count, restarts, rmax):
+    """FP64 phase only, no stopping before the cap: K sweeps of every restart
+    equal K oracle ALS sweeps (normalized after each sweep)."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_FP64
+    probs = synth.batched_problems(count=count, seed=11, restarts=restarts, lo=5, hi=21, rmin=2,
+                                   rmax=rmax, cmin=0.3, cmax=0.8)
+    say(f"batched fixed sweeps: {[(p['dims'], p['R']) for p in probs]} restarts={restarts}")
+    C = make_ctx()
+    dev = _setup(C, probs, restarts, mixed=False)
+    K = 8
+    fits, sweeps = api.cp_als_batched(C, dev, restarts, prec=CP_FP64, tol64=0.0, max_sweeps=K, chunk=3)
+    sync()
+    fits = fits.cpu().numpy()
+    sweeps = sweeps.cpu().numpy()
+    assert C.status() == 0
+    for b, p in enumerate(probs):
+        got = dev[b][1].to_numpy()
+        for k in range(restarts):
+            A = [a.copy() for a in p["starts"][k]]
+            for _ in range(K):
+                A = cp.als_sweep(p["Z"], A)
+            G = _restart(got, k, p["R"])
+            for n in range(3):
+                assert rel_err(G[n], A[n]) < 1e-9, (b, k, n, rel_err(G[n], A[n]))
+            assert fits[b, k] == pytest.approx(cp.fit(p["Z"], A), rel=1e-9, abs=1e-9)
+            assert sweeps[b, k, 0] == 0 and sweeps[b, k, 1] == K
+
+
+def test_batched_fp64_stopping_rule_matches_oracle():
+    """FP64 phase with the per-sweep rule: each restart stops at the oracle's sweep
+    with the oracle's factors."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_FP64
+    restarts = 2
+    probs = synth.batched_problems(count=4, seed=12, restarts=restarts, lo=6, hi=18, rmin=2, rmax=3,
+                                   cmin=0.3, cmax=0.6)
+    C = make_ctx()
+    dev = _setup(C, probs, restarts, mixed=False)
+    tol = 1e-8
+    fits, sweeps = api.cp_als_batched(C, dev, restarts, prec=CP_FP64, tol64=tol, max_sweeps=400, chunk=16)
+    sync()
+    fits = fits.cpu().numpy()
+    sweeps = sweeps.cpu().numpy()
+    for b, p in enumerate(probs):
+        got = dev[b][1].to_numpy()
+        for k in range(restarts):
+            A, h = cp.als(p["Z"], p["starts"][k], max_sweeps=400, fit_tol=tol, sort_at_end=False)
+            say(f"problem {b} restart {k}: oracle {h['sweeps']} sweeps, device {sweeps[b, k, 1]}")
+            assert sweeps[b, k, 1] == h["sweeps"]
+            G = _restart(got, k, p["R"])
+            for n in range(3):
+                assert rel_err(G[n], A[n]) < 1e-8
+            assert fits[b, k] == pytest.approx(h["fit"][-1], rel=1e-10)
+
+
+def test_batched_mixed_reaches_the_fp64_fit():
+    """Mixed form (FP32 windows, then FP64 to the 1e-12 rule): every restart lands
+    on the oracle's FP64 ALS fit from the same start."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_MIXED
+    restarts = 3
+    probs = synth.batched_problems(count=5, seed=13, restarts=restarts, lo=8, hi=24, rmin=2, rmax=4,
+                                   cmin=0.3, cmax=0.6)
+    C = make_ctx()
+    dev = _setup(C, probs, restarts, mixed=True)
+    fits, sweeps = api.cp_als_batched(C, dev, restarts, prec=CP_MIXED, window32=16, tol32=1e-9,
+                                      tol64=1e-12, max_sweeps=3000, chunk=16)
+    sync()
+    fits = fits.cpu().numpy()
+    sweeps = sweeps.cpu().numpy()
+    for b, p in enumerate(probs):
+        for k in range(restarts):
+            _, h = cp.als(p["Z"], p["starts"][k], max_sweeps=3000, fit_tol=1e-12, sort_at_end=False)
+            say(f"problem {b} restart {k}: oracle {h['sweeps']} sweeps fit {h['fit'][-1]:.15f}; device "
+                f"{sweeps[b, k, 0]}+{sweeps[b, k, 1]} sweeps fit {fits[b, k]:.15f}")
+            assert sweeps[b, k, 1] >= 1
+            assert abs(fits[b, k] - h["fit"][-1]) <= 1e-10 * abs(h["fit"][-1])
+
+
+def test_batched_rejects_bad_arguments():
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_FP64
+    probs = synth.batched_problems(count=1, seed=14, restarts=2, lo=6, hi=8, rmin=2, rmax=2)
+    C = make_ctx()
+    dev = _setup(C, probs, 2, mixed=False)
+    with pytest.raises(api.CpError):
+        api.cp_als_batched(C, dev, 3, prec=CP_FP64)        # rank 4 is not 3 restarts
+    with pytest.raises(api.CpError):
+        api.cp_als_batched(C, dev, 2, prec=CP_FP64, window32=1)
+    with pytest.raises(api.CpError):
+        api.cp_als_batched(C, dev, 2, prec=1)              # mixed needs FP32 shadows
