@@ -36,6 +36,7 @@ from . import cp
 
 # Table 1 parameters
 SETUP_PARAMS = dict(nu1=5, nu2=5, nuc=100, nt=2)
+SETUP_PARAMS_NO_NT = dict(nu1=5, nu2=5, nuc=100)   # keyword form for setup_phase
 FAS_PARAMS = dict(nu1=1, nu2=1, nuc=50, gs_iters=10)
 
 
@@ -155,6 +156,7 @@ def fas_correct(Phat, A, Ac, At):
 class Level:
     Z: np.ndarray
     Phat: list = field(default_factory=list)   # per mode: I_n x I_n,c (to next level) or None
+    weights: list = field(default_factory=list)   # per mode: the I_n x 2 weights P^ was built from
 
     @property
     def dims(self):
@@ -166,15 +168,17 @@ def hierarchy_from_weights(Z, weights_per_level, coarsest):
     levels = []
     cur = np.asarray(Z, dtype=np.float64)
     for wl in weights_per_level:
-        Ph = []
+        Ph, Ws = [], []
         for n, In in enumerate(cur.shape):
             if In > coarsest[n] and wl[n] is not None:
                 Ph.append(transfer(interp_from_weights(In, wl[n]))[2])
+                Ws.append(np.asarray(wl[n]))
             else:
                 Ph.append(None)
+                Ws.append(None)
         if all(p is None for p in Ph):
             break
-        levels.append(Level(cur, Ph))
+        levels.append(Level(cur, Ph, Ws))
         cur = restrict_tensor(cur, [None if p is None else p.T for p in Ph])
     levels.append(Level(cur, [None] * cur.ndim))
     return levels
@@ -262,13 +266,15 @@ def mult_vcycle(Z, A, tfms, coarsest, first_cycle, nu1=5, nu2=5, nuc=100,
         tfms = [cp.als_sweep(Z, T) for T in tfms]
         A = cp.als_sweep(Z, A)
     Ph = [None] * N
+    Ws = [None] * N
     for n in Ic:
         w = build_interp(Z, tfms, A, n, use_bfm=not first_cycle)
+        Ws[n] = w
         Ph[n] = transfer(interp_from_weights(Z.shape[n], w))[2]
     At = restrict_factors(Ph, A)
     tfms_c = [restrict_factors(Ph, T) for T in tfms]
     Zc = restrict_tensor(Z, [None if p is None else p.T for p in Ph])
-    levels_out.append(Level(Z, Ph))
+    levels_out.append(Level(Z, Ph, Ws))
     Ac, _, _ = mult_vcycle(Zc, At, tfms_c, coarsest, first_cycle, nu1, nu2, nuc, levels_out)
     A = prolong(Ph, Ac)
     for _ in range(nu2):
@@ -297,10 +303,12 @@ def down_sweep(Z, A_boot, tfms, coarsest, nu1=5, use_bfm=True):
         if fine_tfms is None:
             fine_tfms = tfms
         Ph = [None] * N
+        Ws = [None] * N
         for n in Ic:
             w = build_interp(Z, tfms, B, n, use_bfm=use_bfm)
+            Ws[n] = w
             Ph[n] = transfer(interp_from_weights(Z.shape[n], w))[2]
-        levels.append(Level(Z, Ph))
+        levels.append(Level(Z, Ph, Ws))
         B = restrict_factors(Ph, B)
         tfms = [restrict_factors(Ph, T) for T in tfms]
         Z = restrict_tensor(Z, [None if p is None else p.T for p in Ph])

@@ -1249,6 +1249,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
   BatchRule* rules = nullptr;
   std::vector<BatchPhase> dp(nphase);
   GramJob* jobs = nullptr;
+  int32_t* plist = nullptr;
   int smem_fin = 0;
   auto carve = [&](auto& c, bool real) {
     for (int b = 0; b < nprob; ++b) {
@@ -1264,7 +1265,8 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
     BatchState* stp = c.template take<BatchState>((size_t)nprob);
     BatchRule* ru = c.template take<BatchRule>(2);
     GramJob* jb = c.template take<GramJob>((size_t)nprob * N);
-    if (real) { states = stp; rules = ru; jobs = jb; }
+    int32_t* pl = c.template take<int32_t>((size_t)nprob);
+    if (real) { states = stp; rules = ru; jobs = jb; plist = pl; }
     for (int ph = 0; ph < nphase; ++ph) {
       MttkrpDesc* md = c.template take<MttkrpDesc>((size_t)nsets * nprob);
       EpiDesc* ed = c.template take<EpiDesc>((size_t)N * nprob);
@@ -1453,12 +1455,60 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
       HIPCHK(hipMemcpyAsync(states, hst.data(), hst.size() * sizeof(BatchState), hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
     }
-    const BatchPhase& d = dp[ph];
+    BatchPhase& d = dp[ph];
+    // Launch lists cover the problems still active at the start of a chunk;
+    // problems that stop inside a chunk leave their tiles early.  Few active
+    // problems: longer chunks between host checks (the rules themselves are
+    // applied on the device after every sweep).
+    std::vector<int32_t> act;
+    std::vector<std::vector<std::vector<int2>>> cmt(nsets, std::vector<std::vector<int2>>(2));
+    std::vector<std::vector<int2>> cet(N);
+    for (int b = 0; b < nprob; ++b) act.push_back(b);
     for (int done = 0; done < prm->max_sweeps;) {
-      const int K = std::min(prm->chunk, prm->max_sweeps - done);
+      const int na = (int)act.size();
+      int K = na <= 8 ? prm->chunk * 8 : (na <= 64 ? prm->chunk * 2 : prm->chunk);
+      K = std::min(K, prm->max_sweeps - done);
+      if (na < nprob) {
+        std::vector<char> on(nprob, 0);
+        for (int b : act) on[b] = 1;
+        for (int set = 0; set < nsets; ++set)
+          for (int q = 0; q < 2; ++q) {
+            cmt[set][q].clear();
+            for (const int2& t : hp[ph].mt[set][q])
+              if (on[t.x % nprob]) cmt[set][q].push_back(t);
+            d.mcount[set][q] = (int)cmt[set][q].size();
+            if (!cmt[set][q].empty())
+              HIPCHK(hipMemcpyAsync(d.mtiles[set][q], cmt[set][q].data(), cmt[set][q].size() * sizeof(int2),
+                                    hipMemcpyHostToDevice, st));
+          }
+        for (int n = 0; n < N; ++n) {
+          cet[n].clear();
+          for (const int2& t : hp[ph].et[n])
+            if (on[t.x % nprob]) cet[n].push_back(t);
+          d.ecount[n] = (int)cet[n].size();
+          if (!cet[n].empty())
+            HIPCHK(hipMemcpyAsync(d.etiles[n], cet[n].data(), cet[n].size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, st));
+        }
+      } else {
+        for (int set = 0; set < nsets; ++set)
+          for (int q = 0; q < 2; ++q) {
+            d.mcount[set][q] = (int)hp[ph].mt[set][q].size();
+            if (!hp[ph].mt[set][q].empty())
+              HIPCHK(hipMemcpyAsync(d.mtiles[set][q], hp[ph].mt[set][q].data(),
+                                    hp[ph].mt[set][q].size() * sizeof(int2), hipMemcpyHostToDevice, st));
+          }
+        for (int n = 0; n < N; ++n) {
+          d.ecount[n] = (int)hp[ph].et[n].size();
+          if (!hp[ph].et[n].empty())
+            HIPCHK(hipMemcpyAsync(d.etiles[n], hp[ph].et[n].data(), hp[ph].et[n].size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, st));
+        }
+      }
+      HIPCHK(hipMemcpyAsync(plist, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
       {
         ProfScope ps(ctx, CP_PROF_GRAM);
-        HIPCHK(gram_batched_launch(jobs, nprob * N, st));
+        HIPCHK(gram_batched_launch(jobs, plist, na, N, st));
       }
       for (int k = 0; k < K; ++k)
         for (int n = 0; n < N; ++n) {
@@ -1474,14 +1524,15 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
         }
       {
         ProfScope ps(ctx, CP_PROF_NORMALIZE);
-        HIPCHK(finalize_batched_launch(d.fin, nprob, smem_fin, st));
+        HIPCHK(finalize_batched_launch(d.fin, plist, na, smem_fin, st));
       }
       done += K;
       HIPCHK(hipMemcpyAsync(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      bool any = false;
-      for (int b = 0; b < nprob && !any; ++b) any = hst[b].active != 0;
-      if (!any) break;
+      HIPCHK(hipStreamSynchronize(st));   // also retires the host tile lists uploaded above
+      act.clear();
+      for (int b = 0; b < nprob; ++b)
+        if (hst[b].active) act.push_back(b);
+      if (act.empty()) break;
     }
   }
 

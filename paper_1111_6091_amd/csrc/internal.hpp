@@ -205,13 +205,16 @@ struct GramJob {
   double* sigma;        // R column scales reset to 1 when set
   const BatchState* st; // skip when the problem is inactive
 };
-hipError_t gram_batched_launch(const GramJob* jobs, int njobs, hipStream_t st);
+// one workgroup per (listed problem, mode): jobs[plist[j / N] * N + j % N]
+hipError_t gram_batched_launch(const GramJob* jobs, const int32_t* plist, int count, int N,
+                               hipStream_t st);
 
 // End of a sweep sequence: Gram of the last mode, fused objective, and the
 // pending normalization applied to the stored factors (one workgroup).
 hipError_t finalize_launch(const PrepArgs& a, hipStream_t st);
-// batched: one workgroup per problem (device array of PrepArgs)
-hipError_t finalize_batched_launch(const PrepArgs* pas, int nprob, int smem_doubles, hipStream_t st);
+// batched: one workgroup per listed problem (pas[plist[j]], device arrays)
+hipError_t finalize_batched_launch(const PrepArgs* pas, const int32_t* plist, int count,
+                                   int smem_doubles, hipStream_t st);
 
 // Grams of every mode at fixed A; optionally refresh FP32 shadows and reset the
 // pending normalization scales (sigma, N x R) to 1

@@ -265,17 +265,19 @@ hipError_t finalize_launch(const PrepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Batched: workgroup b finalizes problem b (pas[b]); smem_doubles covers the
-// largest problem.
-__global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const PrepArgs* __restrict__ pas) {
+// Batched: workgroup j finalizes problem plist[j] (pas[plist[j]]); smem_doubles
+// covers the largest problem.
+__global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const PrepArgs* __restrict__ pas,
+                                                                    const int32_t* __restrict__ plist) {
   extern __shared__ double dsmem[];
-  sweep_prep(pas[blockIdx.x], dsmem, true);
+  sweep_prep(pas[plist[blockIdx.x]], dsmem, true);
 }
 
-hipError_t finalize_batched_launch(const PrepArgs* pas, int nprob, int smem_doubles, hipStream_t st) {
-  if (nprob <= 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_batched_kernel, dim3(nprob), dim3(kThreads),
-                     sizeof(double) * (size_t)smem_doubles, st, pas);
+hipError_t finalize_batched_launch(const PrepArgs* pas, const int32_t* plist, int count,
+                                   int smem_doubles, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_batched_kernel, dim3(count), dim3(kThreads),
+                     sizeof(double) * (size_t)smem_doubles, st, pas, plist);
   return hipGetLastError();
 }
 
@@ -326,17 +328,21 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g, int R, doubl
             sigma ? sigma + (size_t)m * R : nullptr);
 }
 
-// Batched: workgroup j computes jobs[j] (one mode of one problem); problems
-// with nothing left in the current phase are skipped.
-__global__ __launch_bounds__(kThreads) void gram_batched_kernel(const GramJob* __restrict__ jobs) {
-  const GramJob& j = jobs[blockIdx.x];
+// Batched: workgroup j computes mode j % N of problem plist[j / N]
+// (jobs[problem * N + mode]); problems with nothing left in the current phase
+// are skipped.
+__global__ __launch_bounds__(kThreads) void gram_batched_kernel(const GramJob* __restrict__ jobs,
+                                                                const int32_t* __restrict__ plist,
+                                                                int N) {
+  const GramJob& j = jobs[(size_t)plist[blockIdx.x / N] * N + blockIdx.x % N];
   if (j.st && !j.st->active) return;
   gram_body(j.A, j.A32, j.I, j.R, j.gram, j.sigma);
 }
 
-hipError_t gram_batched_launch(const GramJob* jobs, int njobs, hipStream_t st) {
-  if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gram_batched_kernel, dim3(njobs), dim3(kThreads), 0, st, jobs);
+hipError_t gram_batched_launch(const GramJob* jobs, const int32_t* plist, int count, int N,
+                               hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gram_batched_kernel, dim3(count * N), dim3(kThreads), 0, st, jobs, plist, N);
   return hipGetLastError();
 }
 

@@ -140,3 +140,24 @@ def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False):
         cur = nxt
     levels.append((cur, [None] * cur.order))
     return levels
+
+
+def fas_solve(ctx, levels, Z, A, fit_tol=1e-12, max_cycles=500, nu1=1, nu2=1, nuc=50, gs_iters=10,
+              ic_rule=0, prec=CP_FP64):
+    """CP-FAS V-cycles (Algorithm 2) until the relative change of the exact fit is
+    <= fit_tol (Section 6 caps: at most ``max_cycles`` cycles).  ``levels`` from
+    :func:`build_hierarchy`; ``Z`` is the finest-level DeviceTensor."""
+    res = SolveResult()
+    prev = None
+    while res.sweeps < max_cycles:
+        api.cp_fas_vcycle(ctx, levels, A, nu1=nu1, nu2=nu2, nuc=nuc, gs_iters=gs_iters, ic_rule=ic_rule,
+                          prec=prec)
+        fit = exact_fit(ctx, Z, A)
+        res.fits.append(fit)
+        res.sweeps += 1
+        if fit_tol and prev is not None and abs(fit - prev) <= fit_tol * abs(fit):
+            res.converged = True
+            break
+        prev = fit
+    res.final_fit = res.fits[-1] if res.fits else float("nan")
+    return res

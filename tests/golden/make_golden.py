@@ -41,5 +41,61 @@ def main(names):
         print(name, ref["sweeps"], ref["final_fit_exact"], f"{ref['oracle_seconds']:.1f}s", flush=True)
 
 
+
+
+def fas_reference(name, coarsest_size=16, restart=0, nt=2, fit_tol=1e-12, max_cycles=500,
+                  max_sweeps=10000):
+    """Setup phase (Algorithm 1 cycles, Table 1 setup parameters, stagnation rule of
+    Section 6.1) from a seeded start with n_t seeded test blocks, then from its
+    result: CP-FAS V-cycles (Algorithm 2, Table 1) and standalone ALS, each to a
+    relative fit change <= fit_tol (exact fit after every cycle / sweep)."""
+    from oracle import amg
+    Z, _, spec = synth.workload(name)
+    dims, R = Z.shape, spec["R"]
+    A0 = synth.uniform_start(dims, R, spec["seed"], restart)
+    tfms0 = [synth.uniform_start(dims, R, spec["seed"], 100 + k) for k in range(nt)]
+    coarsest = [coarsest_size] * len(dims)
+    t = time.time()
+    A, tfms, levels, ghist = amg.setup_phase(Z, A0, tfms0, coarsest, **amg.SETUP_PARAMS_NO_NT)
+    t_setup = time.time() - t
+    weights = [[None if w is None else np.asarray(w).tolist() for w in lv.weights] for lv in levels[:-1]]
+    out = {"workload": name, "restart": restart, "coarsest": coarsest, "levels": len(levels),
+           "setup_cycles": len(ghist), "setup_g": ghist, "setup_seconds": t_setup,
+           "weights": weights, "A_setup": [a.tolist() for a in A], "fit_setup": cp.fit(Z, A),
+           "fit_tol": fit_tol}
+    # FAS V-cycles
+    t = time.time()
+    Af, prev, fits = A, None, []
+    for c in range(max_cycles):
+        Af = amg.fas_vcycle(levels, amg.zeros_like_factors(Af), Af, **amg.FAS_PARAMS)
+        fk = cp.fit(Z, Af)
+        fits.append(fk)
+        if prev is not None and abs(fk - prev) <= fit_tol * abs(fk):
+            break
+        prev = fk
+    out.update({"fas_cycles": len(fits), "fas_fit": fits[-1], "fas_fits": fits,
+                "fas_seconds": time.time() - t})
+    # standalone ALS from the same point
+    t = time.time()
+    Aa, h = cp.als(Z, A, max_sweeps=max_sweeps, fit_tol=fit_tol, record="direct", sort_at_end=False)
+    out.update({"als_sweeps": h["sweeps"], "als_fit": h["fit"][-1], "als_seconds": time.time() - t})
+    return out
+
+
+def main_fas(names):
+    for name in names:
+        ref = fas_reference(name)
+        path = os.path.join(HERE, f"fas_{name}.json")
+        with open(path, "w") as f:
+            json.dump(ref, f)
+        print(name, "setup", ref["setup_cycles"], f"{ref['setup_seconds']:.1f}s", "fas", ref["fas_cycles"],
+              ref["fas_fit"], f"{ref['fas_seconds']:.1f}s", "als", ref["als_sweeps"], ref["als_fit"],
+              f"{ref['als_seconds']:.1f}s", flush=True)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c1_20cube_r3"])
+    args = sys.argv[1:]
+    if args and args[0] == "fas":
+        main_fas(args[1:] or ["c2_128cube_r5"])
+    else:
+        main(args or ["c1_20cube_r3"])
