@@ -121,6 +121,16 @@ cp_status cp_ctx_create(cp_ctx* out, void* hip_stream);
 cp_status cp_ctx_destroy(cp_ctx ctx);
 /* Re-bind the context to another stream (work already enqueued stays where it is). */
 cp_status cp_set_stream(cp_ctx ctx, void* hip_stream);
+
+/* Context options (host values):
+ *   CP_OPT_DIMTREE (default 1): ALS/BNGS sweeps of order N >= 3 reuse the
+ *     stage-1 GEMM tiles of the mode-1 MTTKRP, Y = Z x_1 A^(1)T (exact in exact
+ *     arithmetic), for the MTTKRPs of modes >= 2, so a sweep streams Z twice
+ *     instead of N times; used when Y takes at most a quarter of Z's bytes.
+ *     0: every mode streams Z.
+ * Returns CP_ERR_INVALID for an unknown option or value. */
+#define CP_OPT_DIMTREE 1
+cp_status cp_set_option(cp_ctx ctx, int32_t option, int32_t value);
 /* Text of the last host-side error of this context ("" if none); owned by ctx. */
 const char* cp_last_error(cp_ctx ctx);
 /* Synchronize the stream, return the OR of device flag bits since the last call

@@ -29,6 +29,8 @@ PROF_CLASSES = ["mttkrp_mode0_f64", "mttkrp_mode1_f64", "mttkrp_modeN_f64",
                 "mttkrp_mode0_f32", "mttkrp_mode1_f32", "mttkrp_modeN_f32",
                 "update", "epilogue_other", "gamma_prep", "normalize", "gram", "other"]
 
+CP_OPT_DIMTREE = 1
+
 CP_FLAG_PINV_FALLBACK = 1
 CP_FLAG_NOT_SPD = 2
 CP_FLAG_NONFINITE = 4
@@ -72,6 +74,7 @@ SIGNATURES = {
     "cp_ctx_create": [ctypes.POINTER(c_vp), c_vp],
     "cp_ctx_destroy": [c_vp],
     "cp_set_stream": [c_vp, c_vp],
+    "cp_set_option": [c_vp, c_i32, c_i32],
     "cp_get_status": [c_vp, ctypes.POINTER(c_i32)],
     "cp_cast_f32": [c_vp, c_vp, c_vp, c_i64],
     "cp_norm2": [c_vp, ctypes.POINTER(CpTensor), c_vp],

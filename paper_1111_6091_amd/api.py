@@ -55,6 +55,9 @@ class Context:
         self.check(self._lib.cp_get_status(self.handle, ctypes.byref(flags)))
         return flags.value
 
+    def set_option(self, option, value):
+        self.check(self._lib.cp_set_option(self.handle, int(option), int(value)))
+
     def profile(self, on=True):
         self.check(self._lib.cp_profile_enable(self.handle, int(bool(on))))
 

@@ -39,6 +39,8 @@ struct cp_ctx_s {
   double* prep_out = nullptr;   // Gamma factor + column scales for the next update
   int32_t* chol_kind = nullptr;
   double* scal = nullptr;   // 64 scratch scalars
+  // sweeps of order >= 3 reuse the mode-1 stage-1 tiles for modes >= 2
+  int dimtree = 1;
   // launch configurations of the MTTKRP kernels: tuned options and plan cache
   std::map<std::string, PlanOpts> tuned;
   std::map<std::string, MttkrpPlan> plans;
@@ -257,16 +259,57 @@ struct SweepWS {
   double* partial;
   double* gram_part;
   double* scal_part;
+  double* y;   // dimension tree: stage-1 tiles of the mode-1 launch (NULL: per-mode MTTKRPs)
 };
 
 template <typename Carver>
-void carve_sweep(Carver& c, int N, int R, size_t partial, int64_t maxI, SweepWS* out) {
+void carve_sweep(Carver& c, int N, int R, size_t partial, int64_t maxI, SweepWS* out,
+                 size_t ydoubles = 0) {
   const int64_t nwg = epi_blocks(maxI);
   out->grams = c.template take<double>((size_t)N * R * R);
   out->sigma = c.template take<double>((size_t)N * R);
   out->partial = c.template take<double>(partial);
   out->gram_part = c.template take<double>((size_t)nwg * R * R);
   out->scal_part = c.template take<double>((size_t)std::max<int64_t>(nwg, 2048));
+  out->y = ydoubles ? c.template take<double>(ydoubles) : nullptr;
+}
+
+// Launch plans of a sweep.  Dimension tree (order >= 3): the mode-1 launch runs
+// its contraction unsplit and stores the stage-1 tiles
+//   Y[s][i1][r] = sum_i0 Z(i0, i1, s) A^(0)(i0, r),
+// which depend on Z and A^(0) only, so the MTTKRPs of modes >= 2 contract Y
+// instead of streaming Z again: N - 1 passes over Z per sweep become 2.  Used
+// when Y is at most a quarter of the tensor's bytes.
+struct SweepPlan {
+  std::vector<MttkrpPlan> p;   // per mode, direct MTTKRP
+  bool dimtree = false;
+  MttkrpPlan p1y{};            // mode 1 storing Y
+  std::vector<int> ynsplit;    // modes >= 2 from Y
+  size_t partial = 0;          // doubles of the partial-sum buffer
+  size_t ydoubles = 0;
+};
+
+SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32) {
+  SweepPlan sp;
+  sp.partial = max_partial(ctx, dims, N, R, fp32, &sp.p);
+  if (!ctx->dimtree || N < 3) return sp;
+  int64_t S = 1, P = 1;
+  for (int m = 2; m < N; ++m) S *= dims[m];
+  for (int m = 0; m < N; ++m) P *= dims[m];
+  const size_t yd = (size_t)S * dims[1] * R;
+  if (yd * 8 * 4 > (size_t)P * (fp32 ? 4 : 8)) return sp;
+  sp.dimtree = true;
+  sp.ydoubles = yd;
+  PlanOpts o = sp.p[1].opts;
+  o.ksplit = 1;
+  sp.p1y = mttkrp_plan(N, dims, 1, R, fp32, o);
+  sp.partial = std::max(sp.partial, sp.p1y.partial_doubles);
+  sp.ynsplit.assign(N, 0);
+  for (int n = 2; n < N; ++n) {
+    sp.ynsplit[n] = ymttkrp_nsplit(dims, N, n, R);
+    sp.partial = std::max(sp.partial, (size_t)sp.ynsplit[n] * dims[n] * R);
+  }
+  return sp;
 }
 
 // `nsweeps` BNGS sweeps over all modes starting from the stored factors A.
@@ -274,7 +317,7 @@ void carve_sweep(Carver& c, int N, int R, size_t partial, int64_t maxI, SweepWS*
 // the sweep bookkeeping for the update) and the update, then one finalize.
 cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const void* z, bool fp32,
                          double* const* A, float* const* A32, double* const* F,
-                         const std::vector<MttkrpPlan>& plans, const SweepWS& w, cp_solver solver,
+                         const SweepPlan& sp, const SweepWS& w, cp_solver solver,
                          int gs_iters, int normalize, int nsweeps, double* f_hist,
                          const double* norm2) {
   if (nsweeps <= 0) return CP_OK;
@@ -310,9 +353,23 @@ cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const vo
         pa.boundary = 1;
         pa.f_slot = f_hist ? f_hist + (k - 1) : nullptr;
       }
-      cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
-                                   (const float* const*)A32, plans[n], w.partial, &pa);
-      if (s != CP_OK) return s;
+      const bool tree = sp.dimtree && w.y;
+      int nsplit = sp.p[n].nsplit;
+      if (tree && n >= 2) {
+        ProfScope ps(ctx, fp32 ? CP_PROF_MTTKRP_MODEN_F32 : CP_PROF_MTTKRP_MODEN_F64);
+        HIPCHK(ymttkrp_launch(dims, N, n, R, w.y, (const double* const*)A, w.partial, sp.ynsplit[n], &pa,
+                              ctx->stream));
+        nsplit = sp.ynsplit[n];
+      } else if (tree && n == 1) {
+        ProfScope ps(ctx, fp32 ? CP_PROF_MTTKRP_MODE1_F32 : CP_PROF_MTTKRP_MODE1_F64);
+        HIPCHK(mttkrp_launch(sp.p1y, dims, N, n, R, z, fp32, (const double* const*)A, (const float* const*)A32,
+                             w.partial, &pa, ctx->stream, w.y));
+        nsplit = sp.p1y.nsplit;
+      } else {
+        cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
+                                     (const float* const*)A32, sp.p[n], w.partial, &pa);
+        if (s != CP_OK) return s;
+      }
       EpiDesc d{};
       d.op = EPI_UPDATE;
       d.solver = solver;
@@ -320,7 +377,7 @@ cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const vo
       d.R = R;
       d.N = N;
       d.n = n;
-      d.nsplit = plans[n].nsplit;
+      d.nsplit = nsplit;
       d.In = dims[n];
       d.partial = w.partial;
       d.F = F ? F[n] : nullptr;
@@ -405,6 +462,15 @@ cp_status cp_ctx_destroy(cp_ctx ctx) {
   if (ctx->fixed) (void)hipFree(ctx->fixed);
   delete ctx;
   return CP_OK;
+}
+
+cp_status cp_set_option(cp_ctx ctx, int32_t option, int32_t value) {
+  if (!ctx) return CP_ERR_INVALID;
+  if (option == CP_OPT_DIMTREE && (value == 0 || value == 1)) {
+    ctx->dimtree = value;
+    return CP_OK;
+  }
+  return set_err(ctx, CP_ERR_INVALID, "cp_set_option: unknown option %d or value %d", option, value);
 }
 
 cp_status cp_set_stream(cp_ctx ctx, void* hip_stream) {
@@ -503,19 +569,18 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   if (f_hist && !Z->norm2) return set_err(ctx, CP_ERR_INVALID, "f_hist needs Z->norm2");
   if (nsweeps == 0) return CP_OK;
   const int R = A->rank;
-  std::vector<MttkrpPlan> plans;
-  const size_t part = max_partial(ctx, Z->dims, N, R, mixed, &plans);
+  const SweepPlan sp = sweep_plan(ctx, Z->dims, N, R, mixed);
   Sizer sz;
   SweepWS w{};
-  carve_sweep(sz, N, R, part, max_dim(Z->dims, N), &w);
+  carve_sweep(sz, N, R, sp.partial, max_dim(Z->dims, N), &w, sp.ydoubles);
   if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
   Arena ar(ctx->ws);
-  carve_sweep(ar, N, R, part, max_dim(Z->dims, N), &w);
+  carve_sweep(ar, N, R, sp.partial, max_dim(Z->dims, N), &w, sp.ydoubles);
   bool have32 = true;
   for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   return enqueue_sweeps(ctx, Z->dims, N, R, z, mixed, A->a, have32 ? A->a32 : nullptr,
-                        F ? F->a : nullptr, plans, w, solver, gs_iters, normalize, nsweeps, f_hist,
+                        F ? F->a : nullptr, sp, w, solver, gs_iters, normalize, nsweeps, f_hist,
                         Z->norm2);
 }
 
@@ -962,7 +1027,7 @@ struct FasLevel {
   double* F[CP_MAX_ORDER] = {};
   double* H[CP_MAX_ORDER] = {};
   double* grams = nullptr;
-  std::vector<MttkrpPlan> plans;
+  SweepPlan sp;
   bool has32 = false;
 };
 
@@ -976,14 +1041,15 @@ struct FasRun {
   double* gram_part;
   double* scal_part;
   double* sigma;
+  double* y;
 };
 
 cp_status fas_relax(FasRun& r, int l, int times) {
   cp_ctx ctx = r.ctx;
   FasLevel& L = r.lv[l];
-  SweepWS w{L.grams, r.sigma, r.partial, r.gram_part, r.scal_part};
+  SweepWS w{L.grams, r.sigma, r.partial, r.gram_part, r.scal_part, L.sp.dimtree ? r.y : nullptr};
   return enqueue_sweeps(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A, L.has32 ? L.A32 : nullptr,
-                        l == 0 ? nullptr : L.F, L.plans, w, CP_SOLVE_GS, r.p.gs_iters,
+                        l == 0 ? nullptr : L.F, L.sp, w, CP_SOLVE_GS, r.p.gs_iters,
                         l == 0 ? 1 : 0, times, nullptr, nullptr);
 }
 
@@ -994,14 +1060,14 @@ cp_status fas_H(FasRun& r, int l, double* const* A, float* const* A32, double* c
   TRY(enqueue_gram(ctx, A, A32, L.dims, r.N, r.R, L.grams));
   for (int n = 0; n < r.N; ++n) {
     cp_status s = enqueue_mttkrp(ctx, L.dims, r.N, n, r.R, L.z, r.mixed, (const double* const*)A,
-                                 (const float* const*)A32, L.plans[n], r.partial);
+                                 (const float* const*)A32, L.sp.p[n], r.partial);
     if (s != CP_OK) return s;
     EpiDesc d{};
     d.op = EPI_H;
     d.R = r.R;
     d.N = r.N;
     d.n = n;
-    d.nsplit = L.plans[n].nsplit;
+    d.nsplit = L.sp.p[n].nsplit;
     d.In = L.dims[n];
     d.partial = r.partial;
     d.A = A[n];
@@ -1078,10 +1144,10 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
     return set_err(ctx, CP_ERR_INVALID, "cp_fas_vcycle: bad parameters");
   const int R = A->rank;
   FasRun r{ctx, N, R, nlevels, mixed, p, std::vector<FasLevel>(nlevels), nullptr, nullptr, nullptr,
-           nullptr};
+           nullptr, nullptr};
   bool have32 = true;
   for (int m = 0; m < N; ++m) have32 = have32 && A->a32[m];
-  size_t maxpart = 0;
+  size_t maxpart = 0, maxy = 0;
   int64_t maxI = 0;
   for (int l = 0; l < nlevels; ++l) {
     FasLevel& L = r.lv[l];
@@ -1090,7 +1156,9 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
       L.phat[n] = (l + 1 < nlevels) ? levels[l].phat[n] : nullptr;
     }
     L.z = mixed ? (const void*)levels[l].z.z32 : (const void*)levels[l].z.z64;
-    maxpart = std::max(maxpart, max_partial(ctx, L.dims, N, R, mixed, &L.plans));
+    L.sp = sweep_plan(ctx, L.dims, N, R, mixed);
+    maxpart = std::max(maxpart, L.sp.partial);
+    maxy = std::max(maxy, L.sp.ydoubles);
     maxI = std::max(maxI, max_dim(L.dims, N));
   }
   auto carve = [&](auto& c, bool real) {
@@ -1116,7 +1184,8 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
     double* gp = c.template take<double>((size_t)nwg * R * R);
     double* sp = c.template take<double>((size_t)std::max<int64_t>(nwg, 2048));
     double* sg = c.template take<double>((size_t)N * R);
-    if (real) { r.partial = part; r.gram_part = gp; r.scal_part = sp; r.sigma = sg; }
+    double* yb = maxy ? c.template take<double>(maxy) : nullptr;
+    if (real) { r.partial = part; r.gram_part = gp; r.scal_part = sp; r.sigma = sg; r.y = yb; }
   };
   Sizer sz;
   carve(sz, false);

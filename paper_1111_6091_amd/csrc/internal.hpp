@@ -115,8 +115,33 @@ struct MttkrpDesc {
   int64_t rest_count;             // kind 3: number of stripes per output value
   int32_t prep;                   // 1: workgroup 0 runs sweep_prep(pa) instead of streaming
   int32_t vec;                    // 4-wide tensor loads allowed (I0 % 4 == 0, aligned base)
+  double* y;                      // kind 2 with ksplit == 1: also store the stage-1 tiles
+                                  // Y[s][i1][r] = sum_i0 Z(i0, i1, s) A^(0)(i0, r) (FP64)
   PrepArgs pa;
 };
+
+// Dimension-tree MTTKRP of a mode n >= 2 from the stored stage-1 tiles Y of the
+// mode-1 launch (Y depends only on Z and A^(0), so it serves every mode after 1):
+//   M^(n)(i_n, r) = sum_{s : s_n = i_n} sum_i1 Y[s][i1][r] A^(1)(i1, r) prod_{m >= 2, m != n} A^(m)(s_m, r)
+struct YDesc {
+  const double* y;                // [S][I1][R]
+  const double* a64[kMaxOrder];
+  double* out;                    // partials [nsplit][I_n][R]
+  int64_t I1, S, In;
+  int32_t N, n, R;
+  int32_t ns;
+  int64_t sext[kMaxOrder], sst[kMaxOrder];
+  int64_t rest_count;             // stripes per output value (S / I_n)
+  int64_t rchunk;                 // rest indices per split
+  int32_t nsplit;
+  int32_t prep;
+  PrepArgs pa;
+};
+// plan (nsplit) for a mode-n launch from Y, and the launch itself
+int ymttkrp_nsplit(const int64_t* dims, int N, int n, int R);
+hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double* y,
+                          const double* const* a64, double* out, int nsplit, const PrepArgs* prep,
+                          hipStream_t st);
 
 // planner + launcher (mttkrp.hip)
 struct PlanOpts {
@@ -141,14 +166,16 @@ struct MttkrpPlan {
 MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, bool fp32, const PlanOpts& o);
 // resident workgroups of the plan's kernel on the whole device
 int mttkrp_capacity(const MttkrpPlan& p, bool fp32);
+// y: mode-1 launches with an unsplit contraction may also store Y (dimension tree)
 hipError_t mttkrp_launch(const MttkrpPlan& plan, const int64_t* dims, int N, int n, int R,
                          const void* z, bool fp32, const double* const* a64,
                          const float* const* a32, double* out, const PrepArgs* prep,
-                         hipStream_t st);
+                         hipStream_t st, double* y = nullptr);
 // The launch descriptor mttkrp_launch would use (for batched launches).
 MttkrpDesc mttkrp_desc(const MttkrpPlan& plan, const int64_t* dims, int N, int n, int R,
                        const void* z, bool fp32, const double* const* a64,
-                       const float* const* a32, double* out, const PrepArgs* prep);
+                       const float* const* a32, double* out, const PrepArgs* prep,
+                       double* y = nullptr);
 // dynamic LDS bytes of a launch of `plan` (with or without the bookkeeping workgroup)
 size_t mttkrp_smem_bytes(const MttkrpPlan& p, int N, int R, bool prep);
 // Batched MTTKRPs of one mode: tile t runs workgroup tiles[t].y of descs[tiles[t].x]

@@ -470,6 +470,19 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
       __builtin_amdgcn_sched_barrier(0);
     }
     if (k0 < kend) compute(zA, bA, mA);
+    // dimension tree: keep the stage-1 tile (complete: the contraction is not split)
+    if (!KIND3 && d.y) {
+#pragma unroll
+      for (int a = 0; a < TW; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t i1 = rowbase + a * 16 + mfma_row<T>(g4, v);
+            const int col = t * 16 + r;
+            if (i1 < I1 && col < R) d.y[((size_t)s * I1 + i1) * R + col] = (double)D[a][t][v];
+          }
+    }
     // Hadamard-reduce (FP64)
     if (KIND3) {
 #pragma unroll
@@ -559,6 +572,118 @@ __global__ __launch_bounds__(kThreads) void mttkrp_batched(const MttkrpDesc* __r
     if (d.vec) kind23_body<T, NT, 2, KIND == 3, 4, true, true>(d, t.y, smem);
     else kind23_body<T, NT, 2, KIND == 3, 4, false, true>(d, t.y, smem);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Dimension-tree MTTKRP of mode n >= 2 from Y (FP64 throughout).  Workgroup
+// (row i_n, split) sums its chunk of rest indices; threads cover (rest index,
+// i1) pairs, each accumulating RM column sums, then a block reduction.
+// ---------------------------------------------------------------------------
+template <int RM>
+__global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
+  extern __shared__ double smem[];
+  if (d.prep && blockIdx.x == 0) {
+    sweep_prep(d.pa, smem, false);
+    return;
+  }
+  const int bid = blockIdx.x - d.prep;
+  const int64_t row = bid % d.In;
+  const int split = (int)(bid / d.In);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R = d.R;
+  const int64_t I1 = d.I1;
+  const int jn = d.n - 2;
+  const int64_t qbeg = (int64_t)split * d.rchunk;
+  const int64_t qend = min(d.rest_count, qbeg + d.rchunk);
+  const int lpq = I1 >= kThreads ? kThreads : (int)I1;   // threads per rest index
+  const int qpar = kThreads / lpq;
+  const int qo = tid / lpq, il = tid % lpq;
+  double acc[RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) acc[r] = 0.0;
+  const double* __restrict__ a1 = d.a64[1];
+  if (qo < qpar) {
+    for (int64_t q = qbeg + qo; q < qend; q += qpar) {
+      // stripe index from the output value (mode n) and the rest index q
+      int64_t s = row * d.sst[jn], qq = q;
+      double w[RM];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) w[r] = 1.0;
+      for (int j = 0; j < d.ns; ++j) {
+        if (j == jn) continue;
+        const int64_t sj = qq % d.sext[j];
+        qq /= d.sext[j];
+        s += sj * d.sst[j];
+        const double* am = d.a64[j + 2] + sj * R;
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          if (r < R) w[r] *= am[r];
+      }
+      const double* ys = d.y + (size_t)s * I1 * R;
+      for (int64_t i1 = il; i1 < I1; i1 += lpq) {
+        const double* yr = ys + i1 * R;
+        const double* ar = a1 + i1 * R;
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          if (r < R) acc[r] += w[r] * yr[r] * ar[r];
+      }
+    }
+  }
+  // block reduction: waves by shuffles, then the four wave sums in order
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    double x = acc[r];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+    if (lane == 0) smem[wave * RM + r] = x;
+  }
+  __syncthreads();
+  if (tid < R) {
+    const double sum = smem[tid] + smem[RM + tid] + smem[2 * RM + tid] + smem[3 * RM + tid];
+    d.out[((size_t)split * d.In + row) * R + tid] = sum;
+  }
+}
+
+int ymttkrp_nsplit(const int64_t* dims, int N, int n, int R) {
+  (void)R;
+  int64_t S = 1;
+  for (int m = 2; m < N; ++m) S *= dims[m];
+  const int64_t rest = S / dims[n];
+  // aim for about two workgroups per compute unit over all output rows
+  const int64_t want = std::max<int64_t>(1, 512 / std::max<int64_t>(1, dims[n]));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(rest, want));
+}
+
+hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double* y,
+                          const double* const* a64, double* out, int nsplit, const PrepArgs* prep,
+                          hipStream_t st) {
+  YDesc d{};
+  d.y = y;
+  for (int m = 0; m < N; ++m) d.a64[m] = a64[m];
+  d.out = out;
+  d.I1 = dims[1];
+  d.S = 1;
+  for (int m = 2; m < N; ++m) d.S *= dims[m];
+  d.In = dims[n];
+  d.N = N;
+  d.n = n;
+  d.R = R;
+  d.ns = N - 2;
+  int64_t acc = 1;
+  for (int j = 0; j < d.ns; ++j) {
+    d.sext[j] = dims[j + 2];
+    d.sst[j] = acc;
+    acc *= dims[j + 2];
+  }
+  d.rest_count = d.S / d.In;
+  d.nsplit = nsplit;
+  d.rchunk = (d.rest_count + nsplit - 1) / nsplit;
+  d.prep = prep ? 1 : 0;
+  if (prep) d.pa = *prep;
+  const size_t smem = sizeof(double) * (size_t)std::max(4 * kMaxRank, prep ? prep_smem_doubles(N, R) : 0);
+  dim3 grid((unsigned)(d.In * nsplit + d.prep)), block(kThreads);
+  if (R <= 16) hipLaunchKernelGGL(ymttkrp_kernel<16>, grid, block, smem, st, d);
+  else hipLaunchKernelGGL(ymttkrp_kernel<32>, grid, block, smem, st, d);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -703,8 +828,9 @@ hipError_t mttkrp_batched_launch(int kind, bool fp32, int nt, const MttkrpDesc* 
 hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
                          const void* z, bool fp32, const double* const* a64,
                          const float* const* a32, double* out, const PrepArgs* prep,
-                         hipStream_t st) {
-  MttkrpDesc d = mttkrp_desc(p, dims, N, n, R, z, fp32, a64, a32, out, prep);
+                         hipStream_t st, double* y) {
+  if (y && (p.kind != 2 || p.ksplit != 1)) return hipErrorInvalidValue;
+  MttkrpDesc d = mttkrp_desc(p, dims, N, n, R, z, fp32, a64, a32, out, prep, y);
   const void* k = select_kernel(p, fp32, d.vec != 0);
   if (!k) return hipErrorInvalidValue;
   dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
@@ -714,8 +840,9 @@ hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n,
 
 MttkrpDesc mttkrp_desc(const MttkrpPlan& p, const int64_t* dims, int N, int n, int R,
                        const void* z, bool fp32, const double* const* a64,
-                       const float* const* a32, double* out, const PrepArgs* prep) {
+                       const float* const* a32, double* out, const PrepArgs* prep, double* y) {
   MttkrpDesc d{};
+  d.y = y;
   if (prep) {
     d.prep = 1;
     d.pa = *prep;

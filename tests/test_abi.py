@@ -77,5 +77,6 @@ def test_null_context_is_rejected_without_touching_the_gpu():
     assert lib.cp_get_status(None, ctypes.byref(flags)) == INVALID
     assert lib.cp_ctx_destroy(None) == INVALID
     assert lib.cp_set_stream(None, None) == INVALID
+    assert lib.cp_set_option(None, 1, 0) == INVALID
     assert lib.cp_ctx_create(None, None) == INVALID
     assert lib.cp_last_error(None) == b"invalid context"
