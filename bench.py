@@ -73,6 +73,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-tune", action="store_true")
+    p.add_argument("--no-multilevel", action="store_true",
+                   help="skip the 128^3 R=5 CP-FAS leg (4 levels)")
     p.add_argument("--no-batched", action="store_true",
                    help="skip the batched leg (512 tensors x 4 restarts, mixed form)")
     p.add_argument("--plans-file", default=None,
@@ -171,6 +173,13 @@ def main():
     log(f"mixed sweep: {ms_mixed * 1e3:.1f} us ({1e3 / ms_mixed:.0f} sweeps/s)")
     ms_fp64, wall_fp64 = timed(CP_FP64, K, W)
     log(f"fp64 sweep: {ms_fp64 * 1e3:.1f} us ({1e3 / ms_fp64:.0f} sweeps/s)")
+    # the same sweeps with one pass over Z per mode (no dimension tree)
+    from paper_1111_6091_amd._lib import CP_OPT_DIMTREE
+    ctx.set_option(CP_OPT_DIMTREE, 0)
+    ms_mixed_pm, _ = timed(CP_MIXED, K, W)
+    ms_fp64_pm, _ = timed(CP_FP64, K, W)
+    ctx.set_option(CP_OPT_DIMTREE, 1)
+    log(f"per-mode MTTKRPs: mixed {ms_mixed_pm * 1e3:.1f} us, fp64 {ms_fp64_pm * 1e3:.1f} us per sweep")
 
     # roofline leg: each MTTKRP kernel timed over back-to-back launches in the
     # launch configuration the sweep uses (HIP events on the library's stream)
@@ -244,6 +253,10 @@ def main():
     if not args.no_batched:
         batched = batched_leg(ctx, api, synth)
 
+    multilevel = None
+    if not args.no_multilevel:
+        multilevel = fas_leg(ctx, api, drivers, synth)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(Z, A0, args.cpu_seconds)
@@ -265,6 +278,11 @@ def main():
                                f"{spec['c']}, noise {spec['eta_h']}, mixed FP32/FP64 ALS sweep",
                    "dims": list(dims), "rank": R, "parallelism": "single GPU"},
         "fp64_sweeps_per_s": round(1e3 / ms_fp64, 2),
+        "sweep_us": {"mixed": round(ms_mixed * 1e3, 2), "fp64": round(ms_fp64 * 1e3, 2),
+                     "mixed_per_mode_passes": round(ms_mixed_pm * 1e3, 2),
+                     "fp64_per_mode_passes": round(ms_fp64_pm * 1e3, 2),
+                     "note": "default sweeps stream Z twice (mode 0, mode 1 + stage-1 tiles reused by "
+                             "mode 2); per_mode_passes stream Z once per mode"},
         "wall_seconds": {"mixed": round(wall_mixed, 4), "fp64": round(wall_fp64, 4)},
         "mttkrp_gbs": {k: round(v["achieved_gbs"], 1) for k, v in roof.items()},
         "mttkrp_us": {k: round(v["avg_us"], 2) for k, v in roof.items()},
@@ -273,9 +291,56 @@ def main():
         "equal_fit": equal_fit,
         "tuned_plans": plans.strip().splitlines() if plans else None,
         "batched": batched,
+        "multilevel_128cube_r5": multilevel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def fas_leg(ctx, api, drivers, synth):
+    """128^3 R=5 (c = 0.9, 1% + 1% noise), FP64: CP-FAS V-cycles (Algorithm 2, Table 1
+    parameters) on the 4-level hierarchy from the oracle's setup phase (stored
+    interpolation weights and setup factors, an input here) against standalone ALS
+    from the same factors, each to a relative fit change of 1e-12."""
+    import numpy as np
+    import torch
+    path = os.path.join(HERE, "tests", "golden", "fas_c2_128cube_r5.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    Z, _, spec = synth.workload("c2_128cube_r5")
+    weights = [[None if w is None else np.asarray(w) for w in lv] for lv in g["weights"]]
+    Zd = api.DeviceTensor.from_numpy(ctx, Z)
+    levels = drivers.build_hierarchy(ctx, Zd, weights)
+    A0 = [np.asarray(a) for a in g["A_setup"]]
+    out = {"levels": len(levels), "coarsest": g["coarsest"], "stop": "relative fit change <= 1e-12",
+           "oracle": {"fas_cycles": g["fas_cycles"], "fas_fit": g["fas_fit"], "fas_seconds": round(g["fas_seconds"], 1),
+                      "als_sweeps": g.get("als_sweeps"), "als_fit": g.get("als_fit"),
+                      "als_seconds": round(g.get("als_seconds", 0.0), 1)}}
+    A = api.DeviceFactors.from_numpy(ctx, A0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = drivers.fas_solve(ctx, levels, Zd, A, fit_tol=1e-12, nu1=1, nu2=1, nuc=50, gs_iters=10)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    A = api.DeviceFactors.from_numpy(ctx, A0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ra = drivers.als_solve(ctx, Zd, A, fit_tol=1e-12, prec=0, sort_at_end=False)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    fit_als = drivers.exact_fit(ctx, Zd, A)
+    out["fas"] = {"cycles": r.sweeps, "seconds": round(tf, 4), "ms_per_cycle": round(1e3 * tf / r.sweeps, 3),
+                  "fit": r.final_fit,
+                  "rel_fit_err_vs_oracle": abs(r.final_fit - g["fas_fit"]) / abs(g["fas_fit"])}
+    out["als"] = {"sweeps": ra.sweeps, "seconds": round(ta, 4), "us_per_sweep": round(1e6 * ta / ra.sweeps, 1),
+                  "fit": fit_als}
+    if g.get("als_fit"):
+        out["als"]["rel_fit_err_vs_oracle"] = abs(fit_als - g["als_fit"]) / abs(g["als_fit"])
+    log(f"128^3 FAS: {r.sweeps} V-cycles in {tf:.3f} s ({1e3 * tf / r.sweeps:.2f} ms/cycle), fit {r.final_fit:.13f}; "
+        f"ALS: {ra.sweeps} sweeps in {ta:.3f} s, fit {fit_als:.13f}")
+    return out
 
 
 def batched_leg(ctx, api, synth):

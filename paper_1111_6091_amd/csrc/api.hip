@@ -1471,6 +1471,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
         fa.A32[m] = mixed ? pb.a.a32[m] : nullptr;
         fa.dims[m] = pb.z.dims[m];
       }
+      fa.lds = prep_smem_doubles(N, R);
       hfin[ph][b] = fa;
     }
   }

@@ -16,6 +16,14 @@ constexpr int kMaxOrder = CP_MAX_ORDER;
 constexpr int kMaxRank = CP_MAX_RANK;
 constexpr int kThreads = 256;   // threads per workgroup for every kernel (4 waves)
 
+// Value of v in lane `lane` (uniform across the wave), via scalar reads of
+// the two halves: no LDS crossbar round trip.
+__device__ __forceinline__ double wave_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 // Row of the 16x16 MFMA result held in element v of a lane in lane group g = l/16
 // (column = l % 16).  v_mfma_f64_16x16x4f64 interleaves rows (g + 4v);
 // v_mfma_f32_16x16x4f32 gives each lane group four consecutive rows (4g + v).
@@ -56,11 +64,15 @@ struct BatchState {
   double fit_win[kMaxGroups];     // FP32 phase: fit at the first sweep of the window
 };
 
-constexpr int kGramTile = 512;   // doubles of a factor staged per round by the bookkeeping Gram
-
-// Doubles of LDS the bookkeeping step (sweep.hpp) needs for order N and rank R.
+// LDS of the bookkeeping step (sweep.hpp), in doubles: five R x R work arrays,
+// the N x R column scales and, when the launch provides the room
+// (PrepArgs::lds), the N stored Grams.
+__host__ __device__ constexpr int prep_min_doubles(int N, int R) { return 5 * R * R + N * R; }
+__host__ __device__ constexpr bool prep_stage_grams(int N, int R, int lds) {
+  return 5 * R * R + N * R + N * R * R <= lds;
+}
 __host__ __device__ constexpr int prep_smem_doubles(int N, int R) {
-  return 5 * R * R + N * R + kGramTile;
+  return 5 * R * R + N * R + (N * R * R <= 4096 ? N * R * R : 0);
 }
 
 // Per-mode bookkeeping done by the extra first workgroup of an MTTKRP launch
@@ -88,6 +100,7 @@ struct PrepArgs {
   int32_t groups;           // column groups (independent restarts); 0 or 1: one group
   BatchState* st;           // batched solves: stopping state (NULL otherwise)
   const BatchRule* rule;
+  int32_t lds;              // doubles of LDS the launch provides (set by the launchers)
 };
 
 struct MttkrpDesc {

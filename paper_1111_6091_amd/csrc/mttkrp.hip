@@ -324,7 +324,7 @@ __device__ __forceinline__ void kind1_body(const MttkrpDesc& d, int blk, double*
 // consecutive i0 per lane.  kind 2 (n == 1): rows are the outputs; kind 3
 // (n >= 2): rows are reduced with A^(1)(i1, r) into output s_n.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL>
+template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL, bool YS = false>
 __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double* smem) {
   typedef typename Vec4<T>::type V;
   constexpr int KC = 4 * VW;   // contraction chunk per step of the loop
@@ -471,7 +471,7 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
     }
     if (k0 < kend) compute(zA, bA, mA);
     // dimension tree: keep the stage-1 tile (complete: the contraction is not split)
-    if (!KIND3 && d.y) {
+    if (YS && !KIND3) {
 #pragma unroll
       for (int a = 0; a < TW; ++a)
 #pragma unroll
@@ -548,10 +548,10 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
   kind1_body<T, NT, VW, VEC, BL>(d, blockIdx.x, smem);
 }
 
-template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL>
+template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL, bool YS = false>
 __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
   extern __shared__ double smem[];
-  kind23_body<T, NT, TW, KIND3, VW, VEC, BL>(d, blockIdx.x, smem);
+  kind23_body<T, NT, TW, KIND3, VW, VEC, BL, YS>(d, blockIdx.x, smem);
 }
 
 // Batched MTTKRPs (one mode of many problems in one launch): tile t runs
@@ -583,7 +583,7 @@ template <int RM>
 __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
   extern __shared__ double smem[];
   if (d.prep && blockIdx.x == 0) {
-    sweep_prep(d.pa, smem, false);
+    sweep_prep<16>(d.pa, smem, false);
     return;
   }
   const int bid = blockIdx.x - d.prep;
@@ -629,17 +629,30 @@ __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
       }
     }
   }
-  // block reduction: waves by shuffles, then the four wave sums in order
+  // block reduction through LDS, 16 columns at a time, in a fixed order:
+  // 16 consecutive threads' values, then the 16 part sums
+  (void)lane;
+  (void)wave;
 #pragma unroll
-  for (int r = 0; r < RM; ++r) {
-    double x = acc[r];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
-    if (lane == 0) smem[wave * RM + r] = x;
-  }
-  __syncthreads();
-  if (tid < R) {
-    const double sum = smem[tid] + smem[RM + tid] + smem[2 * RM + tid] + smem[3 * RM + tid];
-    d.out[((size_t)split * d.In + row) * R + tid] = sum;
+  for (int c0 = 0; c0 < RM; c0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) smem[c * kThreads + tid] = acc[c0 + c];
+    __syncthreads();
+    {
+      const int c = tid >> 4, part = tid & 15;
+      double x = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x += smem[c * kThreads + part * 16 + i];
+      smem[16 * kThreads + tid] = x;
+    }
+    __syncthreads();
+    if (tid < 16 && c0 + tid < R) {
+      double x = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x += smem[16 * kThreads + tid * 16 + i];
+      d.out[((size_t)split * d.In + row) * R + c0 + tid] = x;
+    }
   }
 }
 
@@ -678,8 +691,11 @@ hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double
   d.nsplit = nsplit;
   d.rchunk = (d.rest_count + nsplit - 1) / nsplit;
   d.prep = prep ? 1 : 0;
-  if (prep) d.pa = *prep;
-  const size_t smem = sizeof(double) * (size_t)std::max(4 * kMaxRank, prep ? prep_smem_doubles(N, R) : 0);
+  if (prep) {
+    d.pa = *prep;
+    d.pa.lds = prep_smem_doubles(N, R);
+  }
+  const size_t smem = sizeof(double) * (size_t)std::max(17 * kThreads, prep ? prep_smem_doubles(N, R) : 0);
   dim3 grid((unsigned)(d.In * nsplit + d.prep)), block(kThreads);
   if (R <= 16) hipLaunchKernelGGL(ymttkrp_kernel<16>, grid, block, smem, st, d);
   else hipLaunchKernelGGL(ymttkrp_kernel<32>, grid, block, smem, st, d);
@@ -762,10 +778,17 @@ MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, bool fp32, cons
 }
 
 template <typename T, int NT, int VW, bool BL>
-static const void* kernel_ptr(int kind, int tw, bool vec) {
+static const void* kernel_ptr(int kind, int tw, bool vec, bool ys) {
   if (kind == 1)
     return vec ? (const void*)mttkrp_kind1<T, NT, VW, true, BL> : (const void*)mttkrp_kind1<T, NT, VW, false, BL>;
   const bool k3 = kind == 3;
+  if (!k3 && ys) {   // mode 1 storing the stage-1 tiles (dimension tree)
+    if (tw == 4 && NT == 1)
+      return vec ? (const void*)mttkrp_kind23<T, 1, 4, false, VW, true, BL, true>
+                 : (const void*)mttkrp_kind23<T, 1, 4, false, VW, false, BL, true>;
+    return vec ? (const void*)mttkrp_kind23<T, NT, 2, false, VW, true, BL, true>
+               : (const void*)mttkrp_kind23<T, NT, 2, false, VW, false, BL, true>;
+  }
   if (tw == 4 && NT == 1) {
     if (k3) return vec ? (const void*)mttkrp_kind23<T, 1, 4, true, VW, true, BL> : (const void*)mttkrp_kind23<T, 1, 4, true, VW, false, BL>;
     return vec ? (const void*)mttkrp_kind23<T, 1, 4, false, VW, true, BL> : (const void*)mttkrp_kind23<T, 1, 4, false, VW, false, BL>;
@@ -775,21 +798,22 @@ static const void* kernel_ptr(int kind, int tw, bool vec) {
 }
 
 template <typename T, int VW>
-static const void* kernel_ptr_nt(const MttkrpPlan& p, bool vec) {
-  if (p.bl) return p.nt == 1 ? kernel_ptr<T, 1, VW, true>(p.kind, p.tw, vec) : kernel_ptr<T, 2, VW, true>(p.kind, p.tw, vec);
-  return p.nt == 1 ? kernel_ptr<T, 1, VW, false>(p.kind, p.tw, vec) : kernel_ptr<T, 2, VW, false>(p.kind, p.tw, vec);
+static const void* kernel_ptr_nt(const MttkrpPlan& p, bool vec, bool ys) {
+  if (p.bl) return p.nt == 1 ? kernel_ptr<T, 1, VW, true>(p.kind, p.tw, vec, ys) : kernel_ptr<T, 2, VW, true>(p.kind, p.tw, vec, ys);
+  return p.nt == 1 ? kernel_ptr<T, 1, VW, false>(p.kind, p.tw, vec, ys) : kernel_ptr<T, 2, VW, false>(p.kind, p.tw, vec, ys);
 }
 
-static const void* select_kernel(const MttkrpPlan& p, bool fp32, bool vec) {
-  if (fp32) return p.vw == 8 ? kernel_ptr_nt<float, 8>(p, vec) : kernel_ptr_nt<float, 4>(p, vec);
-  return kernel_ptr_nt<double, 4>(p, vec);
+static const void* select_kernel(const MttkrpPlan& p, bool fp32, bool vec, bool ys = false) {
+  if (fp32) return p.vw == 8 ? kernel_ptr_nt<float, 8>(p, vec, ys) : kernel_ptr_nt<float, 4>(p, vec, ys);
+  return kernel_ptr_nt<double, 4>(p, vec, ys);
 }
 
 // dynamic LDS bytes of a launch
 size_t mttkrp_smem_bytes(const MttkrpPlan& p, int N, int R, bool prep) {
   int64_t d = p.kind == 1 ? kind1_smem() : kind23_smem(p.tw, p.nt, p.kind == 3);
   if (p.bl) d = std::max<int64_t>(d, p.bstage_doubles);
-  if (prep) d = std::max<int64_t>(d, prep_smem_doubles(N, R));
+  // the bookkeeping workgroup works within the streaming workgroups' LDS
+  if (prep) d = std::max<int64_t>(d, prep_min_doubles(N, R));
   return sizeof(double) * (size_t)d;
 }
 
@@ -831,7 +855,7 @@ hipError_t mttkrp_launch(const MttkrpPlan& p, const int64_t* dims, int N, int n,
                          hipStream_t st, double* y) {
   if (y && (p.kind != 2 || p.ksplit != 1)) return hipErrorInvalidValue;
   MttkrpDesc d = mttkrp_desc(p, dims, N, n, R, z, fp32, a64, a32, out, prep, y);
-  const void* k = select_kernel(p, fp32, d.vec != 0);
+  const void* k = select_kernel(p, fp32, d.vec != 0, y != nullptr);
   if (!k) return hipErrorInvalidValue;
   dim3 grid((unsigned)((int64_t)p.ngroups * p.nsplit + (d.prep ? 1 : 0))), block(kThreads);
   void* args[] = {&d};
@@ -846,6 +870,7 @@ MttkrpDesc mttkrp_desc(const MttkrpPlan& p, const int64_t* dims, int N, int n, i
   if (prep) {
     d.prep = 1;
     d.pa = *prep;
+    d.pa.lds = (int32_t)(mttkrp_smem_bytes(p, N, R, true) / sizeof(double));
   }
   d.z = z;
   d.N = N;

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.hpp"
+
 namespace cpamg {
 
 constexpr double kEps = 2.220446049250313e-16;
@@ -22,33 +24,96 @@ __device__ inline void hadamard_gamma(const double* __restrict__ grams, int N, i
   __syncthreads();
 }
 
-// In-place Cholesky G = L L^T (row-major, lower triangle receives L).
-// Returns 0 on success, 1 when a pivot is <= R*eps*max(diag G) (caller falls
-// back to the pseudoinverse).  G must be restored by the caller on failure.
-__device__ inline int wg_cholesky(double* G, int R) {
+// In-place Cholesky factorization G = L L^T of the symmetric R x R matrix in
+// LDS (row-major; the lower triangle of G becomes L, the upper triangle is left
+// stale).  Returns 1 in every thread if a pivot is <= R * eps * max diag(G)
+// (or the diagonal is not positive).  Wave 0 does the work: lane i keeps row i
+// in registers (RM >= R columns, loops unrolled), pivots and the entries
+// L(k, j) reach every lane through scalar reads (readlane).
+template <int RM>
+__device__ inline int wave_cholesky(double* G, int R) {
   __shared__ int s_fail;
-  const int lane = threadIdx.x;
-  if (lane == 0) s_fail = 0;
-  __syncthreads();
-  double dmax = 0.0;
-  for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * R + i]);
-  const double thr = R * kEps * dmax;
-  if (!(dmax > 0.0)) return 1;
-  for (int j = 0; j < R; ++j) {
-    const double piv = G[j * R + j];
-    if (!(piv > thr)) return 1;   // uniform: every thread reads the same value
-    const double dj = sqrt(piv);
-    __syncthreads();
-    if (lane > j && lane < R) G[lane * R + j] /= dj;
-    __syncthreads();
-    if (lane == j) G[j * R + j] = dj;
-    if (lane > j && lane < R) {
-      const double lij = G[lane * R + j];
-      for (int k = j + 1; k <= lane; ++k) G[lane * R + k] -= lij * G[k * R + j];
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int lane = tid;
+    const bool own = lane < R;
+    double g[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) g[k] = (own && k < R) ? G[lane * R + k] : 0.0;
+    double dmax = 0.0;
+    for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * R + i]);
+    const double thr = R * kEps * dmax;
+    int fail = dmax > 0.0 ? 0 : 1;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j < R && !fail) {
+        const double piv = wave_bcast(g[j], j);
+        if (!(piv > thr)) {
+          fail = 1;
+        } else {
+          const double dj = sqrt(piv);
+          const double l = lane == j ? dj : (lane > j ? g[j] / dj : g[j]);
+          g[j] = l;
+#pragma unroll
+          for (int k = j + 1; k < RM; ++k) {
+            if (k < R) {
+              const double lk = wave_bcast(l, k);
+              if (lane >= k) g[k] -= l * lk;
+            }
+          }
+        }
+      }
     }
-    __syncthreads();
+    if (!fail && own) {
+#pragma unroll
+      for (int k = 0; k < RM; ++k)
+        if (k < R && k <= lane) G[lane * R + k] = g[k];
+    }
+    if (lane == 0) s_fail = fail;
   }
-  return 0;
+  __syncthreads();
+  return s_fail;
+}
+
+// The same factorization with rows kept in LDS (few registers): lane i owns
+// row i; pivots and L(k, j) are broadcast through scalar reads.
+__device__ inline int wave_cholesky_lds(double* G, int R) {
+  __shared__ int s_fail;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int lane = tid;
+    const bool own = lane < R;
+    double dmax = 0.0;
+    for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * R + i]);
+    const double thr = R * kEps * dmax;
+    int fail = dmax > 0.0 ? 0 : 1;
+    for (int j = 0; j < R && !fail; ++j) {
+      const double gj = own ? G[lane * R + j] : 0.0;
+      const double piv = wave_bcast(gj, j);
+      if (!(piv > thr)) {
+        fail = 1;
+        break;
+      }
+      const double dj = sqrt(piv);
+      const double l = lane == j ? dj : (lane > j && own ? gj / dj : 0.0);
+      if (own && lane >= j) G[lane * R + j] = l;
+      for (int k = j + 1; k < R; ++k) {
+        const double lk = wave_bcast(l, k);
+        if (own && lane >= k) G[lane * R + k] -= l * lk;
+      }
+    }
+    if (lane == 0) s_fail = fail;
+  }
+  __syncthreads();
+  return s_fail;
+}
+
+// REG: rows in registers (standalone bookkeeping kernels); otherwise in LDS
+// (inside streaming kernels, whose register budget it must not raise).
+template <bool REG>
+__device__ inline int wg_cholesky(double* G, int R) {
+  if (!REG) return wave_cholesky_lds(G, R);
+  return R <= 16 ? wave_cholesky<16>(G, R) : wave_cholesky<32>(G, R);
 }
 
 // Pseudoinverse of the symmetric PSD matrix G (R x R) by cyclic Jacobi:
@@ -144,7 +209,7 @@ __device__ inline void gamma_prepare(const double* __restrict__ grams, int N, in
   // keep a copy of Gamma in P (the Cholesky overwrites G)
   for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) P[idx] = G[idx];
   __syncthreads();
-  const int fail = wg_cholesky(G, R);
+  const int fail = wg_cholesky<false>(G, R);
   __syncthreads();
   if (!fail) {
     for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = G[idx];

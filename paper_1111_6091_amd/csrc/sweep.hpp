@@ -29,58 +29,60 @@ __device__ inline double wg_sum(double v, double* sred) {
   return s;
 }
 
-// U (LDS, R*R) = A^T A for A (I x R, global), staged through `tile` (kGramTile doubles).
-__device__ inline void gram_into(const double* __restrict__ A, int64_t I, int R, double* U,
-                                 double* tile) {
-  constexpr int TILE = kGramTile;
-  constexpr int PER = TILE / kThreads;
-  const int tid = threadIdx.x;
-  const int trows = TILE / R;
-  const int RR = R * R;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i0 = 0; i0 < I; i0 += trows) {
-    const int rows = (int)((I - i0) < trows ? (I - i0) : trows);
-    const int cnt = rows * R;
-    double v[PER];
+// U (LDS, R*R) = A^T A for A (I x R row-major, global) on the matrix cores:
+// v_mfma_f64_16x16x4f64 over blocks of 4 rows, lane l supplying row 4b + l/16,
+// column 16t + l%16 as both operands of a diagonal tile (16x16 output tiles
+// (ta, tb), ta <= tb, mirrored).  Wave w takes the row blocks w, w + 4, ...;
+// the four wave sums are added in wave order.
+template <int Q>   // row blocks in flight per wave
+__device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R, double* U) {
+  typedef double d4v __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int nt = (R + 15) / 16;
+  const int64_t nblk = (I + 3) / 4;
+  for (int ta = 0; ta < nt; ++ta)
+    for (int tb = ta; tb < nt; ++tb) {
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      const int ca = ta * 16 + r16, cb = tb * 16 + r16;
+      for (int64_t b0 = wave; b0 < nblk; b0 += 4 * Q) {
+        double va[Q], vb[Q];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int idx = tid + q * kThreads;
-      v[q] = idx < cnt ? A[i0 * R + idx] : 0.0;
-    }
-    __syncthreads();
+        for (int q = 0; q < Q; ++q) {
+          const int64_t row = (b0 + 4 * q) * 4 + kq;
+          const bool okr = row < I;
+          va[q] = (okr && ca < R) ? A[row * R + ca] : 0.0;
+          vb[q] = (ta == tb) ? va[q] : ((okr && cb < R) ? A[row * R + cb] : 0.0);
+        }
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int idx = tid + q * kThreads;
-      if (idx < cnt) tile[idx] = v[q];
-    }
-    __syncthreads();
+        for (int q = 0; q < Q; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], vb[q], acc, 0, 0, 0);
+      }
+      // D(m, n), m = 16 ta + kq + 4 v, n = 16 tb + r16
+      for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * kThreads;
-      if (idx < RR) {
-        const int a = idx / R, b = idx % R;
-        double s = acc[q];
-        for (int rr = 0; rr < rows; ++rr) s += tile[rr * R + a] * tile[rr * R + b];
-        acc[q] = s;
+          for (int v = 0; v < 4; ++v) {
+            const int m = ta * 16 + kq + 4 * v, n = tb * 16 + r16;
+            if (m < R && n < R) {
+              const double val = w == 0 ? acc[v] : U[m * R + n] + acc[v];
+              U[m * R + n] = val;
+              if (ta != tb) U[n * R + m] = val;
+            }
+          }
+        }
+        __syncthreads();
       }
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + q * kThreads;
-    if (idx < RR) U[idx] = acc[q];
-  }
-  __syncthreads();
 }
 
 // Factor Gamma (in G, LDS) for the ALS update: L (kind 0) or the pseudoinverse
 // (kind 1) is written to out[0..R*R).  S, V, P: LDS scratch of R*R each.
+template <bool REG>
 __device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind, uint32_t* flags,
                                     double* S, double* V, double* P) {
   for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) P[idx] = G[idx];
   __syncthreads();
-  const int fail = wg_cholesky(G, R);
+  const int fail = wg_cholesky<REG>(G, R);
   __syncthreads();
   if (!fail) {
     for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = G[idx];
@@ -93,6 +95,31 @@ __device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind
     if (threadIdx.x == 0) {
       *kind = 1;
       atomicOr(flags, zero ? (CP_FLAG_PINV_FALLBACK | CP_FLAG_NOT_SPD) : CP_FLAG_PINV_FALLBACK);
+    }
+  }
+  __syncthreads();
+}
+
+
+// The bookkeeping state into LDS: the column scales into sS and, when
+// staged, the stored Grams into sGr (K loads in flight per thread).
+template <int K>
+__device__ inline void prep_load(const PrepArgs& a, double* sS, double* sGr) {
+  const int N = a.N, R = a.R, RR = R * R;
+  const int n1 = N * R, n2 = sGr ? N * RR : 0;
+  const int L = n1 + n2;
+  for (int base = 0; base < L; base += K * kThreads) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int idx = base + threadIdx.x + k * kThreads;
+      v[k] = idx < n1 ? a.sigma[idx] : (idx < L ? a.grams[idx - n1] : 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int idx = base + threadIdx.x + k * kThreads;
+      if (idx < n1) sS[idx] = v[k];
+      else if (idx < L) sGr[idx - n1] = v[k];
     }
   }
   __syncthreads();
@@ -126,11 +153,14 @@ __device__ inline void batch_rules(BatchState* st, const BatchRule& ru, const do
   st->active = any ? 1 : 0;
 }
 
-// The bookkeeping step; smem: prep_smem_doubles(N, R) doubles of LDS.  With finalize set,
+// The bookkeeping step; smem: a.lds doubles of LDS.  LK: global loads in
+// flight per thread (8 where it shares a kernel with the streaming path, whose
+// register budget it must not raise; 16 in the standalone kernels).  With finalize set,
 // the pending scales are applied to the stored factors and reset instead of
 // preparing an update.  With a.groups > 1 the R columns form independent
 // groups: Gamma is block-diagonal, f is evaluated per group, and in a batched
 // solve (a.st) frozen groups are neither renormalized nor updated.
+template <int LK = 8>
 __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
   __shared__ double sred[8];
   __shared__ double sfit[kMaxGroups];
@@ -147,23 +177,32 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   double* P = V + RR;
   double* U = P + RR;
   double* sS = U + RR;       // sigma, N x R
-  double* tile = sS + N * R; // kGramTile doubles
-  for (int idx = tid; idx < N * R; idx += kThreads) sS[idx] = a.sigma[idx];
-  if (a.p >= 0) gram_into(a.Ap, a.Ip, R, U, tile);
-  __syncthreads();
+  const int lds = a.lds > prep_min_doubles(N, R) ? a.lds : prep_min_doubles(N, R);
+  double* sGr = prep_stage_grams(N, R, lds) ? sS + N * R : nullptr;   // stored Grams, N x R x R
+  prep_load<LK>(a, sS, sGr);
+  if (a.p >= 0) gram_mfma<LK == 8 ? 4 : 16>(a.Ap, a.Ip, R, U);
   // the updated factor is normalized (frozen groups kept their columns)
   if (a.p >= 0 && tid < R && !col_frozen(tid)) sS[a.p * R + tid] = 1.0;
   __syncthreads();
   auto ups = [&](int m, int idx) -> double {
-    return m == a.p ? U[idx] : a.grams[(size_t)m * RR + idx];
+    return m == a.p ? U[idx] : (sGr ? sGr[m * RR + idx] : a.grams[(size_t)m * RR + idx]);
   };
   if (a.boundary && active) {
     if (a.f_slot || st) {
       // per group: f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1),
       // in normalized coordinates
+      double ipg[kMaxGroups];
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; ++g) ipg[g] = 0.0;
+      for (int b = tid; b < a.inner_count; b += kThreads)
+#pragma unroll
+        for (int g = 0; g < kMaxGroups; ++g)
+          if (g < NG) ipg[g] += a.inner_part[(size_t)b * NG + g];
       for (int g = 0; g < NG; ++g) {
         double ip = 0.0;
-        for (int b = tid; b < a.inner_count; b += kThreads) ip += a.inner_part[(size_t)b * NG + g];
+#pragma unroll
+        for (int q = 0; q < kMaxGroups; ++q)
+          if (q == g) ip = ipg[q];
         double h = 0.0;
         for (int idx = tid; idx < Rg * Rg; idx += kThreads) {
           const int r = g * Rg + idx / Rg, c = g * Rg + idx % Rg;
@@ -204,29 +243,35 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   }
   __syncthreads();
   if (finalize) {
-    // apply the scales to the stored factors (and shadows) and to the Grams
+    // apply the scales to the stored factors (and shadows), LK loads in flight
     for (int m = 0; m < N; ++m) {
       double* Am = a.A[m];
       float* A32m = a.A32[m];
       const double* sm = sS + m * R;
       const int64_t cnt = a.dims[m] * R;
-      for (int64_t base = 0; base < cnt; base += 8 * kThreads) {
-        double v[8];
+      for (int64_t base = 0; base < cnt; base += LK * kThreads) {
+        double v[LK];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < LK; ++q) {
           const int64_t idx = base + tid + q * kThreads;
           v[q] = idx < cnt ? Am[idx] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < LK; ++q) {
           const int64_t idx = base + tid + q * kThreads;
-          if (idx < cnt && sm[idx % R] != 1.0) {
-            const double w = v[q] * sm[idx % R];
-            Am[idx] = w;
-            if (A32m) A32m[idx] = (float)w;
+          if (idx < cnt) {
+            const double sc = sm[idx % R];
+            if (sc != 1.0) {
+              const double w = v[q] * sc;
+              Am[idx] = w;
+              if (A32m) A32m[idx] = (float)w;
+            }
           }
         }
       }
+    }
+    for (int m = 0; m < N; ++m) {
+      const double* sm = sS + m * R;
       for (int idx = tid; idx < RR; idx += kThreads) {
         const int r = idx / R, c = idx % R;
         a.grams[(size_t)m * RR + idx] = sm[r] * sm[c] * ups(m, idx);
@@ -263,7 +308,7 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
     __syncthreads();
     return;
   }
-  gamma_factor(G, R, a.out, a.kind, a.flags, S, V, P);
+  gamma_factor<LK != 8>(G, R, a.out, a.kind, a.flags, S, V, P);
 }
 
 }  // namespace cpamg

@@ -88,12 +88,13 @@ __device__ inline void reduce_partials(const EpiDesc& d, int64_t row0, int nrows
 
 // Solve one row x Gamma = b on one wavefront: lane j < R holds b_j, returns x_j.
 // kind 0: G holds L with Gamma = L L^T (forward, then backward substitution,
-// column by column); kind 1: G holds the pseudoinverse (x = b G).
+// column by column); kind 1: G holds the pseudoinverse (x = b G).  Broadcasts
+// read one lane through scalar registers.
 __device__ inline double wave_chol_solve(double b, const double* G, int R, int kind, int lane) {
   if (kind == 1) {
     double x = 0.0;
     for (int i = 0; i < R; ++i) {
-      const double bi = __shfl(b, i);
+      const double bi = wave_bcast(b, i);
       if (lane < R) x += bi * G[i * R + lane];
     }
     return x;
@@ -101,14 +102,14 @@ __device__ inline double wave_chol_solve(double b, const double* G, int R, int k
   // L y = b
   double y = b;
   for (int k = 0; k < R; ++k) {
-    const double yk = __shfl(y, k) / G[k * R + k];
+    const double yk = wave_bcast(y, k) / G[k * R + k];
     if (lane == k) y = yk;
     else if (lane > k && lane < R) y -= G[lane * R + k] * yk;
   }
   // L^T x = y
   double x = y;
   for (int k = R - 1; k >= 0; --k) {
-    const double xk = __shfl(x, k) / G[k * R + k];
+    const double xk = wave_bcast(x, k) / G[k * R + k];
     if (lane == k) x = xk;
     else if (lane < k) x -= G[k * R + lane] * xk;
   }
@@ -116,17 +117,17 @@ __device__ inline double wave_chol_solve(double b, const double* G, int R, int k
 }
 
 // Gauss-Seidel on one row x Gamma = b (Gamma in G), r = 0..R-1 in order, warm
-// start x0; lane j < R holds b_j and x_j.
+// start x0; lane j < R holds b_j and x_j.  Every lane forms the same sum
+// t = sum_k x_k Gamma(k, r) from broadcasts, in increasing k.
 __device__ inline double wave_gs(double b, double x, const double* G, int R, int iters, int lane) {
   for (int it = 0; it < iters; ++it) {
     for (int r = 0; r < R; ++r) {
       const double dg = G[r * R + r];
       if (dg == 0.0) continue;
-      double t = (lane < R) ? x * G[lane * R + r] : 0.0;
-      for (int off = 16; off > 0; off >>= 1) t += __shfl_xor(t, off);
-      t = __shfl(t, 0);   // lanes 0..31 hold the sum over the R <= 32 terms
-      const double br = __shfl(b, r);
-      const double xr = __shfl(x, r);
+      double t = 0.0;
+      for (int k = 0; k < R; ++k) t += wave_bcast(x, k) * G[k * R + r];
+      const double br = wave_bcast(b, r);
+      const double xr = wave_bcast(x, r);
       const double v = (br - t + xr * dg) / dg;
       if (lane == r) x = v;
     }
@@ -256,11 +257,13 @@ hipError_t epi_launch(const EpiDesc& d, hipStream_t st) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void finalize_kernel(PrepArgs a) {
   extern __shared__ double dsmem[];
-  sweep_prep(a, dsmem, true);
+  sweep_prep<16>(a, dsmem, true);
 }
 
-hipError_t finalize_launch(const PrepArgs& a, hipStream_t st) {
-  const size_t bytes = sizeof(double) * prep_smem_doubles(a.N, a.R);
+hipError_t finalize_launch(const PrepArgs& a0, hipStream_t st) {
+  PrepArgs a = a0;
+  a.lds = prep_smem_doubles(a.N, a.R);
+  const size_t bytes = sizeof(double) * a.lds;
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), bytes, st, a);
   return hipGetLastError();
 }
@@ -270,7 +273,7 @@ hipError_t finalize_launch(const PrepArgs& a, hipStream_t st) {
 __global__ __launch_bounds__(kThreads) void finalize_batched_kernel(const PrepArgs* __restrict__ pas,
                                                                     const int32_t* __restrict__ plist) {
   extern __shared__ double dsmem[];
-  sweep_prep(pas[plist[blockIdx.x]], dsmem, true);
+  sweep_prep<16>(pas[plist[blockIdx.x]], dsmem, true);
 }
 
 hipError_t finalize_batched_launch(const PrepArgs* pas, const int32_t* plist, int count,

@@ -44,7 +44,7 @@ def main(names):
 
 
 def fas_reference(name, coarsest_size=16, restart=0, nt=2, fit_tol=1e-12, max_cycles=500,
-                  max_sweeps=10000):
+                  max_sweeps=10000, als=True):
     """Setup phase (Algorithm 1 cycles, Table 1 setup parameters, stagnation rule of
     Section 6.1) from a seeded start with n_t seeded test blocks, then from its
     result: CP-FAS V-cycles (Algorithm 2, Table 1) and standalone ALS, each to a
@@ -75,22 +75,29 @@ def fas_reference(name, coarsest_size=16, restart=0, nt=2, fit_tol=1e-12, max_cy
         prev = fk
     out.update({"fas_cycles": len(fits), "fas_fit": fits[-1], "fas_fits": fits,
                 "fas_seconds": time.time() - t})
+    out["fas_converged"] = len(fits) < max_cycles
     # standalone ALS from the same point
-    t = time.time()
-    Aa, h = cp.als(Z, A, max_sweeps=max_sweeps, fit_tol=fit_tol, record="direct", sort_at_end=False)
-    out.update({"als_sweeps": h["sweeps"], "als_fit": h["fit"][-1], "als_seconds": time.time() - t})
+    if als:
+        t = time.time()
+        Aa, h = cp.als(Z, A, max_sweeps=max_sweeps, fit_tol=fit_tol, record="direct", sort_at_end=False)
+        out.update({"als_sweeps": h["sweeps"], "als_fit": h["fit"][-1], "als_seconds": time.time() - t})
     return out
+
+
+# 64^4: the oracle's sweeps take about a second each, so its reference keeps the
+# setup-phase hierarchy and the first V-cycles only
+FAS_ARGS = {"c4_64quart_r8": dict(max_cycles=3, als=False)}
 
 
 def main_fas(names):
     for name in names:
-        ref = fas_reference(name)
+        ref = fas_reference(name, **FAS_ARGS.get(name, {}))
         path = os.path.join(HERE, f"fas_{name}.json")
         with open(path, "w") as f:
             json.dump(ref, f)
         print(name, "setup", ref["setup_cycles"], f"{ref['setup_seconds']:.1f}s", "fas", ref["fas_cycles"],
-              ref["fas_fit"], f"{ref['fas_seconds']:.1f}s", "als", ref["als_sweeps"], ref["als_fit"],
-              f"{ref['als_seconds']:.1f}s", flush=True)
+              ref["fas_fit"], f"{ref['fas_seconds']:.1f}s", "als", ref.get("als_sweeps"), ref.get("als_fit"),
+              flush=True)
 
 
 if __name__ == "__main__":
