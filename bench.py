@@ -254,8 +254,10 @@ def main():
         batched = batched_leg(ctx, api, synth)
 
     multilevel = None
+    order4 = None
     if not args.no_multilevel:
         multilevel = fas_leg(ctx, api, drivers, synth)
+        order4 = order4_leg(ctx, api, drivers, synth, K)
 
     cpu = None
     if not args.no_cpu:
@@ -292,6 +294,7 @@ def main():
         "tuned_plans": plans.strip().splitlines() if plans else None,
         "batched": batched,
         "multilevel_128cube_r5": multilevel,
+        "order4_64quart_r8": order4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -340,6 +343,64 @@ def fas_leg(ctx, api, drivers, synth):
         out["als"]["rel_fit_err_vs_oracle"] = abs(fit_als - g["als_fit"]) / abs(g["als_fit"])
     log(f"128^3 FAS: {r.sweeps} V-cycles in {tf:.3f} s ({1e3 * tf / r.sweeps:.2f} ms/cycle), fit {r.final_fit:.13f}; "
         f"ALS: {ra.sweeps} sweeps in {ta:.3f} s, fit {fit_als:.13f}")
+    return out
+
+
+def order4_leg(ctx, api, drivers, synth, steps):
+    """64^4 R=8 (c = 0.8, 0.5% noise): ALS sweeps in both forms, each mode's MTTKRP,
+    and CP-FAS V-cycles on the 3-level hierarchy (64 -> 32 -> 16) of the oracle's
+    setup phase (stored weights and factors, an input here), mixed and FP64."""
+    import numpy as np
+    import torch
+    from paper_1111_6091_amd._lib import CP_FP64, CP_MIXED, CP_SOLVE_CHOL
+    Z, _, spec = synth.workload("c4_64quart_r8")
+    dims, R = tuple(spec["dims"]), spec["R"]
+    A0 = synth.uniform_start(dims, R, spec["seed"])
+    Zd = api.DeviceTensor.from_numpy(ctx, Z, fp32=True)
+    At = api.DeviceFactors.from_numpy(ctx, A0, fp32=True)
+    for prec in (CP_MIXED, CP_FP64):
+        api.cp_autotune(ctx, Zd, At, prec, 10)
+    out = {"dims": list(dims), "rank": R}
+    fh = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    for prec, tag in ((CP_MIXED, "mixed"), (CP_FP64, "fp64")):
+        A = api.DeviceFactors.from_numpy(ctx, A0, fp32=True)
+        api.cp_als_sweep(ctx, Zd, A, None, 10, CP_SOLVE_CHOL, 10, True, prec, fh)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.cp_als_sweep(ctx, Zd, A, None, steps, CP_SOLVE_CHOL, 10, True, prec, fh)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"{tag}_sweep_us"] = round(ms * 1e3, 2)
+        out[f"{tag}_sweeps_per_s"] = round(1e3 / ms, 1)
+        eb = 4 if prec == CP_MIXED else 8
+        out[f"{tag}_mttkrp_gbs"] = []
+        for n in range(4):
+            t = api.cp_time_mttkrp(ctx, Zd, A, n, prec, 50)
+            out[f"{tag}_mttkrp_gbs"].append(round(mttkrp_bytes(dims, R, n, eb) / (t * 1e-3) / 1e9, 1))
+    path = os.path.join(HERE, "tests", "golden", "fas_c4_64quart_r8.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            g = json.load(f)
+        weights = [[None if w is None else np.asarray(w) for w in lv] for lv in g["weights"]]
+        levels = drivers.build_hierarchy(ctx, Zd, weights, prec=CP_MIXED, fp32=True)
+        fas = {"levels": len(levels), "oracle_fits_3_cycles": g["fas_fits"]}
+        for prec, tag in ((CP_MIXED, "mixed"), (CP_FP64, "fp64")):
+            A = api.DeviceFactors.from_numpy(ctx, [np.asarray(a) for a in g["A_setup"]], fp32=True)
+            fits = []
+            for _ in range(3):
+                api.cp_fas_vcycle(ctx, levels, A, prec=prec)
+                fits.append(drivers.exact_fit(ctx, Zd, A))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                api.cp_fas_vcycle(ctx, levels, A, prec=prec)
+            torch.cuda.synchronize()
+            fas[tag] = {"ms_per_cycle": round((time.perf_counter() - t0) * 1e2, 3), "fits_3_cycles": fits,
+                        "max_rel_fit_err_vs_oracle": max(abs(a - b) / abs(b) for a, b in zip(fits, g["fas_fits"]))}
+        out["fas_3_levels"] = fas
+    log(f"64^4 R=8: mixed sweep {out['mixed_sweep_us']} us, fp64 sweep {out['fp64_sweep_us']} us; "
+        f"MTTKRP GB/s mixed {out['mixed_mttkrp_gbs']} fp64 {out['fp64_mttkrp_gbs']}; FAS {out.get('fas_3_levels')}")
     return out
 
 

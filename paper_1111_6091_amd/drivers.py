@@ -108,12 +108,13 @@ def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000
     return res
 
 
-def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False):
+def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False, fp64=True):
     """Levels for cp_fas_vcycle from interpolation weights.
 
     ``weights[l][n]``: (I_n x 2) numpy weights of mode n on level l, or None when
     that mode is not coarsened.  Operator prep (B, L, P^) and the coarse tensors
-    run on the device (cp_transfer_build, cp_restrict).
+    run on the device (cp_transfer_build, cp_restrict).  Coarse tensors are kept
+    in FP64 (``fp64``) and/or FP32 (``fp32``, implied by the mixed form).
     """
     torch = _torch()
     levels = []
@@ -130,7 +131,7 @@ def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False):
             api.cp_transfer_build(ctx, w, p)
             ph.append(p)
         cdims = tuple((d + 1) // 2 if ph[n] is not None else d for n, d in enumerate(cur.dims))
-        nxt = api.DeviceTensor.empty(cdims, fp64=(prec == CP_FP64) or not fp32,
+        nxt = api.DeviceTensor.empty(cdims, fp64=fp64 or prec == CP_FP64 or not fp32,
                                      fp32=fp32 or prec == CP_MIXED)
         if prec == CP_MIXED:
             api.cp_restrict(ctx, cur, ph, nxt, CP_MIXED)

@@ -222,3 +222,40 @@ def test_c5_whole_batch_fixed_sweeps_sampled(C):
                 Gk = got[n][:, k * p["R"]:(k + 1) * p["R"]]
                 assert rel_err(Gk, A[n]) < 1e-9, (b, k, n, rel_err(Gk, A[n]))
     assert C.status() == 0
+
+
+def _c4_golden():
+    path = os.path.join(GOLDEN, "fas_c4_64quart_r8.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/fas_c4_64quart_r8.json not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_c4_three_level_vcycles_match_oracle(C, mixed):
+    """64^4 R=8, 3 levels (64 -> 32 -> 16) from the oracle's setup phase: the first
+    three CP-FAS V-cycles against the oracle's (FP64 to rounding; the mixed form,
+    FP32 contractions and coarse tensors, to its FP32 error), and the fit after them."""
+    from paper_1111_6091_amd import api, drivers
+    from paper_1111_6091_amd._lib import CP_FP64, CP_MIXED
+    g = _c4_golden()
+    Z, _, spec = synth.workload("c4_64quart_r8")
+    weights = [[None if w is None else np.asarray(w) for w in lv] for lv in g["weights"]]
+    A = [np.asarray(a) for a in g["A_setup"]]
+    prec = CP_MIXED if mixed else CP_FP64
+    say(f"c4 3-level V-cycles mixed={mixed}")
+    Zd = api.DeviceTensor.from_numpy(C, Z, fp32=mixed)
+    dlev = drivers.build_hierarchy(C, Zd, weights, prec=prec, fp32=mixed)
+    assert len(dlev) == g["levels"] == 3
+    Ad = api.DeviceFactors.from_numpy(C, A, fp32=mixed)
+    fits = []
+    for _ in range(3):
+        api.cp_fas_vcycle(C, dlev, Ad, prec=prec, **amg.FAS_PARAMS)
+        fits.append(drivers.exact_fit(C, Zd, Ad))
+    sync()
+    say(f"  oracle fits {g['fas_fits']}; device {fits}")
+    tol = 1e-6 if mixed else 1e-11
+    for a, b in zip(fits, g["fas_fits"]):
+        assert abs(a - b) <= tol * abs(b)
+    assert C.status() == 0
