@@ -302,6 +302,7 @@ SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32) {
   sp.ydoubles = yd;
   PlanOpts o = sp.p[1].opts;
   o.ksplit = 1;
+  o.nostage = 0;   // the tile-storing variant is tuned with the factor staged
   sp.p1y = mttkrp_plan(N, dims, 1, R, fp32, o);
   sp.partial = std::max(sp.partial, sp.p1y.partial_doubles);
   sp.ynsplit.assign(N, 0);
@@ -875,13 +876,15 @@ cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_pr
       for (int t : targets) {
         if (t < 1) continue;
         for (int ks : kss)
-          for (int q = 0; q < ntw; ++q) {
-            PlanOpts o{t, ks, tws[q], vwo};
-            const MttkrpPlan p = mttkrp_plan(N, Z->dims, n, R, mixed, o);
-            if (p.ksplit != ks && ks != 0) continue;   // clamped duplicate
-            cands[n].push_back(o);
-            maxpart = std::max(maxpart, p.partial_doubles);
-          }
+          for (int q = 0; q < ntw; ++q)
+            for (int ns = 0; ns < 2; ++ns) {
+              PlanOpts o{t, ks, tws[q], vwo, ns};
+              const MttkrpPlan p = mttkrp_plan(N, Z->dims, n, R, mixed, o);
+              if (p.ksplit != ks && ks != 0) continue;   // clamped duplicate
+              if (ns && !p0.bl) continue;                 // never staged anyway
+              cands[n].push_back(o);
+              maxpart = std::max(maxpart, p.partial_doubles);
+            }
       }
     }
   }
@@ -925,7 +928,8 @@ cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_pr
     const std::string key = plan_key(N, Z->dims, n, R, mixed);
     ctx->tuned[key] = bo;
     ctx->plans.erase(key);
-    report << key << " " << bo.target_wgs << " " << bo.ksplit << " " << bo.tw << " " << bo.vw
+    report << key << " " << bo.target_wgs << " " << bo.ksplit << " " << bo.tw << " " << bo.vw << " "
+           << bo.nostage
            << " " << best << "\n";
   }
   (void)hipEventDestroy(e0);
@@ -938,7 +942,7 @@ const char* cp_plans_export(cp_ctx ctx) {
   std::ostringstream o;
   for (const auto& kv : ctx->tuned)
     o << kv.first << " " << kv.second.target_wgs << " " << kv.second.ksplit << " " << kv.second.tw
-      << " " << kv.second.vw << "\n";
+      << " " << kv.second.vw << " " << kv.second.nostage << "\n";
   ctx->plans_text = o.str();
   return ctx->plans_text.c_str();
 }
@@ -956,6 +960,9 @@ cp_status cp_plans_import(cp_ctx ctx, const char* text) {
     PlanOpts o{};
     if (!(ls >> key >> o.target_wgs >> o.ksplit >> o.tw >> o.vw) || o.target_wgs < 1 ||
         o.ksplit < 0 || (o.tw != 2 && o.tw != 4) || (o.vw != 4 && o.vw != 8))
+      return set_err(ctx, CP_ERR_INVALID, "cp_plans_import: bad line '%s'", line.c_str());
+    if (!(ls >> o.nostage)) o.nostage = 0;   // optional last field
+    if (o.nostage != 0 && o.nostage != 1)
       return set_err(ctx, CP_ERR_INVALID, "cp_plans_import: bad line '%s'", line.c_str());
     ctx->tuned[key] = o;
     ctx->plans.erase(key);

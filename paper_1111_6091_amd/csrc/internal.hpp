@@ -162,6 +162,8 @@ struct PlanOpts {
   int32_t ksplit;       // pieces of the contraction range (0: automatic)
   int32_t tw;           // 16-row tiles per wave, kinds 2/3 (0: 2)
   int32_t vw;           // FP32: tensor entries per lane load, 4 (16 B) or 8 (32 B)
+  int32_t nostage;      // 1: read the contracted factor from global memory instead of
+                        //    staging it in LDS at the start of every workgroup
 };
 
 struct MttkrpPlan {

@@ -771,7 +771,7 @@ MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, bool fp32, cons
   // when it takes at most 64 KB
   const int64_t Ik = p.kind == 1 ? I1 : I0;
   p.bstage_doubles = fp32 ? bstage_doubles<float>(Ik, p.nt) : bstage_doubles<double>(Ik, p.nt);
-  p.bl = p.bstage_doubles * 8 <= 64 * 1024 ? 1 : 0;
+  p.bl = (!o.nostage && p.bstage_doubles * 8 <= 64 * 1024) ? 1 : 0;
   if (!p.bl) p.bstage_doubles = 0;
   p.opts = o;
   return p;
