@@ -44,20 +44,21 @@ __device__ inline bool arrive_last(int32_t* counter, int nblk, int* s_flag) {
 }
 
 // Sum p[k * stride] for k = k0, k0 + step, ... < count in increasing k, with
-// 16 independent (predicated) loads in flight per round; the additions stay in
+// 32 independent (predicated) loads in flight per round; the additions stay in
 // order, and the padding adds exact zeros.
 __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int k0, int count,
                                               int step, size_t stride) {
+  constexpr int Q = 32;
   double s = 0.0;
-  for (int k = k0; k < count; k += 16 * step) {
-    double v[16];
+  for (int k = k0; k < count; k += Q * step) {
+    double v[Q];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int kk = k + q * step;
       v[q] = kk < count ? p[(size_t)kk * stride] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s += v[q];
+    for (int q = 0; q < Q; ++q) s += v[q];
   }
   return s;
 }
@@ -150,19 +151,32 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
   const int64_t row0 = (int64_t)blk * EPI_ROWS;
   const int nrows = (int)std::min<int64_t>(EPI_ROWS, d.In - row0);
   int kind = 0;
+  // Gamma^(n) prepared by the MTTKRP launch (factor / pseudoinverse / Gamma,
+  // then the column scale of M^(n) and sigma^(n), normalized coordinates):
+  // loaded into registers here, stored to LDS after the partial sums, so that
+  // both sets of loads are in flight together
+  constexpr int PQ = (kMaxRank * kMaxRank + 2 * kMaxRank + kThreads - 1) / kThreads;
+  double pv[PQ];
   if (d.op == EPI_UPDATE) {
-    // Gamma^(n) prepared by the MTTKRP launch: factor / pseudoinverse / Gamma,
-    // then the column scale of M^(n) and sigma^(n) (normalized coordinates)
-    for (int idx = tid; idx < R * R + 2 * R; idx += kThreads) {
-      const double v = d.prep_out[idx];
-      if (idx < R * R) sG[idx] = v;
-      else sC[idx - R * R] = v;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int idx = tid + q * kThreads;
+      pv[q] = idx < R * R + 2 * R ? d.prep_out[idx] : 0.0;
     }
     kind = *d.kind;
   } else if (d.op != EPI_STORE_M) {
     hadamard_gamma(d.grams, d.N, d.n, R, sG);
   }
   reduce_partials(d, row0, nrows, sM, sT);
+  if (d.op == EPI_UPDATE) {
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int idx = tid + q * kThreads;
+      if (idx < R * R) sG[idx] = pv[q];
+      else if (idx < R * R + 2 * R) sC[idx - R * R] = pv[q];
+    }
+    __syncthreads();
+  }
 
   if (d.op == EPI_STORE_M) {
     for (int idx = tid; idx < nrows * R; idx += kThreads) {
