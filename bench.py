@@ -93,6 +93,38 @@ def mttkrp_bytes(dims, R, n, elem_bytes):
     return P * elem_bytes + other * R * elem_bytes + dims[n] * R * 8
 
 
+def tree_y_doubles(dims, R, elem_bytes):
+    """FP64 entries of the stage-1 tiles Y = Z x_1 A^(1)T the sweep keeps, or 0 when
+    the sweep runs one pass over Z per mode (order 2, or Y above a quarter of Z)."""
+    if len(dims) < 3:
+        return 0
+    yd = math.prod(dims[2:]) * dims[1] * R
+    return yd if yd * 8 * 4 <= math.prod(dims) * elem_bytes else 0
+
+
+def sweep_mttkrp_bytes(dims, R, n, elem_bytes):
+    """Algorithmic bytes of the sweep's mode-n launch: with the dimension tree,
+    mode 1 also writes Y once and modes >= 2 read Y once (with the FP64 factors
+    of modes 1.. other than n) instead of the tensor."""
+    yd = tree_y_doubles(dims, R, elem_bytes)
+    if yd == 0 or n == 0:
+        return mttkrp_bytes(dims, R, n, elem_bytes)
+    if n == 1:
+        return mttkrp_bytes(dims, R, n, elem_bytes) + yd * 8
+    other = sum(d for m, d in enumerate(dims) if m >= 1 and m != n)
+    return yd * 8 + other * R * 8 + dims[n] * R * 8
+
+
+def sweep_kernel_name(dims, R, n, tag):
+    """Name of the sweep's mode-n MTTKRP launch (matches the counter summary)."""
+    tree = tree_y_doubles(dims, R, 4 if tag == "f32" else 8) > 0
+    if tree and n >= 2:
+        return "ymttkrp_modeN"
+    if tree and n == 1:
+        return f"mttkrp_mode1y_{tag}"
+    return f"mttkrp_{('mode0', 'mode1', 'modeN')[min(n, 2)]}_{tag}"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -141,17 +173,22 @@ def main():
             f.write(plans)
 
     if args.mttkrp_only:
+        # the sweep's launches (dimension tree), then one pass over Z per mode
+        from paper_1111_6091_amd._lib import CP_OPT_DIMTREE
         A = fresh()
-        for prec in (CP_MIXED, CP_FP64):
-            for n in range(len(dims)):
-                api.cp_time_mttkrp(ctx, Zd, A, n, prec, K)
+        for tree in (1, 0):
+            ctx.set_option(CP_OPT_DIMTREE, tree)
+            for prec in (CP_MIXED, CP_FP64):
+                for n in range(len(dims)):
+                    api.cp_time_mttkrp(ctx, Zd, A, n, prec, K)
+        ctx.set_option(CP_OPT_DIMTREE, 1)
         src = torch.empty(64 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(K):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"mttkrp-only: {K} launches of each MTTKRP (mixed, fp64 x {len(dims)} modes) and of a "
-            f"64 MiB copy; kernel source hash {kernel_source_hash()}")
+        log(f"mttkrp-only: {K} launches of each MTTKRP (dimension tree on and off, mixed and fp64, "
+            f"{len(dims)} modes) and of a 64 MiB copy; kernel source hash {kernel_source_hash()}")
         return
 
     def timed(prec, steps, warm):
@@ -181,16 +218,17 @@ def main():
     ctx.set_option(CP_OPT_DIMTREE, 1)
     log(f"per-mode MTTKRPs: mixed {ms_mixed_pm * 1e3:.1f} us, fp64 {ms_fp64_pm * 1e3:.1f} us per sweep")
 
-    # roofline leg: each MTTKRP kernel timed over back-to-back launches in the
-    # launch configuration the sweep uses (HIP events on the library's stream)
+    # roofline leg: each MTTKRP launch of the sweep timed over back-to-back
+    # launches in the sweep's launch configuration (HIP events on the library's
+    # stream); with the dimension tree, modes >= 2 are the launches contracting Y
     A = fresh()
     reps = max(10, min(K, 100))
     roof = {}
     for prec, tag, eb in ((CP_MIXED, "f32", 4), (CP_FP64, "f64", 8)):
         for n in range(len(dims)):
             ms = api.cp_time_mttkrp(ctx, Zd, A, n, prec, reps)
-            b = mttkrp_bytes(dims, R, n, eb)
-            roof[f"{tag}_mode{n}"] = dict(kernel=f"mttkrp_{('mode0', 'mode1', 'modeN')[min(n, 2)]}_{tag}",
+            b = sweep_mttkrp_bytes(dims, R, n, eb)
+            roof[f"{tag}_mode{n}"] = dict(kernel=sweep_kernel_name(dims, R, n, tag),
                                           avg_us=ms * 1e3, bytes_per_launch=b,
                                           achieved_gbs=b / (ms * 1e-3) / 1e9)
             log(f"{tag} mode {n}: {ms * 1e3:.2f} us/launch, {b / (ms * 1e-3) / 1e9:.0f} GB/s")
@@ -375,9 +413,11 @@ def order4_leg(ctx, api, drivers, synth, steps):
         out[f"{tag}_sweeps_per_s"] = round(1e3 / ms, 1)
         eb = 4 if prec == CP_MIXED else 8
         out[f"{tag}_mttkrp_gbs"] = []
+        out[f"{tag}_mttkrp_us"] = []
         for n in range(4):
             t = api.cp_time_mttkrp(ctx, Zd, A, n, prec, 50)
-            out[f"{tag}_mttkrp_gbs"].append(round(mttkrp_bytes(dims, R, n, eb) / (t * 1e-3) / 1e9, 1))
+            out[f"{tag}_mttkrp_us"].append(round(t * 1e3, 2))
+            out[f"{tag}_mttkrp_gbs"].append(round(sweep_mttkrp_bytes(dims, R, n, eb) / (t * 1e-3) / 1e9, 1))
     path = os.path.join(HERE, "tests", "golden", "fas_c4_64quart_r8.json")
     if os.path.exists(path):
         with open(path) as f:

@@ -234,7 +234,10 @@ cp_status cp_profile_read(cp_ctx ctx, double* ms, int32_t* counts);
  * with the sweep-bookkeeping workgroup working on scratch Grams and scales;
  * partial sums land in the workspace, neither M nor A is written), between two
  * HIP events recorded on the context's stream; synchronize and return the
- * mean milliseconds per launch in *ms (host). */
+ * mean milliseconds per launch in *ms (host).  When the dimension tree applies
+ * (CP_OPT_DIMTREE on, order >= 3, Y at most a quarter of Z's bytes), mode 1 is
+ * the launch that also stores Y into the workspace and modes >= 2 are the
+ * launches that contract Y, which one untimed mode-1 launch fills first. */
 cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
                          cp_prec prec, int32_t reps, double* ms);
 

@@ -817,26 +817,41 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: bad mode %d", n);
   if (reps < 1 || !ms) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: reps < 1 or ms NULL");
   const int R = A->rank;
-  MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, R, mixed);
+  // the launch the sweep makes for mode n: with the dimension tree, mode 1 also
+  // stores Y and modes >= 2 contract Y (filled by one untimed mode-1 launch)
+  const SweepPlan sp = sweep_plan(ctx, Z->dims, N, R, mixed);
+  const bool tree = sp.dimtree && n >= 1;
+  const MttkrpPlan plan = tree ? sp.p1y : get_plan(ctx, N, Z->dims, n, R, mixed);
   Sizer sz;
   sz.take<double>((size_t)N * R * R);
   sz.take<double>((size_t)N * R);
-  sz.take<double>(plan.partial_doubles);
+  sz.take<double>(tree ? sp.partial : plan.partial_doubles);
+  sz.take<double>(tree ? sp.ydoubles : 0);
   if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
   Arena ar(ctx->ws);
   double* grams = ar.take<double>((size_t)N * R * R);
   double* sigma = ar.take<double>((size_t)N * R);
-  double* part = ar.take<double>(plan.partial_doubles);
+  double* part = ar.take<double>(tree ? sp.partial : plan.partial_doubles);
+  double* y = tree ? ar.take<double>(sp.ydoubles) : nullptr;
   HIPCHK(gram_launch(A->a, nullptr, Z->dims, N, R, grams, ctx->stream, sigma));
   const PrepArgs pa = timing_prep(ctx, Z, A, n, grams, sigma);
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  auto launch = [&]() -> hipError_t {
+    if (tree && n >= 2)
+      return ymttkrp_launch(Z->dims, N, n, R, y, A->a, part, sp.ynsplit[n], &pa, ctx->stream);
+    return mttkrp_launch(plan, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part, &pa,
+                         ctx->stream, y);
+  };
+  if (tree && n >= 2) {
+    const PrepArgs pa1 = timing_prep(ctx, Z, A, 1, grams, sigma);
+    HIPCHK(mttkrp_launch(sp.p1y, Z->dims, N, 1, R, z, mixed, A->a, (const float* const*)A->a32, part, &pa1,
+                         ctx->stream, y));
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, ctx->stream));
-  for (int k = 0; k < reps; ++k)
-    HIPCHK(mttkrp_launch(plan, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
-                         &pa, ctx->stream));
+  for (int k = 0; k < reps; ++k) HIPCHK(launch());
   HIPCHK(hipEventRecord(e1, ctx->stream));
   HIPCHK(hipEventSynchronize(e1));
   float t = 0.f;

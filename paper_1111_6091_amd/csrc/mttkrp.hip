@@ -163,9 +163,11 @@ __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, 
 // Workgroup 0 of a launch with prep set does the sweep bookkeeping for the
 // update that follows (sweep.hpp), concurrently with the streaming workgroups;
 // it is dispatched first, so it is resident from the start.
+// NT: 16-column tiles of the kernel (R <= 16 NT).
+template <int NT>
 __device__ __forceinline__ bool prep_block(const MttkrpDesc& d, int blk, double* smem) {
   if (!d.prep || blk != 0) return false;
-  sweep_prep(d.pa, smem, false);
+  sweep_prep<8, 16 * NT>(d.pa, smem, false);
   return true;
 }
 
@@ -184,7 +186,7 @@ __device__ __forceinline__ void kind1_body(const MttkrpDesc& d, int blk, double*
   constexpr int PANEL = 16 * VW;
   // 16 lanes x 16 bytes cover two whole lines only for 4-wide FP32 loads
   constexpr bool NTH = sizeof(T) == 4 && VW == 4;
-  if (prep_block(d, blk, smem)) return;
+  if (prep_block<NT>(d, blk, smem)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
@@ -329,7 +331,7 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
   typedef typename Vec4<T>::type V;
   constexpr int KC = 4 * VW;   // contraction chunk per step of the loop
   constexpr int ROWS = 16 * TW;
-  if (prep_block(d, blk, smem)) return;
+  if (prep_block<NT>(d, blk, smem)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
@@ -583,7 +585,7 @@ template <int RM>
 __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
   extern __shared__ double smem[];
   if (d.prep && blockIdx.x == 0) {
-    sweep_prep<16>(d.pa, smem, false);
+    sweep_prep<16, RM>(d.pa, smem, false);
     return;
   }
   const int bid = blockIdx.x - d.prep;

@@ -1,5 +1,5 @@
 // Small dense linear algebra on R x R matrices (R <= 32) for one workgroup.
-// Every thread of the workgroup must call these functions (they use
+// Every thread of the workgroup must call the wg_ functions (they use
 // __syncthreads); the first wave does the arithmetic, lane = matrix row.
 #pragma once
 
@@ -24,96 +24,100 @@ __device__ inline void hadamard_gamma(const double* __restrict__ grams, int N, i
   __syncthreads();
 }
 
-// In-place Cholesky factorization G = L L^T of the symmetric R x R matrix in
-// LDS (row-major; the lower triangle of G becomes L, the upper triangle is left
-// stale).  Returns 1 in every thread if a pivot is <= R * eps * max diag(G)
-// (or the diagonal is not positive).  Wave 0 does the work: lane i keeps row i
-// in registers (RM >= R columns, loops unrolled), pivots and the entries
-// L(k, j) reach every lane through scalar reads (readlane).
+// 1/sqrt(d) for a positive normal double: the hardware estimate refined by two
+// Newton-Raphson steps y <- y (3/2 - (d/2) y^2) (within an ulp or two).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// W = L^-1 for the Cholesky factor L of the symmetric positive definite R x R
+// matrix G (LDS, row-major), so that G^-1 = W^T W.  Wave 0, lane i holds row i
+// in registers; rows and columns R..RM-1 are padded with the identity, so every
+// step is straight-line code.
+//  1. Cholesky, right-looking: step k takes the pivot a_kk, forms column k of L
+//     (a_ik / sqrt(a_kk)) and subtracts L_ik L_jk from the trailing entries.
+//     Bad when max diag(G) <= 0 or a pivot is <= R eps max diag(G).
+//  2. Rows of W in order: row k is final after step k (W_kk = 1/L_kk,
+//     W_kj = -acc_kj / L_kk), then every later row i adds L_ik W_kj to its
+//     accumulator acc_ij = sum_{k<i} L_ik W_kj, kept in place of L_ij.
+// Values from one lane reach every lane through scalar reads (readlane), all
+// issued before the updates that use them.  Writes W (zeros above the
+// diagonal) to out, lane i < R writing row i, unless bad; returns bad
+// (wave-uniform).
 template <int RM>
-__device__ inline int wave_cholesky(double* G, int R) {
-  __shared__ int s_fail;
-  const int tid = threadIdx.x;
-  if (tid < 64) {
-    const int lane = tid;
-    const bool own = lane < R;
-    double g[RM];
+__device__ inline bool wave_chol_inverse(const double* G, int R, double* out) {
+  const int lane = threadIdx.x & 63;
+  double a[RM];
 #pragma unroll
-    for (int k = 0; k < RM; ++k) g[k] = (own && k < R) ? G[lane * R + k] : 0.0;
-    double dmax = 0.0;
-    for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * R + i]);
-    const double thr = R * kEps * dmax;
-    int fail = dmax > 0.0 ? 0 : 1;
+  for (int k = 0; k < RM; ++k) a[k] = (lane < R && k < R) ? G[lane * R + k] : (lane == k ? 1.0 : 0.0);
+  double dmax = 0.0;
 #pragma unroll
-    for (int j = 0; j < RM; ++j) {
-      if (j < R && !fail) {
-        const double piv = wave_bcast(g[j], j);
-        if (!(piv > thr)) {
-          fail = 1;
-        } else {
-          const double dj = sqrt(piv);
-          const double l = lane == j ? dj : (lane > j ? g[j] / dj : g[j]);
-          g[j] = l;
+  for (int k = 0; k < RM; ++k)
+    if (k < R) dmax = fmax(dmax, wave_bcast(a[k], k));
+  const double thr = R * kEps * dmax;
+  bool bad = !(dmax > 0.0);
+  double dinv = 1.0;   // 1 / L_ii of this lane's row
 #pragma unroll
-          for (int k = j + 1; k < RM; ++k) {
-            if (k < R) {
-              const double lk = wave_bcast(l, k);
-              if (lane >= k) g[k] -= l * lk;
-            }
-          }
-        }
-      }
+  for (int k = 0; k < RM; ++k) {
+    if (k < R) {
+      const double piv = wave_bcast(a[k], k);
+      bad = bad || !(piv > thr);
+      const double rs = rsqrt_nr(piv);
+      if (lane == k) dinv = rs;
+      const double l = a[k] * rs;
+      a[k] = l;
+      double lj[RM];
+#pragma unroll
+      for (int j = k + 1; j < RM; ++j) lj[j] = wave_bcast(l, j);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = k + 1; j < RM; ++j) a[j] = fma(-l, lj[j], a[j]);
     }
-    if (!fail && own) {
-#pragma unroll
-      for (int k = 0; k < RM; ++k)
-        if (k < R && k <= lane) G[lane * R + k] = g[k];
-    }
-    if (lane == 0) s_fail = fail;
   }
-  __syncthreads();
-  return s_fail;
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+    if (k < R) {
+      const double dk = wave_bcast(dinv, k);
+      double wk[RM];
+#pragma unroll
+      for (int j = 0; j < k; ++j) wk[j] = -wave_bcast(a[j], k) * dk;
+      __builtin_amdgcn_sched_barrier(0);
+      const double c = lane > k ? a[k] : 0.0;
+#pragma unroll
+      for (int j = 0; j < k; ++j) a[j] = fma(c, wk[j], a[j]);
+      a[k] = c * dk;
+    }
+  }
+  if (!bad && lane < R) {
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+      if (j < R) out[lane * R + j] = j < lane ? -a[j] * dinv : (j == lane ? dinv : 0.0);
+  }
+  return bad;
 }
 
-// The same factorization with rows kept in LDS (few registers): lane i owns
-// row i; pivots and L(k, j) are broadcast through scalar reads.
-__device__ inline int wave_cholesky_lds(double* G, int R) {
-  __shared__ int s_fail;
-  const int tid = threadIdx.x;
-  if (tid < 64) {
-    const int lane = tid;
-    const bool own = lane < R;
-    double dmax = 0.0;
-    for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * R + i]);
-    const double thr = R * kEps * dmax;
-    int fail = dmax > 0.0 ? 0 : 1;
-    for (int j = 0; j < R && !fail; ++j) {
-      const double gj = own ? G[lane * R + j] : 0.0;
-      const double piv = wave_bcast(gj, j);
-      if (!(piv > thr)) {
-        fail = 1;
-        break;
-      }
-      const double dj = sqrt(piv);
-      const double l = lane == j ? dj : (lane > j && own ? gj / dj : 0.0);
-      if (own && lane >= j) G[lane * R + j] = l;
-      for (int k = j + 1; k < R; ++k) {
-        const double lk = wave_bcast(l, k);
-        if (own && lane >= k) G[lane * R + k] -= l * lk;
-      }
-    }
-    if (lane == 0) s_fail = fail;
+// The factor inverse above for every thread of the workgroup (wave 0 works;
+// RMAX: the largest rank bucket instantiated, R <= RMAX).  Returns 1 in every
+// thread when G failed the factorization test (nothing written to out).
+template <int RMAX>
+__device__ inline int wg_chol_inverse(const double* G, int R, double* out) {
+  __shared__ int s_bad;
+  if (threadIdx.x < 64) {
+    bool bad;
+    if (R <= 4) bad = wave_chol_inverse<4>(G, R, out);
+    else if (R <= 8) bad = wave_chol_inverse<8>(G, R, out);
+    else if (R <= 12) bad = wave_chol_inverse<12>(G, R, out);
+    else if (RMAX <= 16 || R <= 16) bad = wave_chol_inverse<16>(G, R, out);
+    else if (R <= 24) bad = wave_chol_inverse<RMAX <= 16 ? 16 : 24>(G, R, out);
+    else bad = wave_chol_inverse<RMAX <= 16 ? 16 : 32>(G, R, out);
+    if (threadIdx.x == 0) s_bad = bad ? 1 : 0;
   }
   __syncthreads();
-  return s_fail;
-}
-
-// REG: rows in registers (standalone bookkeeping kernels); otherwise in LDS
-// (inside streaming kernels, whose register budget it must not raise).
-template <bool REG>
-__device__ inline int wg_cholesky(double* G, int R) {
-  if (!REG) return wave_cholesky_lds(G, R);
-  return R <= 16 ? wave_cholesky<16>(G, R) : wave_cholesky<32>(G, R);
+  return s_bad;
 }
 
 // Pseudoinverse of the symmetric PSD matrix G (R x R) by cyclic Jacobi:
@@ -193,39 +197,6 @@ __device__ inline int wg_pinv(const double* G, int R, double* S, double* V, doub
   }
   __syncthreads();
   return kept == 0 ? 1 : 0;
-}
-
-// Factor Gamma^(n) for the ALS update: writes L (kind 0) or the pseudoinverse
-// (kind 1) to `out` (global, R*R) and the kind to *kind.  Needs LDS scratch of
-// 4*R*R doubles.
-__device__ inline void gamma_prepare(const double* __restrict__ grams, int N, int n, int R,
-                                     double* __restrict__ out, int32_t* __restrict__ kind,
-                                     uint32_t* __restrict__ flags, double* lds) {
-  double* G = lds;
-  double* S = lds + R * R;
-  double* V = lds + 2 * R * R;
-  double* P = lds + 3 * R * R;
-  hadamard_gamma(grams, N, n, R, G);
-  // keep a copy of Gamma in P (the Cholesky overwrites G)
-  for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) P[idx] = G[idx];
-  __syncthreads();
-  const int fail = wg_cholesky<false>(G, R);
-  __syncthreads();
-  if (!fail) {
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = G[idx];
-    if (threadIdx.x == 0) *kind = 0;
-  } else {
-    // restore Gamma from P into G, then pseudoinverse into P
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) G[idx] = P[idx];
-    __syncthreads();
-    const int zero = wg_pinv(G, R, S, V, P);
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = P[idx];
-    if (threadIdx.x == 0) {
-      *kind = 1;
-      atomicOr(flags, zero ? (CP_FLAG_PINV_FALLBACK | CP_FLAG_NOT_SPD) : CP_FLAG_PINV_FALLBACK);
-    }
-  }
-  __syncthreads();
 }
 
 }  // namespace cpamg

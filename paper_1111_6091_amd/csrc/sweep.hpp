@@ -75,21 +75,17 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
     }
 }
 
-// Factor Gamma (in G, LDS) for the ALS update: L (kind 0) or the pseudoinverse
-// (kind 1) is written to out[0..R*R).  S, V, P: LDS scratch of R*R each.
-template <bool REG>
+// Gamma (in G, LDS, left unchanged) for the ALS update: the inverse W = L^-1
+// of its Cholesky factor (kind 0, Gamma^-1 = W^T W) or, when it fails the
+// factorization test, its pseudoinverse (kind 1) is written to out[0..R*R).  S, V, P: LDS scratch of R*R each.  RMAX: the largest rank
+// bucket the calling kernel instantiates (R <= RMAX).
+template <int RMAX>
 __device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind, uint32_t* flags,
                                     double* S, double* V, double* P) {
-  for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) P[idx] = G[idx];
-  __syncthreads();
-  const int fail = wg_cholesky<REG>(G, R);
-  __syncthreads();
+  const int fail = wg_chol_inverse<RMAX>(G, R, out);
   if (!fail) {
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = G[idx];
     if (threadIdx.x == 0) *kind = 0;
   } else {
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) G[idx] = P[idx];
-    __syncthreads();
     const int zero = wg_pinv(G, R, S, V, P);
     for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = P[idx];
     if (threadIdx.x == 0) {
@@ -160,7 +156,7 @@ __device__ inline void batch_rules(BatchState* st, const BatchRule& ru, const do
 // preparing an update.  With a.groups > 1 the R columns form independent
 // groups: Gamma is block-diagonal, f is evaluated per group, and in a batched
 // solve (a.st) frozen groups are neither renormalized nor updated.
-template <int LK = 8>
+template <int LK = 8, int RMAX = 32>
 __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
   __shared__ double sred[8];
   __shared__ double sfit[kMaxGroups];
@@ -308,7 +304,7 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
     __syncthreads();
     return;
   }
-  gamma_factor<LK != 8>(G, R, a.out, a.kind, a.flags, S, V, P);
+  gamma_factor<RMAX>(G, R, a.out, a.kind, a.flags, S, V, P);
 }
 
 }  // namespace cpamg

@@ -87,34 +87,40 @@ __device__ inline void reduce_partials(const EpiDesc& d, int64_t row0, int nrows
   __syncthreads();
 }
 
-// Solve one row x Gamma = b on one wavefront: lane j < R holds b_j, returns x_j.
-// kind 0: G holds L with Gamma = L L^T (forward, then backward substitution,
-// column by column); kind 1: G holds the pseudoinverse (x = b G).  Broadcasts
-// read one lane through scalar registers.
-__device__ inline double wave_chol_solve(double b, const double* G, int R, int kind, int lane) {
-  if (kind == 1) {
-    double x = 0.0;
-    for (int i = 0; i < R; ++i) {
-      const double bi = wave_bcast(b, i);
-      if (lane < R) x += bi * G[i * R + lane];
-    }
-    return x;
+// One row solve x Gamma = b on one wavefront (lane c < R holds b_c, gets x_c),
+// with X in LDS (R x R).  kind 0: X = W = L^-1 for Gamma = L L^T, so
+// x = (b W^T) W: y_i = sum_j W_ij b_j, then x_c = sum_i y_i W_ic; kind 1: X is
+// the pseudoinverse, x_c = sum_k b_k X_kc.  Sums in increasing index order;
+// values of other lanes arrive through scalar reads.  RM >= R.
+template <int RM>
+__device__ inline double wave_apply(double b, const double* X, int R, int kind, int lane) {
+  const int c = lane < R ? lane : 0;
+  double v = b;
+  if (kind == 0) {
+    double wr[RM];
+#pragma unroll
+    for (int j = 0; j < RM; ++j) wr[j] = j < R ? X[c * R + j] : 0.0;
+    double y = 0.0;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) y = fma(wr[j], wave_bcast(b, j), y);
+    v = lane < R ? y : 0.0;
   }
-  // L y = b
-  double y = b;
-  for (int k = 0; k < R; ++k) {
-    const double yk = wave_bcast(y, k) / G[k * R + k];
-    if (lane == k) y = yk;
-    else if (lane > k && lane < R) y -= G[lane * R + k] * yk;
-  }
-  // L^T x = y
-  double x = y;
-  for (int k = R - 1; k >= 0; --k) {
-    const double xk = wave_bcast(x, k) / G[k * R + k];
-    if (lane == k) x = xk;
-    else if (lane < k) x -= G[k * R + lane] * xk;
-  }
+  double xc[RM];
+#pragma unroll
+  for (int k = 0; k < RM; ++k) xc[k] = k < R ? X[k * R + c] : 0.0;
+  double x = 0.0;
+#pragma unroll
+  for (int k = 0; k < RM; ++k) x = fma(wave_bcast(v, k), xc[k], x);
   return x;
+}
+
+__device__ inline double wave_apply_any(double b, const double* X, int R, int kind, int lane) {
+  if (R <= 4) return wave_apply<4>(b, X, R, kind, lane);
+  if (R <= 8) return wave_apply<8>(b, X, R, kind, lane);
+  if (R <= 12) return wave_apply<12>(b, X, R, kind, lane);
+  if (R <= 16) return wave_apply<16>(b, X, R, kind, lane);
+  if (R <= 24) return wave_apply<24>(b, X, R, kind, lane);
+  return wave_apply<32>(b, X, R, kind, lane);
 }
 
 // Gauss-Seidel on one row x Gamma = b (Gamma in G), r = 0..R-1 in order, warm
@@ -151,7 +157,7 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
   const int64_t row0 = (int64_t)blk * EPI_ROWS;
   const int nrows = (int)std::min<int64_t>(EPI_ROWS, d.In - row0);
   int kind = 0;
-  // Gamma^(n) prepared by the MTTKRP launch (factor / pseudoinverse / Gamma,
+  // Gamma^(n) prepared by the MTTKRP launch (inverse / pseudoinverse / Gamma,
   // then the column scale of M^(n) and sigma^(n), normalized coordinates):
   // loaded into registers here, stored to LDS after the partial sums, so that
   // both sets of loads are in flight together
@@ -224,7 +230,7 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
     const double b = (lane < R) ? m + (d.F ? d.F[row * R + lane] : 0.0) : 0.0;
     double x;
     if (kind != 2) {
-      x = wave_chol_solve(b, sG, R, kind, lane);
+      x = wave_apply_any(b, sG, R, kind, lane);
     } else {
       const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
       x = wave_gs(b, x0, sG, R, d.gs_iters, lane);
