@@ -32,10 +32,24 @@ __device__ inline double wg_sum(double v, double* sred) {
 // U (LDS, R*R) = A^T A for A (I x R row-major, global) on the matrix cores:
 // v_mfma_f64_16x16x4f64 over blocks of 4 rows, lane l supplying row 4b + l/16,
 // column 16t + l%16 as both operands of a diagonal tile (16x16 output tiles
-// (ta, tb), ta <= tb, mirrored).  Wave w takes the row blocks w, w + 4, ...;
-// the four wave sums are added in wave order.
-template <int Q>   // row blocks in flight per wave
-__device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R, double* U) {
+// (ta, tb), ta <= tb, mirrored).  Wave w takes the row blocks w, w + 4, ...,
+// Q of them per round of loads; the four wave sums are added in wave order.
+// gram_first_loads issues the first round of tile (0, 0) early (into pre), so
+// that it shares a round trip with other loads; gram_mfma consumes it.
+template <int Q>
+__device__ inline void gram_first_loads(const double* __restrict__ A, int64_t I, int R, double (&pre)[Q]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t row = (int64_t)(wave + 4 * q) * 4 + kq;
+    pre[q] = (row < I && r16 < R) ? A[row * R + r16] : 0.0;
+  }
+}
+
+template <int Q>
+__device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R, double* U,
+                                 const double (&pre)[Q]) {
   typedef double d4v __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -45,17 +59,37 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
     for (int tb = ta; tb < nt; ++tb) {
       d4v acc = {0.0, 0.0, 0.0, 0.0};
       const int ca = ta * 16 + r16, cb = tb * 16 + r16;
-      for (int64_t b0 = wave; b0 < nblk; b0 += 4 * Q) {
-        double va[Q], vb[Q];
+      int64_t b0 = wave;
+      if (ta == 0 && tb == 0) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int64_t row = (b0 + 4 * q) * 4 + kq;
-          const bool okr = row < I;
-          va[q] = (okr && ca < R) ? A[row * R + ca] : 0.0;
-          vb[q] = (ta == tb) ? va[q] : ((okr && cb < R) ? A[row * R + cb] : 0.0);
+        for (int q = 0; q < Q; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pre[q], pre[q], acc, 0, 0, 0);
+        b0 += 4 * Q;
+      }
+      if (ta == tb) {
+        for (; b0 < nblk; b0 += 4 * Q) {
+          double va[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const int64_t row = (b0 + 4 * q) * 4 + kq;
+            va[q] = (row < I && ca < R) ? A[row * R + ca] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < Q; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], va[q], acc, 0, 0, 0);
         }
+      } else {
+        constexpr int Q2 = Q / 2;
+        for (; b0 < nblk; b0 += 4 * Q2) {
+          double va[Q2], vb[Q2];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], vb[q], acc, 0, 0, 0);
+          for (int q = 0; q < Q2; ++q) {
+            const int64_t row = (b0 + 4 * q) * 4 + kq;
+            const bool okr = row < I;
+            va[q] = (okr && ca < R) ? A[row * R + ca] : 0.0;
+            vb[q] = (okr && cb < R) ? A[row * R + cb] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < Q2; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], vb[q], acc, 0, 0, 0);
+        }
       }
       // D(m, n), m = 16 ta + kq + 4 v, n = 16 tb + r16
       for (int w = 0; w < 4; ++w) {
@@ -175,8 +209,18 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   double* sS = U + RR;       // sigma, N x R
   const int lds = a.lds > prep_min_doubles(N, R) ? a.lds : prep_min_doubles(N, R);
   double* sGr = prep_stage_grams(N, R, lds) ? sS + N * R : nullptr;   // stored Grams, N x R x R
+  // one round trip for every global load of the step: the first Gram operands
+  // of the factor updated last, the boundary's inner-product partials, then
+  // the scales and stored Grams
+  // (inside a streaming kernel 8 row blocks per wave and round, not 16, to keep
+  // its register count)
+  constexpr int GQ = LK == 8 ? 8 : 16;
+  double gpre[GQ];
+  if (a.p >= 0) gram_first_loads<GQ>(a.Ap, a.Ip, R, gpre);
+  const bool want_f = a.boundary && active && (a.f_slot || st);
+  const double ip0 = (want_f && tid < a.inner_count) ? a.inner_part[(size_t)tid * NG] : 0.0;
   prep_load<LK>(a, sS, sGr);
-  if (a.p >= 0) gram_mfma<LK == 8 ? 4 : 16>(a.Ap, a.Ip, R, U);
+  if (a.p >= 0) gram_mfma<GQ>(a.Ap, a.Ip, R, U, gpre);
   // the updated factor is normalized (frozen groups kept their columns)
   if (a.p >= 0 && tid < R && !col_frozen(tid)) sS[a.p * R + tid] = 1.0;
   __syncthreads();
@@ -184,13 +228,15 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
     return m == a.p ? U[idx] : (sGr ? sGr[m * RR + idx] : a.grams[(size_t)m * RR + idx]);
   };
   if (a.boundary && active) {
-    if (a.f_slot || st) {
+    if (want_f) {
       // per group: f = 1/2 (||Z||^2 - 2 <A^(N), M^(N)> + 1^T (*_m Upsilon^(m)) 1),
-      // in normalized coordinates
+      // in normalized coordinates (partials of blocks b = tid + kThreads j;
+      // that of block tid, group 0 loaded above)
       double ipg[kMaxGroups];
 #pragma unroll
-      for (int g = 0; g < kMaxGroups; ++g) ipg[g] = 0.0;
-      for (int b = tid; b < a.inner_count; b += kThreads)
+      for (int g = 0; g < kMaxGroups; ++g)
+        ipg[g] = g == 0 ? ip0 : ((g < NG && tid < a.inner_count) ? a.inner_part[(size_t)tid * NG + g] : 0.0);
+      for (int b = tid + kThreads; b < a.inner_count; b += kThreads)
 #pragma unroll
         for (int g = 0; g < kMaxGroups; ++g)
           if (g < NG) ipg[g] += a.inner_part[(size_t)b * NG + g];
