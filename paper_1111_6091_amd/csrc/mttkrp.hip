@@ -560,9 +560,12 @@ __global__ __launch_bounds__(kThreads) void mttkrp_kind23(MttkrpDesc d) {
 // workgroup tiles[t].y of the launch described by descs[tiles[t].x].  Every
 // problem stages its contracted factor in LDS; 4-wide loads where the problem
 // allows them.  Tiles of problems with nothing left in the current phase exit.
+// (the FP32 mode-0 variant is held at the three waves per SIMD its streaming
+// path fits, one register above which the bookkeeping path would push it)
 template <typename T, int NT, int KIND>
-__global__ __launch_bounds__(kThreads) void mttkrp_batched(const MttkrpDesc* __restrict__ descs,
-                                                           const int2* __restrict__ tiles) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu((NT == 1 && KIND == 1 && sizeof(T) == 4) ? 3 : 1)))
+void mttkrp_batched(const MttkrpDesc* __restrict__ descs, const int2* __restrict__ tiles) {
   extern __shared__ double smem[];
   const int2 t = tiles[blockIdx.x];
   const MttkrpDesc& d = descs[t.x];
@@ -814,8 +817,13 @@ static const void* select_kernel(const MttkrpPlan& p, bool fp32, bool vec, bool 
 size_t mttkrp_smem_bytes(const MttkrpPlan& p, int N, int R, bool prep) {
   int64_t d = p.kind == 1 ? kind1_smem() : kind23_smem(p.tw, p.nt, p.kind == 3);
   if (p.bl) d = std::max<int64_t>(d, p.bstage_doubles);
-  // the bookkeeping workgroup works within the streaming workgroups' LDS
-  if (prep) d = std::max<int64_t>(d, prep_min_doubles(N, R));
+  // the bookkeeping workgroup works within the streaming workgroups' LDS; it
+  // stages the stored Grams too when that needs at most 16 KB or no more
+  // than the streaming workgroups use anyway
+  if (prep) {
+    const int64_t full = prep_smem_doubles(N, R);
+    d = std::max<int64_t>(d, full <= std::max<int64_t>(d, 2048) ? full : prep_min_doubles(N, R));
+  }
   return sizeof(double) * (size_t)d;
 }
 

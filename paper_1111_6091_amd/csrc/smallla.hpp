@@ -46,10 +46,10 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 //     accumulator acc_ij = sum_{k<i} L_ik W_kj, kept in place of L_ij.
 // Values from one lane reach every lane through scalar reads (readlane), all
 // issued before the updates that use them.  Writes W (zeros above the
-// diagonal) to out, lane i < R writing row i, unless bad; returns bad
+// diagonal) to out (LDS), lane i < R writing row i, unless bad; returns bad
 // (wave-uniform).
 template <int RM>
-__device__ inline bool wave_chol_inverse(const double* G, int R, double* out) {
+__device__ __forceinline__ bool wave_chol_inverse(const double* G, int R, double* out) {
   const int lane = threadIdx.x & 63;
   double a[RM];
 #pragma unroll
@@ -100,17 +100,84 @@ __device__ inline bool wave_chol_inverse(const double* G, int R, double* out) {
   return bad;
 }
 
+// The same W = L^-1 with the rows kept in LDS (for kernels whose register
+// budget the form above would raise): C (LDS, R x R) takes L, out (LDS) gets W.
+// Lane i works on row i; runtime loops over columns, four at a time.  The
+// column-k entries another lane wrote in the same step are read after those
+// writes in program order (LDS operations of a wavefront complete in order).
+__device__ __forceinline__ bool wave_chol_inverse_lds(const double* G, int R, double* C, double* out) {
+  const int lane = threadIdx.x & 63;
+  const bool row = lane < R;
+  double dmax = 0.0;
+  for (int k = 0; k < R; ++k) dmax = fmax(dmax, G[k * R + k]);
+  const double thr = R * kEps * dmax;
+  bool bad = !(dmax > 0.0);
+  if (row)
+    for (int j = 0; j < R; ++j) C[lane * R + j] = G[lane * R + j];
+  double dinv = 1.0;
+  for (int k = 0; k < R; ++k) {
+    const double piv = C[k * R + k];
+    bad = bad || !(piv > thr);
+    const double rs = rsqrt_nr(piv);
+    if (lane == k) dinv = rs;
+    const bool act = row && lane >= k;
+    const double l = act ? C[lane * R + k] * rs : 0.0;
+    if (act) C[lane * R + k] = l;
+    for (int j0 = k + 1; j0 < R; j0 += 4) {
+      double lj[4], cj[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q < R ? j0 + q : R - 1;
+        lj[q] = C[j * R + k];
+        cj[q] = act ? C[lane * R + j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (act && j0 + q < R) C[lane * R + j0 + q] = fma(-l, lj[q], cj[q]);
+    }
+  }
+  // rows of W: acc_ij = sum_{k<i} L_ik W_kj in out, W_kj = -acc_kj / L_kk
+  if (row)
+    for (int j = 0; j < R; ++j) out[lane * R + j] = 0.0;
+  for (int k = 0; k < R; ++k) {
+    const double dk = wave_bcast(dinv, k);
+    const bool act = row && lane > k;
+    const double c = act ? C[lane * R + k] : 0.0;
+    for (int j0 = 0; j0 <= k; j0 += 4) {
+      double wk[4], aj[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q <= k ? j0 + q : k;
+        const double acc = out[k * R + j];
+        wk[q] = j == k ? dk : -acc * dk;
+        aj[q] = act ? out[lane * R + j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (act && j0 + q <= k) out[lane * R + j0 + q] = fma(c, wk[q], aj[q]);
+    }
+  }
+  if (row && !bad)
+    for (int j = 0; j < R; ++j) {
+      const double v = out[lane * R + j];
+      out[lane * R + j] = j < lane ? -v * dinv : (j == lane ? dinv : 0.0);
+    }
+  return bad;
+}
+
 // The factor inverse above for every thread of the workgroup (wave 0 works;
-// RMAX: the largest rank bucket instantiated, R <= RMAX).  Returns 1 in every
-// thread when G failed the factorization test (nothing written to out).
-template <int RMAX>
-__device__ inline int wg_chol_inverse(const double* G, int R, double* out) {
+// rows in registers up to RMAX entries, in LDS (C: work array) beyond RMAX or,
+// with LDSV, beyond 12); out is LDS, visible to the workgroup on return.  Returns 1 in every thread when G failed the
+// factorization test (nothing written to out).
+template <int RMAX, bool LDSV = false>
+__device__ __forceinline__ int wg_chol_inverse(const double* G, int R, double* out, double* C) {
   __shared__ int s_bad;
   if (threadIdx.x < 64) {
     bool bad;
-    if (R <= 4) bad = wave_chol_inverse<4>(G, R, out);
+    if (R > RMAX || (LDSV && R > 12)) bad = wave_chol_inverse_lds(G, R, C, out);
+    else if (R <= 4) bad = wave_chol_inverse<4>(G, R, out);
     else if (R <= 8) bad = wave_chol_inverse<8>(G, R, out);
-    else if (R <= 12) bad = wave_chol_inverse<12>(G, R, out);
+    else if (R <= 12 || RMAX <= 12) bad = wave_chol_inverse<12>(G, R, out);
     else if (RMAX <= 16 || R <= 16) bad = wave_chol_inverse<16>(G, R, out);
     else if (R <= 24) bad = wave_chol_inverse<RMAX <= 16 ? 16 : 24>(G, R, out);
     else bad = wave_chol_inverse<RMAX <= 16 ? 16 : 32>(G, R, out);
@@ -123,7 +190,7 @@ __device__ inline int wg_chol_inverse(const double* G, int R, double* out) {
 // Pseudoinverse of the symmetric PSD matrix G (R x R) by cyclic Jacobi:
 // eigenvalues <= R*eps*lambda_max are dropped.  S, V, P: LDS scratch (R*R
 // each); the result is written to P.  Returns 1 if every eigenvalue was dropped.
-__device__ inline int wg_pinv(const double* G, int R, double* S, double* V, double* P) {
+__device__ __forceinline__ int wg_pinv(const double* G, int R, double* S, double* V, double* P) {
   const int lane = threadIdx.x;
   __shared__ double s_cs[2];
   __shared__ int s_done;

@@ -34,6 +34,7 @@ __device__ inline double wg_sum(double v, double* sred) {
 // column 16t + l%16 as both operands of a diagonal tile (16x16 output tiles
 // (ta, tb), ta <= tb, mirrored).  Wave w takes the row blocks w, w + 4, ...,
 // Q of them per round of loads; the four wave sums are added in wave order.
+// RMAX <= 16: the diagonal tile only (one accumulator).
 // gram_first_loads issues the first round of tile (0, 0) early (into pre), so
 // that it shares a round trip with other loads; gram_mfma consumes it.
 template <int Q>
@@ -47,13 +48,13 @@ __device__ inline void gram_first_loads(const double* __restrict__ A, int64_t I,
   }
 }
 
-template <int Q>
+template <int Q, int RMAX>
 __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R, double* U,
                                  const double (&pre)[Q]) {
   typedef double d4v __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int nt = (R + 15) / 16;
+  const int nt = RMAX <= 16 ? 1 : (R + 15) / 16;   // R <= RMAX
   const int64_t nblk = (I + 3) / 4;
   for (int ta = 0; ta < nt; ++ta)
     for (int tb = ta; tb < nt; ++tb) {
@@ -65,7 +66,7 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
         for (int q = 0; q < Q; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pre[q], pre[q], acc, 0, 0, 0);
         b0 += 4 * Q;
       }
-      if (ta == tb) {
+      if (RMAX <= 16 || ta == tb) {
         for (; b0 < nblk; b0 += 4 * Q) {
           double va[Q];
 #pragma unroll
@@ -111,13 +112,16 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
 
 // Gamma (in G, LDS, left unchanged) for the ALS update: the inverse W = L^-1
 // of its Cholesky factor (kind 0, Gamma^-1 = W^T W) or, when it fails the
-// factorization test, its pseudoinverse (kind 1) is written to out[0..R*R).  S, V, P: LDS scratch of R*R each.  RMAX: the largest rank
-// bucket the calling kernel instantiates (R <= RMAX).
-template <int RMAX>
-__device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind, uint32_t* flags,
+// factorization test, its pseudoinverse (kind 1) is written to out[0..R*R)
+// (global), with no barrier after these stores.  S, V, P: LDS scratch of R*R
+// each.  RMAX: the largest rank bucket the calling kernel instantiates; LDSV:
+// factor with the rows in LDS instead of registers.
+template <int RMAX, bool LDSV>
+__device__ __forceinline__ void gamma_factor(double* G, int R, double* out, int32_t* kind, uint32_t* flags,
                                     double* S, double* V, double* P) {
-  const int fail = wg_chol_inverse<RMAX>(G, R, out);
+  const int fail = wg_chol_inverse<RMAX, LDSV>(G, R, S, P);
   if (!fail) {
+    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = S[idx];
     if (threadIdx.x == 0) *kind = 0;
   } else {
     const int zero = wg_pinv(G, R, S, V, P);
@@ -127,7 +131,6 @@ __device__ inline void gamma_factor(double* G, int R, double* out, int32_t* kind
       atomicOr(flags, zero ? (CP_FLAG_PINV_FALLBACK | CP_FLAG_NOT_SPD) : CP_FLAG_PINV_FALLBACK);
     }
   }
-  __syncthreads();
 }
 
 
@@ -183,6 +186,15 @@ __device__ inline void batch_rules(BatchState* st, const BatchRule& ru, const do
   st->active = any ? 1 : 0;
 }
 
+// End of a sweep, by one thread: the objective values into the history and the
+// stopping rules of a batched solve.
+__device__ __forceinline__ void close_sweep(const PrepArgs& a, BatchState* st, const double* sfv,
+                                            const double* sfit, int NG, bool want_f) {
+  if (a.f_slot && want_f)
+    for (int g = 0; g < NG; ++g) a.f_slot[g] = sfv[g];
+  if (st) batch_rules(st, *a.rule, sfit, NG);
+}
+
 // The bookkeeping step; smem: a.lds doubles of LDS.  LK: global loads in
 // flight per thread (8 where it shares a kernel with the streaming path, whose
 // register budget it must not raise; 16 in the standalone kernels).  With finalize set,
@@ -194,6 +206,7 @@ template <int LK = 8, int RMAX = 32>
 __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
   __shared__ double sred[8];
   __shared__ double sfit[kMaxGroups];
+  __shared__ double sfv[kMaxGroups];
   const int R = a.R, N = a.N, n = a.n, RR = R * R, tid = threadIdx.x;
   const int NG = a.groups > 1 ? a.groups : 1;
   const int Rg = R / NG;
@@ -219,8 +232,9 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   if (a.p >= 0) gram_first_loads<GQ>(a.Ap, a.Ip, R, gpre);
   const bool want_f = a.boundary && active && (a.f_slot || st);
   const double ip0 = (want_f && tid < a.inner_count) ? a.inner_part[(size_t)tid * NG] : 0.0;
+  const double nz2 = want_f ? *a.norm2 : 0.0;
   prep_load<LK>(a, sS, sGr);
-  if (a.p >= 0) gram_mfma<GQ>(a.Ap, a.Ip, R, U, gpre);
+  if (a.p >= 0) gram_mfma<GQ, RMAX>(a.Ap, a.Ip, R, U, gpre);
   // the updated factor is normalized (frozen groups kept their columns)
   if (a.p >= 0 && tid < R && !col_frozen(tid)) sS[a.p * R + tid] = 1.0;
   __syncthreads();
@@ -255,9 +269,9 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
         const double inner = wg_sum(ip, sred);
         const double nrm = wg_sum(h, sred);
         if (tid == 0) {
-          const double f = 0.5 * (*a.norm2 - 2.0 * inner + nrm);
-          if (a.f_slot) a.f_slot[g] = f;
-          sfit[g] = 1.0 - sqrt(fmax(2.0 * f, 0.0) / *a.norm2);
+          const double f = 0.5 * (nz2 - 2.0 * inner + nrm);
+          sfv[g] = f;
+          sfit[g] = 1.0 - sqrt(fmax(2.0 * f, 0.0) / nz2);
         }
       }
     }
@@ -280,10 +294,11 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
           for (int m = 0; m < N; ++m) sS[m * R + r] *= lam / nr[m];
       }
     }
-    __syncthreads();
-    if (st && tid == 0) batch_rules(st, *a.rule, sfit, NG);
   }
   __syncthreads();
+  // global stores of the step come last: a barrier after them would wait for
+  // their completion
+  const bool closed = a.boundary && active && tid == 0;   // a sweep ended here
   if (finalize) {
     // apply the scales to the stored factors (and shadows), LK loads in flight
     for (int m = 0; m < N; ++m) {
@@ -320,11 +335,9 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
       }
     }
     for (int idx = tid; idx < N * R; idx += kThreads) a.sigma[idx] = 1.0;
+    if (closed) close_sweep(a, st, sfv, sfit, NG, want_f);
     return;
   }
-  if (a.p >= 0)
-    for (int idx = tid; idx < RR; idx += kThreads) a.grams[(size_t)a.p * RR + idx] = U[idx];
-  for (int idx = tid; idx < N * R; idx += kThreads) a.sigma[idx] = sS[idx];
   // Gamma^(n) in normalized coordinates, column scale of M^(n), sigma^(n)
   for (int idx = tid; idx < RR; idx += kThreads) {
     const int r = idx / R, c = idx % R;
@@ -336,6 +349,15 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
     }
     G[idx] = g;
   }
+  __syncthreads();
+  if (a.solver == CP_SOLVE_GS) {
+    for (int idx = tid; idx < RR; idx += kThreads) a.out[idx] = G[idx];
+    if (tid == 0) *a.kind = 2;
+  } else {
+    // rows in registers; inside a streaming kernel, whose register count
+    // (occupancy) longer rows would raise, only up to 12 entries
+    gamma_factor<(LK == 8 ? 12 : RMAX), (LK == 8)>(G, R, a.out, a.kind, a.flags, S, V, P);
+  }
   if (tid < R) {
     double c = 1.0;
     for (int m = 0; m < N; ++m)
@@ -343,14 +365,10 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
     a.out[RR + tid] = c;
     a.out[RR + R + tid] = sS[n * R + tid];
   }
-  __syncthreads();
-  if (a.solver == CP_SOLVE_GS) {
-    for (int idx = tid; idx < RR; idx += kThreads) a.out[idx] = G[idx];
-    if (tid == 0) *a.kind = 2;
-    __syncthreads();
-    return;
-  }
-  gamma_factor<RMAX>(G, R, a.out, a.kind, a.flags, S, V, P);
+  if (a.p >= 0)
+    for (int idx = tid; idx < RR; idx += kThreads) a.grams[(size_t)a.p * RR + idx] = U[idx];
+  for (int idx = tid; idx < N * R; idx += kThreads) a.sigma[idx] = sS[idx];
+  if (closed) close_sweep(a, st, sfv, sfit, NG, want_f);
 }
 
 }  // namespace cpamg

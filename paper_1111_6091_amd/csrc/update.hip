@@ -223,31 +223,33 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
   // columns solves every group; frozen groups (batched solve) keep their rows.
   const int NG = d.groups > 1 ? d.groups : 1;
   const int Rg = R / NG;
-  double ip = 0.0;
+  double ip = 0.0, x = 0.0;
+  bool wr = false;
+  const int64_t row = row0 + wave;
   if (wave < nrows) {
-    const int64_t row = row0 + wave;
     const double m = (lane < R) ? sC[lane] * sM[wave * LDP + lane] : 0.0;
     const double b = (lane < R) ? m + (d.F ? d.F[row * R + lane] : 0.0) : 0.0;
-    double x;
     if (kind != 2) {
       x = wave_apply_any(b, sG, R, kind, lane);
     } else {
       const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
       x = wave_gs(b, x0, sG, R, d.gs_iters, lane);
     }
-    if (lane < R && !(d.st && d.st->frozen[lane / Rg])) {
-      if (!isfinite(x)) atomicOr(d.flags, CP_FLAG_NONFINITE);
-      d.A[row * R + lane] = x;
-      if (d.A32) d.A32[row * R + lane] = (float)x;
-      ip = x * m;
-    }
+    wr = lane < R && !(d.st && d.st->frozen[lane / Rg]);
+    if (wr) ip = x * m;
   }
-  if (d.want_obj) {
-    for (int g = 0; g < NG; ++g) {
-      const double ipb = block_sum((lane < R && lane / Rg == g) ? ip : 0.0, sred);
-      if (tid == 0) d.scal_part[(size_t)blk * NG + g] = ipb;
-    }
+  // the block sums (barriers) before the global stores, which a barrier would
+  // wait for
+  double ipb[kMaxGroups];
+  if (d.want_obj)
+    for (int g = 0; g < NG; ++g) ipb[g] = block_sum((lane < R && lane / Rg == g) ? ip : 0.0, sred);
+  if (wr) {
+    if (!isfinite(x)) atomicOr(d.flags, CP_FLAG_NONFINITE);
+    d.A[row * R + lane] = x;
+    if (d.A32) d.A32[row * R + lane] = (float)x;
   }
+  if (d.want_obj && tid == 0)
+    for (int g = 0; g < NG; ++g) d.scal_part[(size_t)blk * NG + g] = ipb[g];
 }
 
 __global__ __launch_bounds__(kThreads) void epi_kernel(EpiDesc d) {
