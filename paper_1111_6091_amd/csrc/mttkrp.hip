@@ -163,11 +163,12 @@ __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, 
 // Workgroup 0 of a launch with prep set does the sweep bookkeeping for the
 // update that follows (sweep.hpp), concurrently with the streaming workgroups;
 // it is dispatched first, so it is resident from the start.
-// NT: 16-column tiles of the kernel (R <= 16 NT).
-template <int NT>
+// NT: 16-column tiles of the kernel (R <= 16 NT); BATCH: batched launch
+// (column groups).
+template <int NT, bool BATCH>
 __device__ __forceinline__ bool prep_block(const MttkrpDesc& d, int blk, double* smem) {
   if (!d.prep || blk != 0) return false;
-  sweep_prep<8, 16 * NT>(d.pa, smem, false);
+  sweep_prep<8, 16 * NT, BATCH>(d.pa, smem, false);
   return true;
 }
 
@@ -180,13 +181,13 @@ constexpr int kind23_smem(int TW, int NT, bool k3) { return k3 ? 4 * 16 * NT : 4
 // sub-tile a holds rows i0 = grp*16*VW + VW*m + a (m = GEMM row).  Contraction
 // over i1 on the matrix cores, Hadamard weight per stripe in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int VW, bool VEC, bool BL>
+template <typename T, int NT, int VW, bool VEC, bool BL, bool BATCH = false>
 __device__ __forceinline__ void kind1_body(const MttkrpDesc& d, int blk, double* smem) {
   typedef typename Vec4<T>::type V;
   constexpr int PANEL = 16 * VW;
   // 16 lanes x 16 bytes cover two whole lines only for 4-wide FP32 loads
   constexpr bool NTH = sizeof(T) == 4 && VW == 4;
-  if (prep_block<NT>(d, blk, smem)) return;
+  if (prep_block<NT, BATCH>(d, blk, smem)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
@@ -326,12 +327,12 @@ __device__ __forceinline__ void kind1_body(const MttkrpDesc& d, int blk, double*
 // consecutive i0 per lane.  kind 2 (n == 1): rows are the outputs; kind 3
 // (n >= 2): rows are reduced with A^(1)(i1, r) into output s_n.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL, bool YS = false>
+template <typename T, int NT, int TW, bool KIND3, int VW, bool VEC, bool BL, bool YS = false, bool BATCH = false>
 __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double* smem) {
   typedef typename Vec4<T>::type V;
   constexpr int KC = 4 * VW;   // contraction chunk per step of the loop
   constexpr int ROWS = 16 * TW;
-  if (prep_block<NT>(d, blk, smem)) return;
+  if (prep_block<NT, BATCH>(d, blk, smem)) return;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, g4 = lane >> 4;
@@ -571,11 +572,11 @@ void mttkrp_batched(const MttkrpDesc* __restrict__ descs, const int2* __restrict
   const MttkrpDesc& d = descs[t.x];
   if (d.pa.st && !d.pa.st->active) return;
   if (KIND == 1) {
-    if (d.vec) kind1_body<T, NT, 4, true, true>(d, t.y, smem);
-    else kind1_body<T, NT, 4, false, true>(d, t.y, smem);
+    if (d.vec) kind1_body<T, NT, 4, true, true, true>(d, t.y, smem);
+    else kind1_body<T, NT, 4, false, true, true>(d, t.y, smem);
   } else {
-    if (d.vec) kind23_body<T, NT, 2, KIND == 3, 4, true, true>(d, t.y, smem);
-    else kind23_body<T, NT, 2, KIND == 3, 4, false, true>(d, t.y, smem);
+    if (d.vec) kind23_body<T, NT, 2, KIND == 3, 4, true, true, false, true>(d, t.y, smem);
+    else kind23_body<T, NT, 2, KIND == 3, 4, false, true, false, true>(d, t.y, smem);
   }
 }
 

@@ -37,7 +37,7 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // W = L^-1 for the Cholesky factor L of the symmetric positive definite R x R
 // matrix G (LDS, row-major), so that G^-1 = W^T W.  Wave 0, lane i holds row i
 // in registers; rows and columns R..RM-1 are padded with the identity, so every
-// step is straight-line code.
+// step is straight-line code.  Element (i, j) of G and of out is at i ld + j.
 //  1. Cholesky, right-looking: step k takes the pivot a_kk, forms column k of L
 //     (a_ik / sqrt(a_kk)) and subtracts L_ik L_jk from the trailing entries.
 //     Bad when max diag(G) <= 0 or a pivot is <= R eps max diag(G).
@@ -49,11 +49,11 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // diagonal) to out (LDS), lane i < R writing row i, unless bad; returns bad
 // (wave-uniform).
 template <int RM>
-__device__ __forceinline__ bool wave_chol_inverse(const double* G, int R, double* out) {
+__device__ __forceinline__ bool wave_chol_inverse(const double* G, int R, int ld, double* out) {
   const int lane = threadIdx.x & 63;
   double a[RM];
 #pragma unroll
-  for (int k = 0; k < RM; ++k) a[k] = (lane < R && k < R) ? G[lane * R + k] : (lane == k ? 1.0 : 0.0);
+  for (int k = 0; k < RM; ++k) a[k] = (lane < R && k < R) ? G[lane * ld + k] : (lane == k ? 1.0 : 0.0);
   double dmax = 0.0;
 #pragma unroll
   for (int k = 0; k < RM; ++k)
@@ -95,7 +95,7 @@ __device__ __forceinline__ bool wave_chol_inverse(const double* G, int R, double
   if (!bad && lane < R) {
 #pragma unroll
     for (int j = 0; j < RM; ++j)
-      if (j < R) out[lane * R + j] = j < lane ? -a[j] * dinv : (j == lane ? dinv : 0.0);
+      if (j < R) out[lane * ld + j] = j < lane ? -a[j] * dinv : (j == lane ? dinv : 0.0);
   }
   return bad;
 }
@@ -105,83 +105,109 @@ __device__ __forceinline__ bool wave_chol_inverse(const double* G, int R, double
 // Lane i works on row i; runtime loops over columns, four at a time.  The
 // column-k entries another lane wrote in the same step are read after those
 // writes in program order (LDS operations of a wavefront complete in order).
-__device__ __forceinline__ bool wave_chol_inverse_lds(const double* G, int R, double* C, double* out) {
+__device__ __forceinline__ bool wave_chol_inverse_lds(const double* G, int R, int ld, double* C, double* out) {
   const int lane = threadIdx.x & 63;
   const bool row = lane < R;
   double dmax = 0.0;
-  for (int k = 0; k < R; ++k) dmax = fmax(dmax, G[k * R + k]);
+  for (int k = 0; k < R; ++k) dmax = fmax(dmax, G[k * ld + k]);
   const double thr = R * kEps * dmax;
   bool bad = !(dmax > 0.0);
   if (row)
-    for (int j = 0; j < R; ++j) C[lane * R + j] = G[lane * R + j];
+    for (int j = 0; j < R; ++j) C[lane * ld + j] = G[lane * ld + j];
   double dinv = 1.0;
   for (int k = 0; k < R; ++k) {
-    const double piv = C[k * R + k];
+    const double piv = C[k * ld + k];
     bad = bad || !(piv > thr);
     const double rs = rsqrt_nr(piv);
     if (lane == k) dinv = rs;
     const bool act = row && lane >= k;
-    const double l = act ? C[lane * R + k] * rs : 0.0;
-    if (act) C[lane * R + k] = l;
+    const double l = act ? C[lane * ld + k] * rs : 0.0;
+    if (act) C[lane * ld + k] = l;
     for (int j0 = k + 1; j0 < R; j0 += 4) {
       double lj[4], cj[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + q < R ? j0 + q : R - 1;
-        lj[q] = C[j * R + k];
-        cj[q] = act ? C[lane * R + j] : 0.0;
+        lj[q] = C[j * ld + k];
+        cj[q] = act ? C[lane * ld + j] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (act && j0 + q < R) C[lane * R + j0 + q] = fma(-l, lj[q], cj[q]);
+        if (act && j0 + q < R) C[lane * ld + j0 + q] = fma(-l, lj[q], cj[q]);
     }
   }
   // rows of W: acc_ij = sum_{k<i} L_ik W_kj in out, W_kj = -acc_kj / L_kk
   if (row)
-    for (int j = 0; j < R; ++j) out[lane * R + j] = 0.0;
+    for (int j = 0; j < R; ++j) out[lane * ld + j] = 0.0;
   for (int k = 0; k < R; ++k) {
     const double dk = wave_bcast(dinv, k);
     const bool act = row && lane > k;
-    const double c = act ? C[lane * R + k] : 0.0;
+    const double c = act ? C[lane * ld + k] : 0.0;
     for (int j0 = 0; j0 <= k; j0 += 4) {
       double wk[4], aj[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + q <= k ? j0 + q : k;
-        const double acc = out[k * R + j];
+        const double acc = out[k * ld + j];
         wk[q] = j == k ? dk : -acc * dk;
-        aj[q] = act ? out[lane * R + j] : 0.0;
+        aj[q] = act ? out[lane * ld + j] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (act && j0 + q <= k) out[lane * R + j0 + q] = fma(c, wk[q], aj[q]);
+        if (act && j0 + q <= k) out[lane * ld + j0 + q] = fma(c, wk[q], aj[q]);
     }
   }
   if (row && !bad)
     for (int j = 0; j < R; ++j) {
-      const double v = out[lane * R + j];
-      out[lane * R + j] = j < lane ? -v * dinv : (j == lane ? dinv : 0.0);
+      const double v = out[lane * ld + j];
+      out[lane * ld + j] = j < lane ? -v * dinv : (j == lane ? dinv : 0.0);
     }
   return bad;
 }
 
-// The factor inverse above for every thread of the workgroup (wave 0 works;
-// rows in registers up to RMAX entries, in LDS (C: work array) beyond RMAX or,
-// with LDSV, beyond 12); out is LDS, visible to the workgroup on return.  Returns 1 in every thread when G failed the
-// factorization test (nothing written to out).
-template <int RMAX, bool LDSV = false>
-__device__ __forceinline__ int wg_chol_inverse(const double* G, int R, double* out, double* C) {
+// The factor inverse above for every thread of the workgroup (wave 0 works),
+// block by block when G is block-diagonal with `groups` equal blocks (GROUPED
+// kernels only; each
+// block factored and tested on its own; zeros between the blocks of out).
+// Blocks are factored with the rows in registers up to RMAX entries, in LDS (C:
+// work array) beyond RMAX or, with LDSV, beyond 12.  out is LDS, visible to the
+// workgroup on return.  Returns 1 in every thread when a block failed the
+// factorization test (out incomplete).
+template <int RMAX, bool LDSV>
+__device__ __forceinline__ bool chol_inverse_block(const double* G, int n, int ld, double* C, double* out) {
+  if (n > RMAX || (LDSV && n > 12)) return wave_chol_inverse_lds(G, n, ld, C, out);
+  if (n <= 4) return wave_chol_inverse<4>(G, n, ld, out);
+  if (n <= 8) return wave_chol_inverse<8>(G, n, ld, out);
+  if (n <= 12 || RMAX <= 12) return wave_chol_inverse<12>(G, n, ld, out);
+  if (RMAX <= 16 || n <= 16) return wave_chol_inverse<16>(G, n, ld, out);
+  if (n <= 24) return wave_chol_inverse<RMAX <= 16 ? 16 : 24>(G, n, ld, out);
+  return wave_chol_inverse<RMAX <= 16 ? 16 : 32>(G, n, ld, out);
+}
+
+template <int RMAX, bool LDSV = false, bool GROUPED = false>
+__device__ __forceinline__ int wg_chol_inverse(const double* G, int R, int groups, double* out, double* C) {
   __shared__ int s_bad;
   if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     bool bad;
-    if (R > RMAX || (LDSV && R > 12)) bad = wave_chol_inverse_lds(G, R, C, out);
-    else if (R <= 4) bad = wave_chol_inverse<4>(G, R, out);
-    else if (R <= 8) bad = wave_chol_inverse<8>(G, R, out);
-    else if (R <= 12 || RMAX <= 12) bad = wave_chol_inverse<12>(G, R, out);
-    else if (RMAX <= 16 || R <= 16) bad = wave_chol_inverse<16>(G, R, out);
-    else if (R <= 24) bad = wave_chol_inverse<RMAX <= 16 ? 16 : 24>(G, R, out);
-    else bad = wave_chol_inverse<RMAX <= 16 ? 16 : 32>(G, R, out);
-    if (threadIdx.x == 0) s_bad = bad ? 1 : 0;
+    if (!GROUPED || groups <= 1) {
+      bad = chol_inverse_block<RMAX, LDSV>(G, R, R, C, out);
+    } else {
+      // blocks of at most 8 columns in registers (the batched restarts)
+      const int n = R / groups;
+      if (lane < R)
+        for (int j = 0; j < R; ++j)
+          if (j / n != lane / n) out[lane * R + j] = 0.0;
+      bad = false;
+      for (int g = 0; g < groups; ++g) {
+        const int o = g * n * (R + 1);
+        const bool b = n <= 8 ? (n <= 4 ? wave_chol_inverse<4>(G + o, n, R, out + o)
+                                        : wave_chol_inverse<8>(G + o, n, R, out + o))
+                              : wave_chol_inverse_lds(G + o, n, R, C + o, out + o);
+        bad = bad || b;
+      }
+    }
+    if (lane == 0) s_bad = bad ? 1 : 0;
   }
   __syncthreads();
   return s_bad;

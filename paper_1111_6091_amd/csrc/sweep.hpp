@@ -110,16 +110,17 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
     }
 }
 
-// Gamma (in G, LDS, left unchanged) for the ALS update: the inverse W = L^-1
-// of its Cholesky factor (kind 0, Gamma^-1 = W^T W) or, when it fails the
+// Gamma (in G, LDS, left unchanged; block-diagonal over `groups` column groups)
+// for the ALS update: the inverse W = L^-1 of its Cholesky factor (kind 0,
+// Gamma^-1 = W^T W, factored block by block) or, when a block fails the
 // factorization test, its pseudoinverse (kind 1) is written to out[0..R*R)
 // (global), with no barrier after these stores.  S, V, P: LDS scratch of R*R
 // each.  RMAX: the largest rank bucket the calling kernel instantiates; LDSV:
 // factor with the rows in LDS instead of registers.
-template <int RMAX, bool LDSV>
-__device__ __forceinline__ void gamma_factor(double* G, int R, double* out, int32_t* kind, uint32_t* flags,
-                                    double* S, double* V, double* P) {
-  const int fail = wg_chol_inverse<RMAX, LDSV>(G, R, S, P);
+template <int RMAX, bool LDSV, bool GROUPED>
+__device__ __forceinline__ void gamma_factor(double* G, int R, int groups, double* out, int32_t* kind,
+                                             uint32_t* flags, double* S, double* V, double* P) {
+  const int fail = wg_chol_inverse<RMAX, LDSV, GROUPED>(G, R, groups, S, P);
   if (!fail) {
     for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = S[idx];
     if (threadIdx.x == 0) *kind = 0;
@@ -201,8 +202,9 @@ __device__ __forceinline__ void close_sweep(const PrepArgs& a, BatchState* st, c
 // the pending scales are applied to the stored factors and reset instead of
 // preparing an update.  With a.groups > 1 the R columns form independent
 // groups: Gamma is block-diagonal, f is evaluated per group, and in a batched
-// solve (a.st) frozen groups are neither renormalized nor updated.
-template <int LK = 8, int RMAX = 32>
+// solve (a.st) frozen groups are neither renormalized nor updated; GROUPED
+// (the batched kernels) factors such a Gamma block by block.
+template <int LK = 8, int RMAX = 32, bool GROUPED = false>
 __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize) {
   __shared__ double sred[8];
   __shared__ double sfit[kMaxGroups];
@@ -356,7 +358,7 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   } else {
     // rows in registers; inside a streaming kernel, whose register count
     // (occupancy) longer rows would raise, only up to 12 entries
-    gamma_factor<(LK == 8 ? 12 : RMAX), (LK == 8)>(G, R, a.out, a.kind, a.flags, S, V, P);
+    gamma_factor<(LK == 8 ? 12 : RMAX), (LK == 8), GROUPED>(G, R, NG, a.out, a.kind, a.flags, S, V, P);
   }
   if (tid < R) {
     double c = 1.0;
