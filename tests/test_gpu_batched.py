@@ -28,13 +28,15 @@ def _restart(A, k, R):
     return [a[:, k * R:(k + 1) * R] for a in A]
 
 
-@pytest.mark.parametrize("count,restarts,rmax", [(6, 3, 4), (5, 4, 8)])
-def test_batched_fixed_sweeps_match_oracle(count, restarts, rmax):
+@pytest.mark.parametrize("count,restarts,rmin,rmax", [(6, 3, 2, 4), (5, 4, 2, 8), (3, 2, 9, 14)])
+def test_batched_fixed_sweeps_match_oracle(count, restarts, rmin, rmax):
     """FP64 phase only, no stopping before the cap: K sweeps of every restart
-    equal K oracle ALS sweeps (normalized after each sweep)."""
+    equal K oracle ALS sweeps (normalized after each sweep).  The last case has
+    restart blocks of 9 to 14 columns (32-column kernels, blocks factored with
+    the rows in LDS)."""
     from paper_1111_6091_amd import api
     from paper_1111_6091_amd._lib import CP_FP64
-    probs = synth.batched_problems(count=count, seed=11, restarts=restarts, lo=5, hi=21, rmin=2,
+    probs = synth.batched_problems(count=count, seed=11, restarts=restarts, lo=max(5, rmax), hi=21, rmin=rmin,
                                    rmax=rmax, cmin=0.3, cmax=0.8)
     say(f"batched fixed sweeps: {[(p['dims'], p['R']) for p in probs]} restarts={restarts}")
     C = make_ctx()
