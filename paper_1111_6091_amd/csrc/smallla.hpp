@@ -178,6 +178,7 @@ __device__ __forceinline__ bool chol_inverse_block(const double* G, int n, int l
   if (n > RMAX || (LDSV && n > 12)) return wave_chol_inverse_lds(G, n, ld, C, out);
   if (n <= 4) return wave_chol_inverse<4>(G, n, ld, out);
   if (n <= 8) return wave_chol_inverse<8>(G, n, ld, out);
+  if (n <= 10) return wave_chol_inverse<10>(G, n, ld, out);
   if (n <= 12 || RMAX <= 12) return wave_chol_inverse<12>(G, n, ld, out);
   if (RMAX <= 16 || n <= 16) return wave_chol_inverse<16>(G, n, ld, out);
   if (n <= 24) return wave_chol_inverse<RMAX <= 16 ? 16 : 24>(G, n, ld, out);
