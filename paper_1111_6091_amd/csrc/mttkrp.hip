@@ -108,17 +108,19 @@ __device__ __forceinline__ void stage_b(const T* __restrict__ ak, int I, int R, 
     for (int c = 0; c < NC; ++c)
       if (c >= R || padrow) Bs[c * ldb + i] = T(0);
   }
-  // the factor is contiguous (I x R): coalesced loads, 8 in flight per thread
+  // the factor is contiguous (I x R): coalesced loads, 16 in flight per thread
+  // (one round trip up to 4096 entries)
+  constexpr int SQ = 16;
   const int total = I * R;
-  for (int base = 0; base < total; base += 8 * kThreads) {
-    T v[8];
+  for (int base = 0; base < total; base += SQ * kThreads) {
+    T v[SQ];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < SQ; ++j) {
       const int idx = base + j * kThreads + (int)threadIdx.x;
       v[j] = ak[idx < total ? idx : 0];
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < SQ; ++j) {
       const int idx = base + j * kThreads + (int)threadIdx.x;
       if (idx < total) {
         const int i = idx / R, c = idx - i * R;
