@@ -100,3 +100,32 @@ def test_host_side_argument_errors(C):
     with pytest.raises(api.CpError):
         api.cp_als_sweep(C, Zd, Ad, None, -1)          # negative sweep count
     assert C.status() == 0
+
+
+@pytest.mark.parametrize("R", [14, 20, 32])
+def test_als_sweeps_dimension_tree_wide_rank(C, R):
+    """Three FP64 sweeps at 128 x 12 x 12 with R = 14, 20, 32: the dimension
+    tree applies (Y is a quarter of Z), so mode 2 runs the Y-contracting kernel,
+    whose bookkeeping factors Gamma with 16-, 24- and 32-entry register rows."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_FP64, CP_SOLVE_CHOL
+    dims = (128, 12, 12)
+    say(f"dimension-tree sweeps dims={dims} R={R}")
+    Z, _ = synth.collinear_tensor(dims, 3, 0.5, 0.01, 0.0, seed=3)
+    A0 = synth.uniform_start(dims, R, 3)
+    Zd = api.DeviceTensor.from_numpy(C, Z)
+    Ad = api.DeviceFactors.from_numpy(C, A0)
+    K = 3
+    fh = torch.zeros(K, dtype=torch.float64, device="cuda")
+    api.cp_als_sweep(C, Zd, Ad, None, K, CP_SOLVE_CHOL, 10, True, CP_FP64, fh)
+    sync()
+    assert C.status() == 0
+    ref = [a.copy() for a in A0]
+    fref = []
+    for _ in range(K):
+        ref = cp.als_sweep(Z, ref)
+        fref.append(cp.objective(Z, ref))
+    got = Ad.to_numpy()
+    for n in range(3):
+        assert rel_err(got[n], ref[n]) < 1e-8, (n, rel_err(got[n], ref[n]))
+    np.testing.assert_allclose(fh.cpu().numpy(), fref, rtol=1e-9)
