@@ -157,8 +157,9 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
 /* `nsweeps` iterations of block nonlinear Gauss-Seidel (Section 3 ALS, or the
  * FAS relaxation of Section 5.2 when F != NULL) on A^(n) Gamma^(n) =
  * Z_(n) Phi^(n) + F^(n), n = 0..N-1, updating A (and its shadows) in place.
- * solver: CP_SOLVE_CHOL = A^(n) <- (M + F) Gamma^dagger (Cholesky, pseudoinverse
- * fallback); CP_SOLVE_GS = `gs_iters` Gauss-Seidel iterations warm-started from
+ * solver: CP_SOLVE_CHOL = A^(n) <- (M + F) Gamma^dagger (Cholesky factor L,
+ * applied through W = L^-1 as (M + F) W^T W; pseudoinverse fallback when a
+ * pivot fails the test); CP_SOLVE_GS = `gs_iters` Gauss-Seidel iterations warm-started from
  * the current A^(n).  normalize != 0 applies eq. (10) after every sweep.
  * F: NULL for plain ALS, else F->a[n] (I_n x R FP64).  f_hist (optional,
  * device, nsweeps doubles): f = 1/2||Z - [[A]]||^2 after each sweep from the
