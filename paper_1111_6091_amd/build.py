@@ -1,6 +1,6 @@
 """Build libcpamg.so (HIP for gfx950) in-tree.
 
-    python -m paper_1111_6091_amd.build        # or __graft_entry__.build()
+    python -m paper_1111_6091_amd.build [--incremental]   # or __graft_entry__.build()
 
 Every .hip file under csrc/ is compiled with hipcc for gfx950 into an object in
 csrc/../_build/, then linked into paper_1111_6091_amd/libcpamg.so.  Packed FP32
@@ -29,8 +29,16 @@ COMMON = [
 ]
 
 
-def _compile(src):
+def _headers():
+    return glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(PKG, "..", "include", "*.h"))
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(f) for f in [src, *_headers()])
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -38,12 +46,14 @@ def _compile(src):
     return obj
 
 
-def build(verbose=False):
+def build(verbose=False, incremental=False):
+    """Compile every source (incremental=True: only sources newer than their
+    object or than any header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,5 +66,5 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)
