@@ -154,6 +154,24 @@ cp_status cp_norm2(cp_ctx ctx, const cp_tensor* Z, double* out);
 cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
                     double* M, cp_prec prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cp_mttkrp
+ * without any allocation.  Same arguments, launch configuration, kernels and
+ * result as cp_mttkrp; the per-split partial sums go to a static device array
+ * of CP_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * has run on until the process ends (its address is looked up once per device
+ * by cp_ctx_create), never to the context's workspace.  The call allocates no
+ * device memory and calls no allocating routine.  Every call on one device
+ * shares that device's array and leaves its contents behind (each call
+ * overwrites what it reads, so nothing needs to start at zero): calls that
+ * overlap on one device (two streams, two contexts, two host threads) race
+ * and must be ordered by the caller.  Errors: as cp_mttkrp; CP_ERR_SHAPE when
+ * the partial sums of this mode's launch (splits x I_n x R doubles) exceed the
+ * array; CP_ERR_HIP when no context was ever created on the current device. */
+#define CP_NOALLOC_SCRATCH_BYTES (32u << 20)
+cp_status cp_mttkrp_noalloc(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
+                            double* M, cp_prec prec);
+
 /* `nsweeps` iterations of block nonlinear Gauss-Seidel (Section 3 ALS, or the
  * FAS relaxation of Section 5.2 when F != NULL) on A^(n) Gamma^(n) =
  * Z_(n) Phi^(n) + F^(n), n = 0..N-1, updating A (and its shadows) in place.

@@ -10,6 +10,7 @@ import os
 CP_MAX_ORDER = 8
 CP_MAX_RANK = 32
 CP_MAX_RESTARTS = 8
+CP_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 CP_OK = 0
 CP_ERR_INVALID = -1
@@ -79,6 +80,8 @@ SIGNATURES = {
     "cp_cast_f32": [c_vp, c_vp, c_vp, c_i64],
     "cp_norm2": [c_vp, ctypes.POINTER(CpTensor), c_vp],
     "cp_mttkrp": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_vp, c_i32],
+    "cp_mttkrp_noalloc": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_vp,
+                          c_i32],
     "cp_als_sweep": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors),
                      ctypes.POINTER(CpFactors), c_i32, c_i32, c_i32, c_i32, c_i32, c_vp],
     "cp_objective": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_vp,

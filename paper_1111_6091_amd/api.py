@@ -197,6 +197,12 @@ def cp_mttkrp(ctx, Z, A, n, M, prec=CP_FP64):
     ctx.check(ctx._lib.cp_mttkrp(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), n, _ptr(M), prec))
 
 
+def cp_mttkrp_noalloc(ctx, Z, A, n, M, prec=CP_FP64):
+    zs, fs = Z.struct(), A.struct()
+    ctx.check(ctx._lib.cp_mttkrp_noalloc(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), n, _ptr(M),
+                                         prec))
+
+
 def cp_als_sweep(ctx, Z, A, F=None, nsweeps=1, solver=CP_SOLVE_CHOL, gs_iters=10, normalize=True,
                  prec=CP_FP64, f_hist=None):
     zs, fs = Z.struct(), A.struct()

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -23,6 +24,35 @@ constexpr int kNumCounters = 16;
 enum CounterId { CNT_EPI = 0, CNT_RES = 1, CNT_DOT = 2, CNT_DOT2 = 3 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Scratch of the allocation-free entry point (cp_mttkrp_noalloc): the per-split
+// MTTKRP partial sums.  Each device holds its own copy of the array for the
+// life of the process.  In host code the array's name is not a device address:
+// host code uses only the address that hipGetSymbolAddress returned for the
+// device (g_scratch[device]), looked up once per device in cp_ctx_create.
+static __device__ __align__(256) double scratch[CP_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Address of this device's scratch array (the device is current); looked up on
+// the first call per device.
+hipError_t scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch[device] = ptr;
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -215,7 +245,7 @@ std::string plan_key(int N, const int64_t* dims, int n, int R, bool fp32) {
 // Launch configuration for the MTTKRP of mode n: the tuned options when the
 // autotuner (or an imported plan set) has seen this shape, otherwise as many
 // streaming workgroups as stay resident next to the bookkeeping workgroup.
-MttkrpPlan get_plan(cp_ctx ctx, int N, const int64_t* dims, int n, int R, bool fp32) {
+MttkrpPlan find_plan(cp_ctx ctx, int N, const int64_t* dims, int n, int R, bool fp32) {
   const std::string key = plan_key(N, dims, n, R, fp32);
   auto hit = ctx->plans.find(key);
   if (hit != ctx->plans.end()) return hit->second;
@@ -229,6 +259,15 @@ MttkrpPlan get_plan(cp_ctx ctx, int N, const int64_t* dims, int n, int R, bool f
     o.target_wgs = std::max(1, cap - 1);
     p = mttkrp_plan(N, dims, n, R, fp32, o);
   }
+  return p;
+}
+
+// find_plan, remembered in the context's plan cache
+MttkrpPlan get_plan(cp_ctx ctx, int N, const int64_t* dims, int n, int R, bool fp32) {
+  const std::string key = plan_key(N, dims, n, R, fp32);
+  auto hit = ctx->plans.find(key);
+  if (hit != ctx->plans.end()) return hit->second;
+  const MttkrpPlan p = find_plan(ctx, N, dims, n, R, fp32);
   ctx->plans[key] = p;
   return p;
 }
@@ -425,6 +464,11 @@ cp_status cp_ctx_create(cp_ctx* out, void* hip_stream) {
     delete ctx;
     return CP_ERR_HIP;
   }
+  e = scratch_lookup(ctx->device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return CP_ERR_HIP;
+  }
   const size_t fixed_bytes = align_up(kNumCounters * sizeof(int32_t)) + align_up(64) +
                              align_up((kMaxRank * kMaxRank + 2 * kMaxRank) * sizeof(double)) +
                              align_up(64) +
@@ -532,6 +576,50 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
     return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M);
   if ((s = ensure_ws(ctx, align_up(plan.partial_doubles * sizeof(double)))) != CP_OK) return s;
   double* part = (double*)ctx->ws;
+  if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan,
+                          part)) != CP_OK)
+    return s;
+  EpiDesc d{};
+  d.op = EPI_STORE_M;
+  d.R = R;
+  d.N = N;
+  d.n = n;
+  d.nsplit = plan.nsplit;
+  d.In = Z->dims[n];
+  d.partial = part;
+  d.outbuf = M;
+  TRY(enqueue_epi(ctx, d));
+  return CP_OK;
+}
+
+cp_status cp_mttkrp_noalloc(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
+                            double* M, cp_prec prec) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
+  if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp_noalloc: mode %d outside [0, %d)", n, N);
+  if (!M) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp_noalloc: M is NULL");
+  int device = -1;
+  HIPCHK(hipGetDevice(&device));
+  if (device < 0 || device >= kMaxDevices || !g_scratch[device])
+    return set_err(ctx, CP_ERR_HIP, "cp_mttkrp_noalloc: no scratch address for device %d "
+                   "(create a context on that device first)", device);
+  const int R = A->rank;
+  // the launch configuration cp_mttkrp uses, without adding it to the plan cache
+  const MttkrpPlan plan = find_plan(ctx, N, Z->dims, n, R, mixed);
+  const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  if (plan.nsplit == 1)
+    return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M);
+  const size_t need = plan.partial_doubles * sizeof(double);
+  if (need > (size_t)CP_NOALLOC_SCRATCH_BYTES)
+    return set_err(ctx, CP_ERR_SHAPE,
+                   "cp_mttkrp_noalloc: mode %d needs %zu bytes of partial sums, the static scratch "
+                   "holds %zu (use cp_mttkrp)", n, need, (size_t)CP_NOALLOC_SCRATCH_BYTES);
+  double* part = (double*)g_scratch[device];
   if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan,
                           part)) != CP_OK)
     return s;

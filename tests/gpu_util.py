@@ -36,3 +36,28 @@ def rel_err(a, b):
 def say(*args):
     print(*args, flush=True)
     sys.stdout.flush()
+
+
+def elem_err(a, b, floor=1e-3):
+    """max_i |a_i - b_i| / (|b_i| + floor * max|b|): element by element, with a
+    floor for entries far below the largest one."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if b.size == 0:
+        return 0.0
+    den = np.abs(b) + floor * np.max(np.abs(b))
+    den = np.where(den > 0, den, 1.0)
+    return float(np.max(np.abs(a - b) / den))
+
+
+def mttkrp_err(got, Z, A, n):
+    """Element-wise error of an MTTKRP result against the oracle, relative to the
+    scale a floating-point sum of its terms is accurate to: the MTTKRP of |Z|
+    with |A^(m)|, i.e. sum over the contraction of |z| prod |a|.  A summation of
+    K terms in precision u is within about K u of it per element (FP32 GEMM
+    chunks of K <= 256: about 1.5e-5; FP64: below 1e-12)."""
+    from oracle import cp
+    ref = cp.mttkrp(Z, A, n)
+    scale = cp.mttkrp(np.abs(Z), [np.abs(a) for a in A], n)
+    scale = np.where(scale > 0, scale, 1.0)
+    return float(np.max(np.abs(np.asarray(got, dtype=np.float64) - ref) / scale))
