@@ -32,7 +32,8 @@ if HERE not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(HERE, "profiles", "mttkrp_256cube_r10_pmc.md")
-KERNEL_SOURCES = ["mttkrp.hip", "sweep.hpp", "internal.hpp", "smallla.hpp"]
+KERNEL_SOURCES = ["mttkrp.hip", "mttkrp_kernels.hpp", "mttkrp_k_f32v4.hip", "mttkrp_k_f32v8.hip",
+                  "mttkrp_k_f64.hip", "sweep.hpp", "internal.hpp", "smallla.hpp"]
 
 
 def kernel_source_hash():
@@ -83,6 +84,11 @@ def parse():
     p.add_argument("--mttkrp-only", action="store_true",
                    help="launch each MTTKRP kernel --steps times and a 64 MiB device copy "
                         "(byte-counter calibration), then exit; for profiler runs")
+    p.add_argument("--sweeps-only", action="store_true",
+                   help="time the mixed and FP64 sweeps only, then exit; for profiler runs")
+    p.add_argument("--cold", action="store_true",
+                   help="with --mttkrp-only: write and read a 1 GiB buffer before every MTTKRP "
+                        "launch (evicts the L2 caches and the 256 MB Infinity Cache)")
     return p.parse_args()
 
 
@@ -113,6 +119,14 @@ def sweep_mttkrp_bytes(dims, R, n, elem_bytes):
         return mttkrp_bytes(dims, R, n, elem_bytes) + yd * 8
     other = sum(d for m, d in enumerate(dims) if m >= 1 and m != n)
     return yd * 8 + other * R * 8 + dims[n] * R * 8
+
+
+def sweep_mttkrp_overhead_bytes(dims, R, n, elem_bytes):
+    """Bytes the sweep's mode-n launch moves beyond the algorithmic bytes of an
+    MTTKRP: the mode-1 launch's Y store (the dimension tree's trade: written
+    once, read by the modes >= 2 instead of another pass over Z)."""
+    yd = tree_y_doubles(dims, R, elem_bytes)
+    return yd * 8 if (yd and n == 1) else 0
 
 
 def sweep_kernel_name(dims, R, n, tag):
@@ -176,11 +190,19 @@ def main():
         # the sweep's launches (dimension tree), then one pass over Z per mode
         from paper_1111_6091_amd._lib import CP_OPT_DIMTREE
         A = fresh()
+        flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if args.cold else None
+        flush_sum = torch.empty(1, dtype=torch.float32, device="cuda")
         for tree in (1, 0):
             ctx.set_option(CP_OPT_DIMTREE, tree)
             for prec in (CP_MIXED, CP_FP64):
                 for n in range(len(dims)):
-                    api.cp_time_mttkrp(ctx, Zd, A, n, prec, K)
+                    if flush is None:
+                        api.cp_time_mttkrp(ctx, Zd, A, n, prec, K)
+                        continue
+                    for _ in range(K):
+                        flush.fill_(1.0)
+                        torch.sum(flush, dim=0, keepdim=True, out=flush_sum)
+                        api.cp_time_mttkrp(ctx, Zd, A, n, prec, 1)
         ctx.set_option(CP_OPT_DIMTREE, 1)
         src = torch.empty(64 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -210,6 +232,8 @@ def main():
     log(f"mixed sweep: {ms_mixed * 1e3:.1f} us ({1e3 / ms_mixed:.0f} sweeps/s)")
     ms_fp64, wall_fp64 = timed(CP_FP64, K, W)
     log(f"fp64 sweep: {ms_fp64 * 1e3:.1f} us ({1e3 / ms_fp64:.0f} sweeps/s)")
+    if args.sweeps_only:
+        return
     # the same sweeps with one pass over Z per mode (no dimension tree)
     from paper_1111_6091_amd._lib import CP_OPT_DIMTREE
     ctx.set_option(CP_OPT_DIMTREE, 0)
@@ -227,11 +251,43 @@ def main():
     for prec, tag, eb in ((CP_MIXED, "f32", 4), (CP_FP64, "f64", 8)):
         for n in range(len(dims)):
             ms = api.cp_time_mttkrp(ctx, Zd, A, n, prec, reps)
-            b = sweep_mttkrp_bytes(dims, R, n, eb)
+            ov = sweep_mttkrp_overhead_bytes(dims, R, n, eb)
+            b = sweep_mttkrp_bytes(dims, R, n, eb) - ov
             roof[f"{tag}_mode{n}"] = dict(kernel=sweep_kernel_name(dims, R, n, tag),
-                                          avg_us=ms * 1e3, bytes_per_launch=b,
+                                          avg_us=ms * 1e3, bytes_per_launch=b, overhead_bytes=ov,
                                           achieved_gbs=b / (ms * 1e-3) / 1e9)
-            log(f"{tag} mode {n}: {ms * 1e3:.2f} us/launch, {b / (ms * 1e-3) / 1e9:.0f} GB/s")
+            log(f"{tag} mode {n}: {ms * 1e3:.2f} us/launch, {b / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic"
+                f" (+{ov / 1e6:.2f} MB overhead)")
+    # cold launches: a 1 GiB buffer is written and then read before each launch,
+    # so neither the L2 caches nor the 256 MB Infinity Cache hold the tensor
+    # (the read leaves them clean: no write-back of the flush inside the timed
+    # launch); single launches between their own events, median of 20, warm
+    # single launches (the same method without the flush) beside them
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    flush_sum = torch.empty(1, dtype=torch.float32, device="cuda")
+
+    def evict():
+        flush.fill_(1.0)
+        torch.sum(flush, dim=0, keepdim=True, out=flush_sum)
+
+    cold = {}
+    for prec, tag, eb in ((CP_MIXED, "f32", 4), (CP_FP64, "f64", 8)):
+        for n in range(2):
+            c_ms, w_ms = [], []
+            for _ in range(20):
+                evict()
+                c_ms.append(api.cp_time_mttkrp(ctx, Zd, A, n, prec, 1))
+                w_ms.append(api.cp_time_mttkrp(ctx, Zd, A, n, prec, 1))
+            b = sweep_mttkrp_bytes(dims, R, n, eb) - sweep_mttkrp_overhead_bytes(dims, R, n, eb)
+            cm, wm = float(np.median(c_ms)), float(np.median(w_ms))
+            cold[f"{tag}_mode{n}"] = {"cold_us": round(cm * 1e3, 2), "warm_single_us": round(wm * 1e3, 2),
+                                      "cold_gbs": round(b / (cm * 1e-3) / 1e9, 1),
+                                      "cold_p10_p90_us": [round(float(np.percentile(c_ms, q)) * 1e3, 2)
+                                                          for q in (10, 90)]}
+            log(f"{tag} mode {n} cold: {cm * 1e3:.2f} us ({b / (cm * 1e-3) / 1e9:.0f} GB/s), "
+                f"warm single launch {wm * 1e3:.2f} us")
+    del flush
+    torch.cuda.empty_cache()
 
     # per-kernel breakdown of one sweep (event pair around every launch)
     breakdown = {}
@@ -249,8 +305,18 @@ def main():
         "bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom["achieved_gbs"], 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(dom["kernel"]), "bytes_per_launch": dom["bytes_per_launch"],
-        "avg_launch_us": round(dom["avg_us"], 2),
+        "overhead_bytes": dom["overhead_bytes"], "avg_launch_us": round(dom["avg_us"], 2),
+        "bytes_note": "algorithmic bytes: the tensor once, the other factors, the output "
+                      "(P*4 + sum_{m != n} I_m R 4 + I_n R 8); overhead_bytes: the Y store",
     }
+    # the whole sweep against the dimension-tree bound: two passes over Z per sweep
+    sweep_bytes = sum(r["bytes_per_launch"] for k, r in roof.items() if k.startswith("f32_"))
+    sweep_roof = {"bytes_per_sweep": sweep_bytes,
+                  "achieved_gbs": round(sweep_bytes / (ms_mixed * 1e-3) / 1e9, 1),
+                  "frac": round(sweep_bytes / (ms_mixed * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "bound_sweeps_per_s": round(HBM_PEAK_GBS * 1e9 / sweep_bytes, 1),
+                  "note": "sum of the algorithmic bytes of the sweep's MTTKRP launches (mode 0 and mode 1 "
+                          "read Z, modes >= 2 read Y) over the measured mixed sweep time"}
 
     equal_fit = None
     if not args.no_equal_fit:
@@ -286,6 +352,21 @@ def main():
             equal_fit["oracle_sweeps"] = g["sweeps"]
             equal_fit["fp64_rel_err_vs_oracle"] = abs(fit64 - g["final_fit_exact"]) / g["final_fit_exact"]
             equal_fit["mixed_rel_err_vs_oracle"] = abs(fitm - g["final_fit_exact"]) / g["final_fit_exact"]
+            # parity at equal sweep counts: the FP64 path run for exactly the
+            # oracle's sweeps (the 1e-12 rule can trip a few sweeps apart on two
+            # trajectories that agree to rounding)
+            A = fresh()
+            done = 0
+            while done < g["sweeps"]:
+                k = min(256, g["sweeps"] - done)
+                api.cp_als_sweep(ctx, Zd, A, None, k, CP_SOLVE_CHOL, 10, True, CP_FP64)
+                done += k
+            fit_eq = drivers.exact_fit(ctx, Zd, A)
+            equal_fit["fp64_at_oracle_sweeps"] = {
+                "sweeps": g["sweeps"], "fit": fit_eq,
+                "rel_err_vs_oracle": abs(fit_eq - g["final_fit_exact"]) / g["final_fit_exact"]}
+            log(f"fp64 at the oracle's {g['sweeps']} sweeps: fit {fit_eq:.16f}, rel err "
+                f"{abs(fit_eq - g['final_fit_exact']) / g['final_fit_exact']:.2e}")
 
     batched = None
     if not args.no_batched:
@@ -327,6 +408,8 @@ def main():
         "mttkrp_gbs": {k: round(v["achieved_gbs"], 1) for k, v in roof.items()},
         "mttkrp_us": {k: round(v["avg_us"], 2) for k, v in roof.items()},
         "roofline": roofline,
+        "sweep_roofline": sweep_roof,
+        "mttkrp_cold": cold,
         "per_sweep_us_event_bracketed": breakdown,
         "equal_fit": equal_fit,
         "tuned_plans": plans.strip().splitlines() if plans else None,
@@ -491,27 +574,49 @@ def batched_leg(ctx, api, synth):
     return out
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(Z, A0, seconds):
-    """The oracle's ALS sweep on the host: as many sweeps as fit in ``seconds``."""
+    """The oracle's ALS sweep on the host: as many sweeps as fit in ``seconds`` with
+    the BLAS thread pool as it is, then a third of that with one thread."""
     from oracle import cp
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
-    A = [a.copy() for a in A0]
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        A = cp.als_sweep(Z, A)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or n >= 500:
-            break
-    return {"value": round(n / el, 3), "unit": "ALS sweeps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} FP64 NumPy oracle ALS sweeps (explicit Khatri-Rao MTTKRP) on the same "
-                      f"{'x'.join(map(str, Z.shape))} R={A0[0].shape[1]} tensor from the same start, "
-                      f"{el:.1f} s"}
+
+    def run(limit_s):
+        A = [a.copy() for a in A0]
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            A = cp.als_sweep(Z, A)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= limit_s or n >= 500:
+                return n, el
+
+    n, el = run(seconds)
+    out = {"value": round(n / el, 3), "unit": "ALS sweeps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} FP64 NumPy oracle ALS sweeps (explicit Khatri-Rao MTTKRP) on the same "
+                     f"{'x'.join(map(str, Z.shape))} R={A0[0].shape[1]} tensor from the same start, "
+                     f"{el:.1f} s", "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, el1 = run(seconds / 3)
+        out["one_thread"] = {"value": round(n1 / el1, 3), "sample": f"{n1} sweeps, {el1:.1f} s"}
+    return out
 
 
 if __name__ == "__main__":

@@ -40,30 +40,59 @@ def fit_from_f(f, norm2):
     return 1.0 - math.sqrt(max(2.0 * f, 0.0) / norm2)
 
 
+def _copy_factors(dst, src):
+    for d, s in zip(dst.mats, src.mats):
+        d.copy_(s)
+    if dst.mats32 is not None and src.mats32 is not None:
+        for d, s in zip(dst.mats32, src.mats32):
+            d.copy_(s)
+
+
 def als_solve(ctx, Z, A, max_sweeps=10000, fit_tol=1e-12, chunk=16, prec=CP_FP64,
-              solver=CP_SOLVE_CHOL, sort_at_end=True):
-    """Standalone ALS (Section 3) with the fused objective read back per chunk."""
+              solver=CP_SOLVE_CHOL, sort_at_end=True, exact_stop=True):
+    """Standalone ALS (Section 3) with the fused objective read back per chunk.
+
+    The device runs ``chunk`` sweeps between two reads of the fit history.
+    With ``exact_stop`` the factors are kept as they were before each chunk, and
+    when the stopping rule holds after sweep j < chunk of a chunk they are put
+    back and exactly j sweeps are run again (the kernels are deterministic, so
+    this reproduces the first j sweeps): the solve ends on the sweep where the
+    rule first holds.  Without it the rest of the chunk runs too.
+    """
     torch = _torch()
     norm2 = float(Z.norm2.item())
     fh = torch.zeros(chunk, dtype=torch.float64, device=Z.z64.device if Z.z64 is not None else "cuda")
     res = SolveResult()
     prev = None
+    snap = A.clone() if (exact_stop and fit_tol) else None
     while res.sweeps < max_sweeps:
         k = min(chunk, max_sweeps - res.sweeps)
+        if snap is not None:
+            _copy_factors(snap, A)
         api.cp_als_sweep(ctx, Z, A, None, k, solver, 10, True, prec, fh)
         fv = fh[:k].cpu().numpy()
-        stop = False
+        stop_at = None
         for j in range(k):
             fit = fit_from_f(float(fv[j]), norm2)
-            res.fits.append(fit)
-            res.sweeps += 1
             if fit_tol and prev is not None and abs(fit - prev) <= fit_tol * abs(fit):
-                stop = True
-                res.converged = True
-                # the device already ran the rest of the chunk; keep counting them
+                stop_at = j + 1
+                break
             prev = fit
-        if stop:
-            break
+        if stop_at is None:
+            res.fits.extend(fit_from_f(float(x), norm2) for x in fv)
+            res.sweeps += k
+            continue
+        res.converged = True
+        if snap is not None and stop_at < k:
+            _copy_factors(A, snap)
+            api.cp_als_sweep(ctx, Z, A, None, stop_at, solver, 10, True, prec, fh)
+            fv = fh[:stop_at].cpu().numpy()
+            res.fits.extend(fit_from_f(float(x), norm2) for x in fv)
+            res.sweeps += stop_at
+        else:
+            res.fits.extend(fit_from_f(float(x), norm2) for x in fv)
+            res.sweeps += k
+        break
     if sort_at_end:
         api.cp_sort(ctx, A)
     res.final_fit = res.fits[-1] if res.fits else float("nan")
@@ -144,21 +173,45 @@ def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False, fp64=True):
 
 
 def fas_solve(ctx, levels, Z, A, fit_tol=1e-12, max_cycles=500, nu1=1, nu2=1, nuc=50, gs_iters=10,
-              ic_rule=0, prec=CP_FP64):
+              ic_rule=0, prec=CP_FP64, tol32=1e-9, window=1):
     """CP-FAS V-cycles (Algorithm 2) until the relative change of the exact fit is
     <= fit_tol (Section 6 caps: at most ``max_cycles`` cycles).  ``levels`` from
-    :func:`build_hierarchy`; ``Z`` is the finest-level DeviceTensor."""
+    :func:`build_hierarchy`; ``Z`` is the finest-level DeviceTensor.
+
+    Mixed form: V-cycles with FP32 contractions and coarse tensors while the fit
+    gains more than ``tol32`` * fit per cycle, then FP64 V-cycles (the levels
+    need both the FP32 and the FP64 tensors) until the fit_tol rule holds, so
+    the solve ends on the FP64 fixed point.  ``sweeps32`` / ``sweeps64`` count
+    the cycles of each phase.
+
+    CP-FAS is not a descent method: the fit of successive cycles can zigzag,
+    and a single small change can be a crossing rather than convergence.
+    ``window`` > 1 stops only when the last ``window`` changes are all within
+    the tolerance (1: the plain rule, as the oracle's driver applies it).
+    """
     res = SolveResult()
     prev = None
+    cur = prec
+    small = 0
     while res.sweeps < max_cycles:
         api.cp_fas_vcycle(ctx, levels, A, nu1=nu1, nu2=nu2, nuc=nuc, gs_iters=gs_iters, ic_rule=ic_rule,
-                          prec=prec)
+                          prec=cur)
         fit = exact_fit(ctx, Z, A)
         res.fits.append(fit)
         res.sweeps += 1
-        if fit_tol and prev is not None and abs(fit - prev) <= fit_tol * abs(fit):
-            res.converged = True
-            break
+        if cur == CP_MIXED:
+            res.sweeps32 += 1
+            if prev is not None and fit - prev <= tol32 * abs(fit):
+                cur = CP_FP64
+        else:
+            res.sweeps64 += 1
+            if fit_tol and prev is not None and abs(fit - prev) <= fit_tol * abs(fit):
+                small += 1
+                if small >= window:
+                    res.converged = True
+                    break
+            else:
+                small = 0
         prev = fit
     res.final_fit = res.fits[-1] if res.fits else float("nan")
     return res

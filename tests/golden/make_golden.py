@@ -100,9 +100,67 @@ def main_fas(names):
               flush=True)
 
 
+def c1_pipeline(restart=0, nt=2, first_sweeps=10, fit_tol=1e-12, max_sweeps=10000):
+    """The 20^3 R=3 workload as configured: ALS sweeps from the seeded start, one
+    down-sweep of Algorithm 1 (n_t seeded test blocks, the ALS iterate as the
+    boot factors) to build the 20 -> 10 transfer operators, one CP-FAS V-cycle
+    (Algorithm 2, Table 1), then ALS to the stopping rule."""
+    from oracle import amg
+    name = "c1_20cube_r3"
+    Z, _, spec = synth.workload(name)
+    dims, R = Z.shape, spec["R"]
+    A = synth.uniform_start(dims, R, spec["seed"], restart)
+    for _ in range(first_sweeps):
+        A = cp.als_sweep(Z, A)
+    tfms = [synth.uniform_start(dims, R, spec["seed"], 100 + k) for k in range(nt)]
+    levels, _ = amg.down_sweep(Z, A, tfms, [10, 10, 10])
+    weights = [[None if w is None else np.asarray(w).tolist() for w in lv.weights] for lv in levels[:-1]]
+    A = amg.fas_vcycle(levels, amg.zeros_like_factors(A), A, **amg.FAS_PARAMS)
+    fit_cycle = cp.fit(Z, A)
+    A, h = cp.als(Z, A, max_sweeps=max_sweeps, fit_tol=fit_tol, record="fused", sort_at_end=False)
+    return {"workload": name, "restart": restart, "first_sweeps": first_sweeps, "weights": weights,
+            "levels": len(levels), "fit_after_cycle": fit_cycle, "fit_tol": fit_tol,
+            "als_sweeps": h["sweeps"], "final_fit_exact": cp.fit(Z, A), "final_fit_fused": h["fit"][-1]}
+
+
+# Problems of the 512-tensor batch whose restarts the oracle solves: the
+# largest and the smallest tensor, the two problems with a restart that runs
+# into the 10^4-sweep cap (22: restart 2, 46: restart 1), the two whose
+# restarts need the most sweeps (187, 480), and ten more spread over the list.
+BATCH_SAMPLE = [267, 296, 22, 46, 187, 480, 0, 37, 101, 150, 199, 257, 310, 355, 420, 505]
+
+
+def batch_reference(sample=BATCH_SAMPLE, restarts=4, fit_tol=1e-12, max_sweeps=10000):
+    """Oracle FP64 ALS to the stopping rule (fused fit, as the batched solve uses)
+    for every restart of the sampled problems of the batched workload."""
+    probs = synth.batched_problems(max(sample) + 1)
+    out = {"sample": list(sample), "fit_tol": fit_tol, "max_sweeps": max_sweeps, "problems": []}
+    for b in sample:
+        p = probs[b]
+        rows = []
+        for k in range(restarts):
+            t = time.time()
+            A, h = cp.als(p["Z"], p["starts"][k], max_sweeps=max_sweeps, fit_tol=fit_tol, record="fused",
+                          sort_at_end=False)
+            rows.append({"restart": k, "sweeps": h["sweeps"], "final_fit_exact": cp.fit(p["Z"], A),
+                         "final_fit_fused": h["fit"][-1], "seconds": time.time() - t})
+            print(b, k, rows[-1], flush=True)
+        out["problems"].append({"b": b, "dims": list(p["dims"]), "R": p["R"], "c": p["c"], "restarts": rows})
+    return out
+
+
+def _dump(obj, name):
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(obj, f, indent=1)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if args and args[0] == "fas":
         main_fas(args[1:] or ["c2_128cube_r5"])
+    elif args and args[0] == "c1":
+        _dump(c1_pipeline(), "c1_20cube_r3_pipeline.json")
+    elif args and args[0] == "batch":
+        _dump(batch_reference(), "batch_sampled_final_fits.json")
     else:
         main(args or ["c1_20cube_r3"])

@@ -61,3 +61,11 @@ def mttkrp_err(got, Z, A, n):
     scale = cp.mttkrp(np.abs(Z), [np.abs(a) for a in A], n)
     scale = np.where(scale > 0, scale, 1.0)
     return float(np.max(np.abs(np.asarray(got, dtype=np.float64) - ref) / scale))
+
+
+def scaled_err(got, ref, scale):
+    """max_i |got_i - ref_i| / scale_i, where scale_i is the sum of the absolute
+    values of the terms that make ref_i (what a floating-point sum is accurate to)."""
+    scale = np.asarray(scale, dtype=np.float64)
+    scale = np.where(scale > 0, scale, 1.0)
+    return float(np.max(np.abs(np.asarray(got, dtype=np.float64) - np.asarray(ref, dtype=np.float64)) / scale))

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import cp
 from paper_1111_6091_amd import synth
-from tests.gpu_util import ctx as make_ctx, rel_err, say, sync
+from tests.gpu_util import ctx as make_ctx, elem_err, mttkrp_err, say, sync
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -46,7 +46,7 @@ def test_mttkrp_edge_shapes(C, dims, R, mixed):
         M = torch.empty((dims[n], R), dtype=torch.float64, device="cuda")
         api.cp_mttkrp(C, Zd, Ad, n, M, CP_MIXED if mixed else CP_FP64)
         sync()
-        e = rel_err(M.cpu().numpy(), cp.mttkrp(Z, A, n))
+        e = mttkrp_err(M.cpu().numpy(), Z, A, n)
         assert e < (2e-5 if mixed else 1e-12), (n, e)
 
 
@@ -74,9 +74,13 @@ def test_als_sweeps_edge_shapes(C, dims, R):
         ref = cp.als_sweep(Z, ref)
     got = Ad.to_numpy()
     assert C.status() == 0
+    # at R = 32 Gamma has a condition number near 2e6, so each solve carries
+    # absolute errors of about cond(Gamma) u max|A| (1e-10 max|A|) into entries
+    # of any size: there every entry is held against the factor's largest one
+    fl = 1.0 if R >= 32 else 1e-3
     for n in range(len(dims)):
-        assert rel_err(got[n], ref[n]) < 1e-8, (n, rel_err(got[n], ref[n]))
-    assert rel_err(cp.full(got), cp.full(ref)) < 1e-9
+        assert elem_err(got[n], ref[n], floor=fl) < 1e-8, (n, elem_err(got[n], ref[n], floor=fl))
+    assert elem_err(cp.full(got), cp.full(ref), floor=fl) < 1e-9
 
 
 def test_host_side_argument_errors(C):
@@ -126,6 +130,8 @@ def test_als_sweeps_dimension_tree_wide_rank(C, R):
         ref = cp.als_sweep(Z, ref)
         fref.append(cp.objective(Z, ref))
     got = Ad.to_numpy()
+    # at R = 32 against the factor's largest entry (Gamma's condition number grows with R)
+    fl = 1.0 if R >= 32 else 1e-3
     for n in range(3):
-        assert rel_err(got[n], ref[n]) < 1e-8, (n, rel_err(got[n], ref[n]))
+        assert elem_err(got[n], ref[n], floor=fl) < 1e-8, (n, elem_err(got[n], ref[n], floor=fl))
     np.testing.assert_allclose(fh.cpu().numpy(), fref, rtol=1e-9)
