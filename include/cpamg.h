@@ -128,8 +128,22 @@ cp_status cp_set_stream(cp_ctx ctx, void* hip_stream);
  *     arithmetic), for the MTTKRPs of modes >= 2, so a sweep streams Z twice
  *     instead of N times; used when Y takes at most a quarter of Z's bytes.
  *     0: every mode streams Z.
+ *   CP_OPT_GRAPHS (default 1): cp_fas_vcycle records its launch sequence into
+ *     a HIP graph the first time it sees an argument set (level tensors,
+ *     transfer operators, factors, parameters, precision) and replays the graph
+ *     on later calls with the same set; changing an option or growing the
+ *     workspace drops the recorded graphs.  Not while per-kernel profiling is
+ *     on.  0: every call launches its kernels one by one.
+ *   CP_OPT_SMALL_LEVELS (default 1): Gauss-Seidel relaxations without
+ *     normalization (every coarse level of cp_fas_vcycle, and cp_als_sweep with
+ *     CP_SOLVE_GS, normalize == 0 and no f_hist) on a tensor that fits in LDS
+ *     with its stage-1 tiles (about 150 KB; R <= 16) run all their sweeps in one
+ *     workgroup, tensor and factors resident in LDS, arithmetic in FP64.
+ *     0: the general per-mode kernels.
  * Returns CP_ERR_INVALID for an unknown option or value. */
 #define CP_OPT_DIMTREE 1
+#define CP_OPT_GRAPHS 2
+#define CP_OPT_SMALL_LEVELS 3
 cp_status cp_set_option(cp_ctx ctx, int32_t option, int32_t value);
 /* Text of the last host-side error of this context ("" if none); owned by ctx. */
 const char* cp_last_error(cp_ctx ctx);

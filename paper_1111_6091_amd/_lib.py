@@ -31,6 +31,8 @@ PROF_CLASSES = ["mttkrp_mode0_f64", "mttkrp_mode1_f64", "mttkrp_modeN_f64",
                 "update", "epilogue_other", "gamma_prep", "normalize", "gram", "other"]
 
 CP_OPT_DIMTREE = 1
+CP_OPT_GRAPHS = 2
+CP_OPT_SMALL_LEVELS = 3
 
 CP_FLAG_PINV_FALLBACK = 1
 CP_FLAG_NOT_SPD = 2

@@ -71,6 +71,13 @@ struct cp_ctx_s {
   double* scal = nullptr;   // 64 scratch scalars
   // sweeps of order >= 3 reuse the mode-1 stage-1 tiles for modes >= 2
   int dimtree = 1;
+  // CP-FAS V-cycles are recorded once into a HIP graph per argument set and
+  // replayed (CP_OPT_GRAPHS); capture runs on a private stream
+  int graphs = 1;
+  // relaxations of small levels in one workgroup (CP_OPT_SMALL_LEVELS)
+  int small = 1;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> gcache;
   // launch configurations of the MTTKRP kernels: tuned options and plan cache
   std::map<std::string, PlanOpts> tuned;
   std::map<std::string, MttkrpPlan> plans;
@@ -136,9 +143,16 @@ struct ProfScope {
 };
 
 // Grow the workspace to at least `bytes` (synchronizes the stream first).
+// Drop the recorded graphs (they hold workspace addresses).
+void clear_graphs(cp_ctx ctx) {
+  for (auto& kv : ctx->gcache) (void)hipGraphExecDestroy(kv.second);
+  ctx->gcache.clear();
+}
+
 cp_status ensure_ws(cp_ctx ctx, size_t bytes) {
   if (bytes <= ctx->ws_cap) return CP_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  clear_graphs(ctx);
   if (ctx->ws) HIPCHK(hipFree(ctx->ws));
   ctx->ws = nullptr;
   ctx->ws_cap = 0;
@@ -352,6 +366,32 @@ SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32) {
   return sp;
 }
 
+// Small-level relaxation (one workgroup, tensor in LDS) when the context allows
+// it and the level fits; returns false when the general path must run.
+bool try_small_relax(cp_ctx ctx, const int64_t* dims, int N, int R, const void* z, bool fp32,
+                     double* const* A, float* const* A32, double* const* F, int gs_iters, int nsweeps,
+                     cp_status* st) {
+  if (!ctx->small || nsweeps <= 0) return false;
+  SmallDesc d{};
+  d.z = z;
+  d.N = N;
+  d.R = R;
+  d.nsweeps = nsweeps;
+  d.gs_iters = gs_iters;
+  d.P = 1;
+  for (int m = 0; m < N; ++m) {
+    d.dims[m] = dims[m];
+    d.P *= dims[m];
+    d.A[m] = A[m];
+    d.A32[m] = A32 ? A32[m] : nullptr;
+    d.F[m] = F ? F[m] : nullptr;
+  }
+  if (!small_eligible(d, fp32)) return false;
+  ProfScope ps(ctx, CP_PROF_OTHER);
+  *st = hip_check(ctx, relax_small_launch(d, fp32, ctx->stream), "relax_small_launch");
+  return true;
+}
+
 // `nsweeps` BNGS sweeps over all modes starting from the stored factors A.
 // Enqueues: Grams of A, then per mode an MTTKRP launch (whose workgroup 0 does
 // the sweep bookkeeping for the update) and the update, then one finalize.
@@ -503,6 +543,8 @@ cp_status cp_ctx_destroy(cp_ctx ctx) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  clear_graphs(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->fixed) (void)hipFree(ctx->fixed);
   delete ctx;
@@ -513,6 +555,17 @@ cp_status cp_set_option(cp_ctx ctx, int32_t option, int32_t value) {
   if (!ctx) return CP_ERR_INVALID;
   if (option == CP_OPT_DIMTREE && (value == 0 || value == 1)) {
     ctx->dimtree = value;
+    clear_graphs(ctx);
+    return CP_OK;
+  }
+  if (option == CP_OPT_SMALL_LEVELS && (value == 0 || value == 1)) {
+    ctx->small = value;
+    clear_graphs(ctx);
+    return CP_OK;
+  }
+  if (option == CP_OPT_GRAPHS && (value == 0 || value == 1)) {
+    ctx->graphs = value;
+    clear_graphs(ctx);
     return CP_OK;
   }
   return set_err(ctx, CP_ERR_INVALID, "cp_set_option: unknown option %d or value %d", option, value);
@@ -658,6 +711,15 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   if (f_hist && !Z->norm2) return set_err(ctx, CP_ERR_INVALID, "f_hist needs Z->norm2");
   if (nsweeps == 0) return CP_OK;
   const int R = A->rank;
+  {
+    bool h32 = true;
+    for (int m = 0; m < N; ++m) h32 = h32 && A->a32[m];
+    cp_status st = CP_OK;
+    if (solver == CP_SOLVE_GS && !normalize && !f_hist &&
+        try_small_relax(ctx, Z->dims, N, R, mixed ? (const void*)Z->z32 : (const void*)Z->z64, mixed, A->a,
+                        h32 ? A->a32 : nullptr, F ? F->a : nullptr, gs_iters, nsweeps, &st))
+      return st;
+  }
   const SweepPlan sp = sweep_plan(ctx, Z->dims, N, R, mixed);
   Sizer sz;
   SweepWS w{};
@@ -1157,6 +1219,10 @@ struct FasRun {
 cp_status fas_relax(FasRun& r, int l, int times) {
   cp_ctx ctx = r.ctx;
   FasLevel& L = r.lv[l];
+  cp_status st = CP_OK;
+  if (l > 0 && try_small_relax(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A, L.has32 ? L.A32 : nullptr, L.F,
+                               r.p.gs_iters, times, &st))
+    return st;
   SweepWS w{L.grams, r.sigma, r.partial, r.gram_part, r.scal_part, L.sp.dimtree ? r.y : nullptr};
   return enqueue_sweeps(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A, L.has32 ? L.A32 : nullptr,
                         l == 0 ? nullptr : L.F, L.sp, w, CP_SOLVE_GS, r.p.gs_iters,
@@ -1185,6 +1251,48 @@ cp_status fas_H(FasRun& r, int l, double* const* A, float* const* A32, double* c
     d.outbuf = Hout[n];
     TRY(enqueue_epi(ctx, d));
   }
+  return CP_OK;
+}
+
+// Run `body` (which enqueues on ctx->stream) as a HIP graph: recorded on the
+// context's private capture stream the first time `key` is seen, replayed on
+// the context's stream after that.  A capture that fails leaves graphs off for
+// this context and runs `body` directly.
+template <typename F>
+cp_status run_graph(cp_ctx ctx, const std::string& key, F&& body) {
+  auto hit = ctx->gcache.find(key);
+  if (hit != ctx->gcache.end()) {
+    HIPCHK(hipGraphLaunch(hit->second, ctx->stream));
+    return CP_OK;
+  }
+  if (ctx->gcache.size() >= 32) clear_graphs(ctx);
+  if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = ctx->stream;
+  ctx->stream = ctx->cap_stream;
+  hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    ctx->stream = user;
+    ctx->graphs = 0;
+    return body();
+  }
+  const cp_status sb = body();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(ctx->cap_stream, &g);
+  ctx->stream = user;
+  if (sb != CP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return sb;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->graphs = 0;
+    return body();
+  }
+  ctx->gcache[key] = ex;
+  HIPCHK(hipGraphLaunch(ex, ctx->stream));
   return CP_OK;
 }
 
@@ -1307,10 +1415,25 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
     r.lv[0].A32[n] = A->a32[n];
   }
   for (int l = 0; l < nlevels; ++l) r.lv[l].has32 = (l == 0) ? have32 : (mixed || have32);
-  if ((s = fas_vcycle_rec(r, 0)) != CP_OK) return s;
-  if (r.lv[0].has32)   // shadows of the finest factors follow the last correction
-    TRY(enqueue_gram(ctx, A->a, A->a32, r.lv[0].dims, N, R, r.lv[0].grams));
-  return CP_OK;
+  auto body = [&]() -> cp_status {
+    cp_status t = fas_vcycle_rec(r, 0);
+    if (t != CP_OK) return t;
+    if (r.lv[0].has32)   // shadows of the finest factors follow the last correction
+      return enqueue_gram(ctx, A->a, A->a32, r.lv[0].dims, N, R, r.lv[0].grams);
+    return CP_OK;
+  };
+  if (!ctx->graphs || ctx->prof) return body();
+  // the launch sequence depends only on these arguments and the workspace
+  std::ostringstream key;
+  key << "fas;" << nlevels << ";" << N << ";" << R << ";" << (int)mixed << ";" << p.nu1 << "," << p.nu2 << ","
+      << p.nuc << "," << p.gs_iters << "," << p.ic_rule << ";" << (const void*)ctx->ws << ";" << ctx->ws_cap << ";"
+      << ctx->dimtree;
+  for (int l = 0; l < nlevels; ++l) {
+    key << "|" << r.lv[l].z;
+    for (int n = 0; n < N; ++n) key << "," << r.lv[l].dims[n] << "," << (const void*)r.lv[l].phat[n];
+  }
+  for (int n = 0; n < N; ++n) key << "|" << (const void*)A->a[n] << "," << (const void*)A->a32[n];
+  return run_graph(ctx, key.str(), body);
 }
 
 // ===========================================================================

@@ -277,6 +277,24 @@ hipError_t finish_g_launch(const double* acc, const double* norm2, double* g, hi
 hipError_t inner_launch(const double* A, const double* M, int64_t count, double* part,
                         int32_t* counter, double* out, hipStream_t st);
 
+// Relaxation of a small level in one workgroup (small.hip): `nsweeps` BNGS
+// sweeps with Gauss-Seidel inner solves and optional right-hand side F, no
+// normalization, the tensor resident in LDS.  Used when the tensor, the
+// stage-1 tiles and the factors fit in kSmallLdsBytes and R <= 16.
+struct SmallDesc {
+  const void* z;                  // tensor (double, or float for the mixed form)
+  int32_t N, R, nsweeps, gs_iters;
+  int64_t dims[kMaxOrder];
+  int64_t P;
+  double* A[kMaxOrder];
+  float* A32[kMaxOrder];          // refreshed at the end when set
+  const double* F[kMaxOrder];     // NULL: no right-hand side
+};
+constexpr size_t kSmallLdsBytes = 152 * 1024;
+bool small_eligible(const SmallDesc& d, bool fp32);
+size_t small_lds_bytes(const SmallDesc& d, bool fp32);
+hipError_t relax_small_launch(const SmallDesc& d, bool fp32, hipStream_t st);
+
 // utilities
 hipError_t cast_launch(const double* src, float* dst, int64_t count, hipStream_t st);
 hipError_t norm2_launch(const double* z, int64_t count, double* part, int32_t* counter,

@@ -1,0 +1,324 @@
+// Relaxation of a small level in one workgroup.
+//
+// A CP-FAS V-cycle (Algorithm 2) ends on its coarsest level with nu_c = 50
+// BNGS sweeps (Table 1), and every coarse level relaxes with right-hand side F
+// and Gauss-Seidel inner solves (Section 5.2).  There the tensor holds a few
+// thousand entries, so one sweep is a few microseconds of arithmetic while the
+// general path spends two kernel launches per mode on it.  This kernel runs all
+// the sweeps of one relaxation in a single workgroup: it loads the level tensor
+// into LDS once, keeps the factors, their Gram matrices and Gamma in LDS, and
+// writes the factors back at the end.
+//
+// Per sweep and mode n (in the order of the oracle's BNGS sweep):
+//   Gamma^(n) = Hadamard product of the Grams of the other modes (eq. (8)),
+//   M^(n)     = Z_(n) Phi^(n) (eq. (6)-(7)), Khatri-Rao matrix never formed:
+//               mode 0 sums fibres along mode 0 weighted by the products of the
+//               other factors; after A^(0) is updated, the stage-1 tiles
+//               T0[s][r] = sum_i0 Z(i0, s) A^(0)(i0, r) serve every mode >= 1,
+//   A^(n)     <- gs_iters Gauss-Seidel iterations on A^(n) Gamma = M + F, r in
+//               increasing order with the newest values, warm-started (the
+//               division by the pivot applied as a product with its reciprocal),
+//   Upsilon^(n) = A^(n)T A^(n).
+// All arithmetic is FP64; an FP32 tensor is widened on load.  Sums run in a
+// fixed order, so results are deterministic.
+#include "internal.hpp"
+
+namespace cpamg {
+
+constexpr int kSmallThreads = 512;    // 8 waves, two per SIMD; leaves room for Gamma in registers
+
+// LDS layout (in doubles unless noted); the host computes the same offsets
+struct SmallLayout {
+  int64_t a, grams, gam, m, red, t0, dig, perm, z;   // dig: uint16, perm: int32, z: T
+  int64_t bytes;
+};
+
+__host__ __device__ inline SmallLayout small_layout(const SmallDesc& d, int esz) {
+  SmallLayout L{};
+  int64_t sumIR = 0, imax = 0;
+  for (int m = 0; m < d.N; ++m) {
+    sumIR += d.dims[m] * d.R;
+    imax = d.dims[m] > imax ? d.dims[m] : imax;
+  }
+  const int64_t RR = (int64_t)d.R * d.R;
+  const int64_t S0 = d.P / d.dims[0];
+  int64_t o = 0;
+  L.a = o;      o += sumIR;
+  L.grams = o;  o += d.N * RR;
+  L.gam = o;    o += RR;
+  L.m = o;      o += imax * d.R;
+  L.red = o;    o += kSmallThreads;
+  L.t0 = o;     o += S0 * d.R;
+  L.dig = o;    o += (S0 * (d.N - 1) * 2 + 7) / 8;        // digits s_m of every fibre, uint16
+  L.perm = o;   o += (S0 * (d.N - 1) * 4 + 7) / 8;        // fibres ordered by s_n, per mode n >= 1
+  L.z = o;
+  L.bytes = o * 8 + d.P * esz;
+  return L;
+}
+
+template <typename T, int RM>
+__global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d) {
+  extern __shared__ double sm[];
+  const SmallLayout L = small_layout(d, (int)sizeof(T));
+  const int N = d.N, R = d.R, RR = R * R, tid = threadIdx.x;
+  double* sA = sm + L.a;
+  double* sGr = sm + L.grams;
+  double* sG = sm + L.gam;
+  double* sM = sm + L.m;
+  double* sRed = sm + L.red;
+  double* sT0 = sm + L.t0;   // stage-1 tiles T0[s][r]; during mode 0 the weights W[s][r]
+  uint16_t* sDig = reinterpret_cast<uint16_t*>(sm + L.dig);   // [s][m - 1]
+  int32_t* sPerm = reinterpret_cast<int32_t*>(sm + L.perm);    // [n - 1][s_n * rest + k]
+  T* sZ = reinterpret_cast<T*>(sm + L.z);
+  int I[kMaxOrder];
+  int offA[kMaxOrder];
+  int st[kMaxOrder];   // strides of modes 1..N-1 in the fibre index s
+  {
+    int o = 0, acc = 1;
+    for (int m = 0; m < N; ++m) {
+      I[m] = (int)d.dims[m];
+      offA[m] = o;
+      o += I[m] * R;
+      if (m >= 1) {
+        st[m] = acc;
+        acc *= I[m];
+      }
+    }
+  }
+  const int I0 = I[0];
+  const int S0 = (int)(d.P / I0);
+  const int NM = N - 1;   // modes 1..N-1
+  const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
+  // tensor and factors into LDS (several loads in flight per thread)
+  for (int64_t base = 0; base < d.P; base += 8 * kSmallThreads) {
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t idx = base + tid + q * kSmallThreads;
+      v[q] = idx < d.P ? z[idx] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t idx = base + tid + q * kSmallThreads;
+      if (idx < d.P) sZ[idx] = v[q];
+    }
+  }
+  for (int m = 0; m < N; ++m)
+    for (int idx = tid; idx < I[m] * R; idx += kSmallThreads) sA[offA[m] + idx] = d.A[m][idx];
+  // index tables, built once: the digits of every fibre, and for each mode
+  // n >= 1 the fibres listed by their digit s_n (the other digits in
+  // increasing mixed-radix order)
+  for (int s = tid; s < S0; s += kSmallThreads)
+    for (int m = 1; m < N; ++m) sDig[s * NM + m - 1] = (uint16_t)((s / st[m]) % I[m]);
+  for (int n = 1; n < N; ++n) {
+    const int rest = S0 / I[n];
+    int32_t* perm = sPerm + (n - 1) * S0;
+    for (int j = tid; j < S0; j += kSmallThreads) {
+      const int i = j / rest;
+      int k = j - i * rest;
+      int s = i * st[n];
+      for (int m = 1; m < N; ++m) {
+        if (m == n) continue;
+        s += (k % I[m]) * st[m];
+        k /= I[m];
+      }
+      perm[j] = s;
+    }
+  }
+  __syncthreads();
+  // Gram of mode m from the LDS factor: the rows split over GG thread groups,
+  // the group sums added in group order (every thread calls it)
+  auto gram = [&](int m) {
+    const int GG = RR >= kSmallThreads ? 1 : (kSmallThreads / RR < 16 ? kSmallThreads / RR : 16);
+    const double* a = sA + offA[m];
+    for (int q0 = 0; q0 < RR; q0 += kSmallThreads) {
+      const int idx = q0 + (RR < kSmallThreads ? tid % RR : tid);
+      const int g = RR < kSmallThreads ? tid / RR : 0;
+      double acc = 0.0;
+      if (idx < RR && g < GG) {
+        const int r = idx / R, c = idx % R;
+        for (int i = g; i < I[m]; i += GG) acc += a[i * R + r] * a[i * R + c];
+      }
+      if (GG > 1) {
+        if (idx < RR && g < GG) sRed[g * RR + idx] = acc;
+        __syncthreads();
+        if (tid < RR) {
+          double t = 0.0;
+          for (int gg = 0; gg < GG; ++gg) t += sRed[gg * RR + tid];
+          sGr[m * RR + tid] = t;
+        }
+        __syncthreads();
+      } else if (idx < RR) {
+        sGr[m * RR + idx] = acc;
+      }
+    }
+  };
+  for (int m = 0; m < N; ++m) gram(m);
+  __syncthreads();
+
+  for (int sweep = 0; sweep < d.nsweeps; ++sweep) {
+    for (int n = 0; n < N; ++n) {
+      // Gamma^(n)
+      for (int idx = tid; idx < RR; idx += kSmallThreads) {
+        double g = 1.0;
+        for (int m = 0; m < N; ++m)
+          if (m != n) g *= sGr[m * RR + idx];
+        sG[idx] = g;
+      }
+      if (n == 0) {
+        // weights W[s][r] = prod_{m >= 1} A^(m)(s_m, r) of every fibre
+        for (int idx = tid; idx < S0 * R; idx += kSmallThreads) {
+          const int s = idx / R, r = idx - (idx / R) * R;
+          double w = 1.0;
+          for (int m = 1; m < N; ++m) w *= sA[offA[m] + sDig[s * NM + m - 1] * R + r];
+          sT0[idx] = w;
+        }
+        __syncthreads();
+      }
+      // M^(n): (row, column) pairs, the contraction split over G thread groups
+      const int pairs = I[n] * R;
+      const int G = pairs >= kSmallThreads ? 1 : kSmallThreads / pairs;
+      const int rest = S0 / (n == 0 ? 1 : I[n]);
+      for (int q0 = 0; q0 < pairs; q0 += kSmallThreads) {
+        const int q = q0 + tid % (pairs < kSmallThreads ? pairs : kSmallThreads);
+        const int g = pairs < kSmallThreads ? tid / pairs : 0;
+        double acc = 0.0;
+        const bool live = (pairs < kSmallThreads) ? (g < G) : (q < pairs);
+        if (live) {
+          const int i = q % I[n], r = q / I[n];
+          double a4[4] = {0.0, 0.0, 0.0, 0.0};
+          if (n == 0) {
+            int s = g;
+            for (; s + 3 * G < S0; s += 4 * G)
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                a4[u] += (double)sZ[(s + u * G) * I0 + i] * sT0[(s + u * G) * R + r];
+            for (int u = 0; s < S0; s += G, ++u) a4[u] += (double)sZ[s * I0 + i] * sT0[s * R + r];
+          } else {
+            const int32_t* pr = sPerm + (n - 1) * S0 + i * rest;
+            int k = g;
+            for (int u = 0; k < rest; k += G, u = (u + 1) & 3) {
+              const int s = pr[k];
+              double w = sT0[s * R + r];
+              for (int m = 1; m < N; ++m)
+                if (m != n) w *= sA[offA[m] + sDig[s * NM + m - 1] * R + r];
+              a4[u] += w;
+            }
+          }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        }
+        if (pairs < kSmallThreads) {
+          if (live) sRed[g * pairs + q] = acc;
+          __syncthreads();
+          if (tid < pairs) {
+            double t = 0.0;
+            for (int gg = 0; gg < G; ++gg) t += sRed[gg * pairs + tid];
+            sM[(tid % I[n]) * R + tid / I[n]] = t;
+          }
+        } else if (q < pairs) {
+          sM[(q % I[n]) * R + q / I[n]] = acc;
+        }
+      }
+      __syncthreads();
+      // Gauss-Seidel on the rows of A^(n) (one thread per row):
+      //   x_r <- (b_r - sum_{k != r} x_k Gamma_kr) / Gamma_rr, r = 0..R-1, newest values;
+      // Gamma (and its reciprocal pivots) in registers for R <= 8
+      {
+        const double* __restrict__ F = d.F[n];
+        double* a = sA + offA[n];
+        for (int i = tid; i < I[n]; i += kSmallThreads) {
+          double x[RM], b[RM], dinv[RM];
+          double gm[RM <= 8 ? RM : 1][RM <= 8 ? RM : 1];
+#pragma unroll
+          for (int r = 0; r < RM; ++r) {
+            x[r] = r < R ? a[i * R + r] : 0.0;
+            b[r] = r < R ? sM[i * R + r] + (F ? F[(int64_t)i * R + r] : 0.0) : 0.0;
+            const double dg = r < R ? sG[r * R + r] : 0.0;
+            dinv[r] = dg != 0.0 ? 1.0 / dg : 0.0;
+          }
+          if (RM <= 8) {
+#pragma unroll
+            for (int k = 0; k < (RM <= 8 ? RM : 1); ++k)
+#pragma unroll
+              for (int r = 0; r < (RM <= 8 ? RM : 1); ++r) gm[k][r] = (k < R && r < R) ? sG[k * R + r] : 0.0;
+          }
+          for (int it = 0; it < d.gs_iters; ++it) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+              if (r >= R) break;
+              if (dinv[r] == 0.0) continue;
+              double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+              for (int k = 0; k < RM; ++k) {
+                if (k >= R || k == r) continue;
+                const double gkr = RM <= 8 ? gm[RM <= 8 ? k : 0][RM <= 8 ? r : 0] : sG[k * R + r];
+                if (k & 1) t1 += x[k] * gkr;
+                else t0 += x[k] * gkr;
+              }
+              x[r] = (b[r] - (t0 + t1)) * dinv[r];
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RM; ++r)
+            if (r < R) a[i * R + r] = x[r];
+        }
+      }
+      __syncthreads();
+      gram(n);
+      if (n == 0 && N > 1) {
+        // stage-1 tiles of the updated A^(0) for the modes >= 1 of this sweep
+        for (int idx = tid; idx < S0 * R; idx += kSmallThreads) {
+          const int s = idx / R, r = idx - (idx / R) * R;
+          const T* zf = sZ + s * I0;
+          const double* a0 = sA + offA[0];
+          double t0 = 0.0, t1 = 0.0;
+          int i0 = 0;
+          for (; i0 + 1 < I0; i0 += 2) {
+            t0 += (double)zf[i0] * a0[i0 * R + r];
+            t1 += (double)zf[i0 + 1] * a0[(i0 + 1) * R + r];
+          }
+          if (i0 < I0) t0 += (double)zf[i0] * a0[i0 * R + r];
+          sT0[idx] = t0 + t1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int m = 0; m < N; ++m)
+    for (int idx = tid; idx < I[m] * R; idx += kSmallThreads) {
+      const double v = sA[offA[m] + idx];
+      d.A[m][idx] = v;
+      if (d.A32[m]) d.A32[m][idx] = (float)v;
+    }
+}
+
+size_t small_lds_bytes(const SmallDesc& d, bool fp32) {
+  return (size_t)small_layout(d, fp32 ? 4 : 8).bytes;
+}
+
+bool small_eligible(const SmallDesc& d, bool fp32) {
+  if (d.N < 2 || d.N > kMaxOrder || d.R < 1 || d.R > 16) return false;
+  for (int m = 1; m < d.N; ++m)
+    if (d.dims[m] > 65535) return false;   // digits are held as 16-bit values
+  return small_lds_bytes(d, fp32) <= kSmallLdsBytes;
+}
+
+hipError_t relax_small_launch(const SmallDesc& d, bool fp32, hipStream_t st) {
+  if (!small_eligible(d, fp32)) return hipErrorInvalidValue;
+  const size_t lds = small_lds_bytes(d, fp32);
+  const void* k;
+  if (fp32) k = d.R <= 8 ? (const void*)relax_small_kernel<float, 8> : (const void*)relax_small_kernel<float, 16>;
+  else k = d.R <= 8 ? (const void*)relax_small_kernel<double, 8> : (const void*)relax_small_kernel<double, 16>;
+  static bool attr_set[4] = {false, false, false, false};
+  const int ki = (fp32 ? 2 : 0) + (d.R <= 8 ? 0 : 1);
+  if (!attr_set[ki]) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsBytes);
+    if (e != hipSuccess) return e;
+    attr_set[ki] = true;
+  }
+  SmallDesc dd = d;
+  void* args[] = {&dd};
+  return hipLaunchKernel(k, dim3(1), dim3(kSmallThreads), args, lds, st);
+}
+
+}  // namespace cpamg

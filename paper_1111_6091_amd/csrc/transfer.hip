@@ -79,9 +79,19 @@ __global__ void prolong_kernel(int64_t I, int64_t Ic, int R, const double* __res
   const int r = (int)(idx % R);
   double acc;
   if (phat) {
-    acc = 0.0;
-    for (int64_t j = 0; j < Ic; ++j)
-      acc += phat[i * Ic + j] * (Act ? (Ac[j * R + r] - Act[j * R + r]) : Ac[j * R + r]);
+    // four partial sums, so that many loads are in flight per thread
+    const double* prow = phat + i * Ic;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t j = 0;
+    for (; j + 3 < Ic; j += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t jj = j + u;
+        a4[u] += prow[jj] * (Act ? (Ac[jj * R + r] - Act[jj * R + r]) : Ac[jj * R + r]);
+      }
+    for (int u = 0; j < Ic; ++j, ++u)
+      a4[u] += prow[j] * (Act ? (Ac[j * R + r] - Act[j * R + r]) : Ac[j * R + r]);
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   } else {
     acc = Act ? (Ac[i * R + r] - Act[i * R + r]) : Ac[i * R + r];
   }
@@ -105,7 +115,13 @@ __global__ void restrict_factor_kernel(int64_t I, int64_t Ic, int R,
   const int r = (int)(idx % R);
   double acc = 0.0;
   if (phat) {
-    for (int64_t i = 0; i < I; ++i) acc += phat[i * Ic + j] * A[i * R + r];
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = 0;
+    for (; i + 3 < I; i += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] += phat[(i + u) * Ic + j] * A[(i + u) * R + r];
+    for (int u = 0; i < I; ++i, ++u) a4[u] += phat[i * Ic + j] * A[i * R + r];
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   } else {
     acc = A[j * R + r];
   }
@@ -127,10 +143,16 @@ __global__ void fas_rhs_kernel(int64_t I, int64_t Ic, int R, const double* __res
   if (idx >= Ic * R) return;
   const int64_t j = idx / R;
   const int r = (int)(idx % R);
-  double acc = 0.0;
-  for (int64_t i = 0; i < I; ++i)
-    acc += phat[i * Ic + j] * ((F ? F[i * R + r] : 0.0) - H[i * R + r]);
-  Fc[idx] = Hc[idx] + acc;
+  double a4[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = 0;
+  for (; i + 3 < I; i += 4)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t ii = i + u;
+      a4[u] += phat[ii * Ic + j] * ((F ? F[ii * R + r] : 0.0) - H[ii * R + r]);
+    }
+  for (int u = 0; i < I; ++i, ++u) a4[u] += phat[i * Ic + j] * ((F ? F[i * R + r] : 0.0) - H[i * R + r]);
+  Fc[idx] = Hc[idx] + ((a4[0] + a4[1]) + (a4[2] + a4[3]));
 }
 
 hipError_t fas_rhs_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* F,

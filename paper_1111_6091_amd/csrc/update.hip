@@ -142,6 +142,52 @@ __device__ inline double wave_gs(double b, double x, const double* G, int R, int
   return x;
 }
 
+// The same Gauss-Seidel iterations with every lane holding the whole row
+// (uniform across the wave) and Gamma in registers: no broadcasts or LDS reads
+// inside the iteration; x_r <- (b_r - sum_{k != r} x_k Gamma_kr) / Gamma_rr with
+// the division applied as a product with the reciprocal pivot.  RM >= R.
+template <int RM>
+__device__ inline double wave_gs_reg(double b, double x, const double* G, int R, int iters, int lane) {
+  double xv[RM], bv[RM], dinv[RM], g[RM][RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    xv[r] = r < R ? wave_bcast(x, r) : 0.0;
+    bv[r] = r < R ? wave_bcast(b, r) : 0.0;
+    const double dg = r < R ? G[r * R + r] : 0.0;
+    dinv[r] = dg != 0.0 ? 1.0 / dg : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < RM; ++k)
+#pragma unroll
+    for (int r = 0; r < RM; ++r) g[k][r] = (k < R && r < R) ? G[k * R + r] : 0.0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+      if (r >= R) break;
+      if (dinv[r] == 0.0) continue;
+      double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < RM; ++k) {
+        if (k >= R || k == r) continue;
+        if (k & 1) t1 += xv[k] * g[k][r];
+        else t0 += xv[k] * g[k][r];
+      }
+      xv[r] = (bv[r] - (t0 + t1)) * dinv[r];
+    }
+  }
+  double out = 0.0;
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+    if (lane == r) out = xv[r];
+  return out;
+}
+
+__device__ inline double wave_gs_any(double b, double x, const double* G, int R, int iters, int lane) {
+  if (R <= 4) return wave_gs_reg<4>(b, x, G, R, iters, lane);
+  if (R <= 8) return wave_gs_reg<8>(b, x, G, R, iters, lane);
+  return wave_gs(b, x, G, R, iters, lane);
+}
+
 // One block of rows of a mode epilogue; blk / nblk: this block's index and the
 // number of blocks of the epilogue (blk * EPI_ROWS is its first row).
 __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
@@ -233,7 +279,7 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
       x = wave_apply_any(b, sG, R, kind, lane);
     } else {
       const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
-      x = wave_gs(b, x0, sG, R, d.gs_iters, lane);
+      x = wave_gs_any(b, x0, sG, R, d.gs_iters, lane);
     }
     wr = lane < R && !(d.st && d.st->frozen[lane / Rg]);
     if (wr) ip = x * m;

@@ -145,6 +145,44 @@ def test_als_gs_with_rhs_matches_oracle_bngs(C):
         assert elem_err(got[n], A[n]) < 1e-10, (n, elem_err(got[n], A[n]))
 
 
+@pytest.mark.parametrize("dims,R,sweeps,mixed", [
+    ((14, 15, 16), 3, 3, False), ((10, 10, 10), 5, 50, False), ((6, 7, 8, 5), 4, 4, False),
+    ((12, 9), 2, 5, False), ((16, 16, 16), 16, 3, False), ((16, 16, 16), 5, 20, True),
+    ((7, 5, 9), 8, 6, False)])
+def test_small_level_relaxation_matches_oracle(C, dims, R, sweeps, mixed):
+    """BNGS sweeps with a right-hand side and Gauss-Seidel solves, no
+    normalization (a coarse-level relaxation of Algorithm 2) on tensors that fit
+    in LDS: one workgroup runs every sweep.  With an FP32 tensor the kernel widens
+    each entry and computes in FP64, so it is held against the oracle on the
+    FP32-rounded tensor.  The same call with the option off (general kernels)
+    agrees too."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_OPT_SMALL_LEVELS
+    say(f"small-level relaxation dims={dims} R={R} sweeps={sweeps} mixed={mixed}")
+    Z, _ = synth.collinear_tensor(dims, min(R, 3), 0.6, 0.02, 0.0, seed=sum(dims))
+    A0 = synth.uniform_start(dims, R, 7)
+    rng = np.random.default_rng(11)
+    F = [0.1 * rng.standard_normal((d, R)) for d in dims]
+    Zref = Z.astype(np.float32).astype(np.float64) if mixed else Z
+    ref = A0
+    for _ in range(sweeps):
+        ref = amg.bngs(Zref, ref, F, gs_iters=10, normalize_after=False)
+    Fd = api.DeviceFactors.from_numpy(C, F)
+    prec = api.CP_MIXED if mixed else api.CP_FP64
+    for small in (1, 0):
+        C.set_option(CP_OPT_SMALL_LEVELS, small)
+        Zd, Ad = dev_inputs(C, Z, A0, fp32=mixed)
+        api.cp_als_sweep(C, Zd, Ad, Fd, sweeps, api.CP_SOLVE_GS, 10, False, prec, None)
+        sync()
+        got = Ad.to_numpy()
+        tol = 1e-9 if small else (2e-4 if mixed else 1e-9)
+        for n in range(len(dims)):
+            e = elem_err(got[n], ref[n], floor=1e-3 if sweeps <= 6 else 1.0)
+            assert e < tol, (small, n, e)
+    C.set_option(CP_OPT_SMALL_LEVELS, 1)
+    assert C.status() == 0
+
+
 def test_singular_gamma_uses_pseudoinverse(C):
     from paper_1111_6091_amd import api
     say("pinv fallback")
@@ -261,10 +299,13 @@ def _oracle_levels(Z, weights, coarsest):
     return amg.hierarchy_from_weights(Z, weights, coarsest)
 
 
+@pytest.mark.parametrize("small", [1, 0])
 @pytest.mark.parametrize("dims,R,nlev", [((20, 20, 20), 3, 2), ((32, 32, 32), 3, 3), ((24, 20, 6), 2, 2)])
-def test_fas_vcycle_matches_oracle(C, dims, R, nlev):
+def test_fas_vcycle_matches_oracle(C, dims, R, nlev, small):
     from paper_1111_6091_amd import api, drivers
-    say(f"fas vcycle dims={dims} R={R} levels={nlev}")
+    from paper_1111_6091_amd._lib import CP_OPT_SMALL_LEVELS
+    C.set_option(CP_OPT_SMALL_LEVELS, small)
+    say(f"fas vcycle dims={dims} R={R} levels={nlev} small-level kernel={small}")
     Z, _ = synth.collinear_tensor(dims, R, 0.5, 0.01, 0.0, seed=10)
     A0, _ = cp.als(Z, synth.uniform_start(dims, R, 10), max_sweeps=10, fit_tol=0.0, sort_at_end=False)
     # weights per level (linear interpolation); modes of size <= 6 are not coarsened
@@ -286,3 +327,4 @@ def test_fas_vcycle_matches_oracle(C, dims, R, nlev):
     for n in range(len(dims)):
         assert elem_err(got[n], ref[n]) < 1e-9, (n, elem_err(got[n], ref[n]))
     assert elem_err(cp.full(got), cp.full(ref)) < 1e-11
+    C.set_option(CP_OPT_SMALL_LEVELS, 1)
