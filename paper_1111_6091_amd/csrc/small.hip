@@ -56,7 +56,72 @@ __host__ __device__ inline SmallLayout small_layout(const SmallDesc& d, int esz)
   return L;
 }
 
-template <typename T, int RM>
+// Gauss-Seidel iterations on the rows i < I of X (LDS, row-major, ld R), one
+// thread per row: x Gamma = b with b = M (LDS) + F (global, optional),
+//   x_r <- (b_r - sum_{k != r} x_k Gamma_kr) / Gamma_rr, r = 0..R-1, newest values,
+// a zero pivot leaving x_r as is.  RM >= R: register arrays of exactly RM
+// entries with static indices only (entries r >= R are zero and never change).
+// Per iteration the sums over k > r use the previous iterate and are formed
+// first, side by side; each new x_r is then added into the pending sums of the
+// later components, so the serial chain per component is one product, a
+// subtraction and a scaling (the division applied as a product with the
+// reciprocal pivot).
+template <int RM, int NT>
+__device__ __forceinline__ void gs_rows(double* X, const double* sM, const double* __restrict__ F,
+                                        const double* sG, int I, int R, int iters) {
+  for (int i = threadIdx.x; i < I; i += NT) {
+    double x[RM], b[RM], dinv[RM], g[RM][RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+      x[r] = r < R ? X[i * R + r] : 0.0;
+      b[r] = r < R ? sM[i * R + r] + (F ? F[(int64_t)i * R + r] : 0.0) : 0.0;
+      const double dg = r < R ? sG[r * R + r] : 0.0;
+      dinv[r] = dg != 0.0 ? 1.0 / dg : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RM; ++k)
+#pragma unroll
+      for (int r = 0; r < RM; ++r) g[k][r] = (k < R && r < R) ? sG[k * R + r] : 0.0;
+    for (int it = 0; it < iters; ++it) {
+      double up[RM], lo[RM];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = r + 1; k < RM; ++k) t += x[k] * g[k][r];
+        up[r] = t;
+        lo[r] = 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        const double v = (b[r] - (up[r] + lo[r])) * dinv[r];
+        x[r] = (r < R && dinv[r] != 0.0) ? v : x[r];
+#pragma unroll
+        for (int j = r + 1; j < RM; ++j) lo[j] += x[r] * g[r][j];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+      if (r < R) X[i * R + r] = x[r];
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void gs_rows_any(double* X, const double* sM, const double* F,
+                                            const double* sG, int I, int R, int iters) {
+  switch (R) {
+    case 1: case 2: gs_rows<2, NT>(X, sM, F, sG, I, R, iters); break;
+    case 3: gs_rows<3, NT>(X, sM, F, sG, I, R, iters); break;
+    case 4: gs_rows<4, NT>(X, sM, F, sG, I, R, iters); break;
+    case 5: gs_rows<5, NT>(X, sM, F, sG, I, R, iters); break;
+    case 6: gs_rows<6, NT>(X, sM, F, sG, I, R, iters); break;
+    case 7: case 8: gs_rows<8, NT>(X, sM, F, sG, I, R, iters); break;
+    case 9: case 10: case 11: case 12: gs_rows<12, NT>(X, sM, F, sG, I, R, iters); break;
+    default: gs_rows<16, NT>(X, sM, F, sG, I, R, iters); break;
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d) {
   extern __shared__ double sm[];
   const SmallLayout L = small_layout(d, (int)sizeof(T));
@@ -220,49 +285,8 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
         }
       }
       __syncthreads();
-      // Gauss-Seidel on the rows of A^(n) (one thread per row):
-      //   x_r <- (b_r - sum_{k != r} x_k Gamma_kr) / Gamma_rr, r = 0..R-1, newest values;
-      // Gamma (and its reciprocal pivots) in registers for R <= 8
-      {
-        const double* __restrict__ F = d.F[n];
-        double* a = sA + offA[n];
-        for (int i = tid; i < I[n]; i += kSmallThreads) {
-          double x[RM], b[RM], dinv[RM];
-          double gm[RM <= 8 ? RM : 1][RM <= 8 ? RM : 1];
-#pragma unroll
-          for (int r = 0; r < RM; ++r) {
-            x[r] = r < R ? a[i * R + r] : 0.0;
-            b[r] = r < R ? sM[i * R + r] + (F ? F[(int64_t)i * R + r] : 0.0) : 0.0;
-            const double dg = r < R ? sG[r * R + r] : 0.0;
-            dinv[r] = dg != 0.0 ? 1.0 / dg : 0.0;
-          }
-          if (RM <= 8) {
-#pragma unroll
-            for (int k = 0; k < (RM <= 8 ? RM : 1); ++k)
-#pragma unroll
-              for (int r = 0; r < (RM <= 8 ? RM : 1); ++r) gm[k][r] = (k < R && r < R) ? sG[k * R + r] : 0.0;
-          }
-          for (int it = 0; it < d.gs_iters; ++it) {
-#pragma unroll
-            for (int r = 0; r < RM; ++r) {
-              if (r >= R) break;
-              if (dinv[r] == 0.0) continue;
-              double t0 = 0.0, t1 = 0.0;
-#pragma unroll
-              for (int k = 0; k < RM; ++k) {
-                if (k >= R || k == r) continue;
-                const double gkr = RM <= 8 ? gm[RM <= 8 ? k : 0][RM <= 8 ? r : 0] : sG[k * R + r];
-                if (k & 1) t1 += x[k] * gkr;
-                else t0 += x[k] * gkr;
-              }
-              x[r] = (b[r] - (t0 + t1)) * dinv[r];
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < RM; ++r)
-            if (r < R) a[i * R + r] = x[r];
-        }
-      }
+      // Gauss-Seidel on the rows of A^(n), one thread per row
+      gs_rows_any<kSmallThreads>(sA + offA[n], sM, d.F[n], sG, I[n], R, d.gs_iters);
       __syncthreads();
       gram(n);
       if (n == 0 && N > 1) {
@@ -306,11 +330,9 @@ bool small_eligible(const SmallDesc& d, bool fp32) {
 hipError_t relax_small_launch(const SmallDesc& d, bool fp32, hipStream_t st) {
   if (!small_eligible(d, fp32)) return hipErrorInvalidValue;
   const size_t lds = small_lds_bytes(d, fp32);
-  const void* k;
-  if (fp32) k = d.R <= 8 ? (const void*)relax_small_kernel<float, 8> : (const void*)relax_small_kernel<float, 16>;
-  else k = d.R <= 8 ? (const void*)relax_small_kernel<double, 8> : (const void*)relax_small_kernel<double, 16>;
-  static bool attr_set[4] = {false, false, false, false};
-  const int ki = (fp32 ? 2 : 0) + (d.R <= 8 ? 0 : 1);
+  const void* k = fp32 ? (const void*)relax_small_kernel<float> : (const void*)relax_small_kernel<double>;
+  static bool attr_set[2] = {false, false};
+  const int ki = fp32 ? 1 : 0;
   if (!attr_set[ki]) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsBytes);
     if (e != hipSuccess) return e;

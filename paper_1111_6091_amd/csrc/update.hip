@@ -160,19 +160,26 @@ __device__ inline double wave_gs_reg(double b, double x, const double* G, int R,
   for (int k = 0; k < RM; ++k)
 #pragma unroll
     for (int r = 0; r < RM; ++r) g[k][r] = (k < R && r < R) ? G[k * R + r] : 0.0;
+  // static indices only (entries r >= R are zero and never change).  Per
+  // iteration the sums over k > r (previous iterate) are formed side by side
+  // first; each new x_r is then added into the pending sums of the later
+  // components (serial chain per component: one product, a subtraction, a scaling)
   for (int it = 0; it < iters; ++it) {
+    double up[RM], lo[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-      if (r >= R) break;
-      if (dinv[r] == 0.0) continue;
-      double t0 = 0.0, t1 = 0.0;
+      double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < RM; ++k) {
-        if (k >= R || k == r) continue;
-        if (k & 1) t1 += xv[k] * g[k][r];
-        else t0 += xv[k] * g[k][r];
-      }
-      xv[r] = (bv[r] - (t0 + t1)) * dinv[r];
+      for (int k = r + 1; k < RM; ++k) t += xv[k] * g[k][r];
+      up[r] = t;
+      lo[r] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+      const double v = (bv[r] - (up[r] + lo[r])) * dinv[r];
+      xv[r] = (r < R && dinv[r] != 0.0) ? v : xv[r];
+#pragma unroll
+      for (int j = r + 1; j < RM; ++j) lo[j] += xv[r] * g[r][j];
     }
   }
   double out = 0.0;
@@ -183,9 +190,15 @@ __device__ inline double wave_gs_reg(double b, double x, const double* G, int R,
 }
 
 __device__ inline double wave_gs_any(double b, double x, const double* G, int R, int iters, int lane) {
-  if (R <= 4) return wave_gs_reg<4>(b, x, G, R, iters, lane);
-  if (R <= 8) return wave_gs_reg<8>(b, x, G, R, iters, lane);
-  return wave_gs(b, x, G, R, iters, lane);
+  switch (R) {
+    case 1: case 2: return wave_gs_reg<2>(b, x, G, R, iters, lane);
+    case 3: return wave_gs_reg<3>(b, x, G, R, iters, lane);
+    case 4: return wave_gs_reg<4>(b, x, G, R, iters, lane);
+    case 5: return wave_gs_reg<5>(b, x, G, R, iters, lane);
+    case 6: return wave_gs_reg<6>(b, x, G, R, iters, lane);
+    case 7: case 8: return wave_gs_reg<8>(b, x, G, R, iters, lane);
+    default: return wave_gs(b, x, G, R, iters, lane);
+  }
 }
 
 // One block of rows of a mode epilogue; blk / nblk: this block's index and the
