@@ -33,7 +33,8 @@ __device__ inline double wg_sum(double v, double* sred) {
 // v_mfma_f64_16x16x4f64 over blocks of 4 rows, lane l supplying row 4b + l/16,
 // column 16t + l%16 as both operands of a diagonal tile (16x16 output tiles
 // (ta, tb), ta <= tb, mirrored).  Wave w takes the row blocks w, w + 4, ...,
-// Q of them per round of loads; the four wave sums are added in wave order.
+// Q of them per round of loads; the four wave sums are added in wave order
+// (W4: 1024 doubles of LDS scratch: one barrier; NULL: a barrier per wave).
 // RMAX <= 16: the diagonal tile only (one accumulator).
 // gram_first_loads issues the first round of tile (0, 0) early (into pre), so
 // that it shares a round trip with other loads; gram_mfma consumes it.
@@ -50,7 +51,7 @@ __device__ inline void gram_first_loads(const double* __restrict__ A, int64_t I,
 
 template <int Q, int RMAX>
 __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R, double* U,
-                                 const double (&pre)[Q]) {
+                                 const double (&pre)[Q], double* W4) {
   typedef double d4v __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -92,20 +93,39 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
           for (int q = 0; q < Q2; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], vb[q], acc, 0, 0, 0);
         }
       }
-      // D(m, n), m = 16 ta + kq + 4 v, n = 16 tb + r16
-      for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
+      if (W4) {
+        // D(m, n), m = 16 ta + kq + 4 v, n = 16 tb + r16: every wave parks its
+        // tile in its own slot of W4 (4 x 256 doubles), one barrier, then the
+        // four tiles are added in wave order
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int m = ta * 16 + kq + 4 * v, n = tb * 16 + r16;
-            if (m < R && n < R) {
-              const double val = w == 0 ? acc[v] : U[m * R + n] + acc[v];
-              U[m * R + n] = val;
-              if (ta != tb) U[n * R + m] = val;
-            }
+        for (int v = 0; v < 4; ++v) W4[wave * 256 + (kq + 4 * v) * 16 + r16] = acc[v];
+        __syncthreads();
+        {
+          const int m16 = tid >> 4, n16 = tid & 15;
+          const int m = ta * 16 + m16, n = tb * 16 + n16;
+          if (m < R && n < R) {
+            const double val = ((W4[tid] + W4[256 + tid]) + W4[512 + tid]) + W4[768 + tid];
+            U[m * R + n] = val;
+            if (ta != tb) U[n * R + m] = val;
           }
         }
         __syncthreads();
+      } else {
+        // the waves add their tiles into U one after the other (no scratch)
+        for (int w = 0; w < 4; ++w) {
+          if (wave == w) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int m = ta * 16 + kq + 4 * v, n = tb * 16 + r16;
+              if (m < R && n < R) {
+                const double val = w == 0 ? acc[v] : U[m * R + n] + acc[v];
+                U[m * R + n] = val;
+                if (ta != tb) U[n * R + m] = val;
+              }
+            }
+          }
+          __syncthreads();
+        }
       }
     }
 }
@@ -209,6 +229,13 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   __shared__ double sred[8];
   __shared__ double sfit[kMaxGroups];
   __shared__ double sfv[kMaxGroups];
+  // Gram scratch (the four wave tiles) only in the standalone kernels (LK = 16):
+  // inside a streaming kernel it would raise every workgroup's LDS and registers
+  double* sW4 = nullptr;
+  if constexpr (LK == 16) {
+    __shared__ double w4[4 * 256];
+    sW4 = w4;
+  }
   const int R = a.R, N = a.N, n = a.n, RR = R * R, tid = threadIdx.x;
   const int NG = a.groups > 1 ? a.groups : 1;
   const int Rg = R / NG;
@@ -236,7 +263,7 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   const double ip0 = (want_f && tid < a.inner_count) ? a.inner_part[(size_t)tid * NG] : 0.0;
   const double nz2 = want_f ? *a.norm2 : 0.0;
   prep_load<LK>(a, sS, sGr);
-  if (a.p >= 0) gram_mfma<GQ, RMAX>(a.Ap, a.Ip, R, U, gpre);
+  if (a.p >= 0) gram_mfma<GQ, RMAX>(a.Ap, a.Ip, R, U, gpre, sW4);
   // the updated factor is normalized (frozen groups kept their columns)
   if (a.p >= 0 && tid < R && !col_frozen(tid)) sS[a.p * R + tid] = 1.0;
   __syncthreads();
