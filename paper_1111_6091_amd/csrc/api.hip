@@ -1443,6 +1443,8 @@ namespace {
 
 // Tensor bytes one streaming workgroup of a batched MTTKRP aims to cover.
 constexpr int64_t kBatchBytesPerWg = 192 * 1024;
+// Mixed form: below this many active problems the FP32-phase ones move to FP64.
+constexpr int kBatchMergeBelow = 64;
 
 struct BatchPhase {           // device arrays of one phase (FP32 or FP64 contractions)
   MttkrpDesc* md = nullptr;   // [(N + 1) * nprob]: set 0 = first sweep of a chunk, mode 0;
@@ -1567,7 +1569,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
     BatchState* stp = c.template take<BatchState>((size_t)nprob);
     BatchRule* ru = c.template take<BatchRule>(2);
     GramJob* jb = c.template take<GramJob>((size_t)nprob * N);
-    int32_t* pl = c.template take<int32_t>((size_t)nprob);
+    int32_t* pl = c.template take<int32_t>((size_t)nprob * 3);
     if (real) { states = stp; rules = ru; jobs = jb; plist = pl; }
     for (int ph = 0; ph < nphase; ++ph) {
       MttkrpDesc* md = c.template take<MttkrpDesc>((size_t)nsets * nprob);
@@ -1609,7 +1611,10 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
     hr[ph].tol64 = prm->tol64;
     hr[ph].max_sweeps = prm->max_sweeps;
   }
-  auto phase_rule = [&](int ph) { return rules + ((mixed && ph == 0) ? 0 : 1); };
+  // rule index of launch phase ph: the mixed form runs FP32 (0) and FP64 (1)
+  // launches, the FP64 form only FP64 (1)
+  auto run_phase = [&](int ph) { return (mixed && ph == 0) ? 0 : 1; };
+  auto phase_rule = [&](int ph) { return rules + run_phase(ph); };
   std::vector<GramJob> hjobs((size_t)nprob * N);
   for (int b = 0; b < nprob; ++b)
     for (int n = 0; n < N; ++n) {
@@ -1653,6 +1658,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
         pa.groups = G;
         pa.st = states + b;
         pa.rule = phase_rule(ph);
+        pa.run_phase = run_phase(ph);
         return pa;
       };
       const void* z = fp32 ? (const void*)pb.z.z32 : (const void*)pb.z.z64;
@@ -1692,6 +1698,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
         d.want_obj = n == N - 1 ? 1 : 0;
         d.groups = G;
         d.st = states + b;
+        d.run_phase = run_phase(ph);
         hed[ph][(size_t)n * nprob + b] = d;
       }
       PrepArgs fa = base(0);
@@ -1713,6 +1720,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
     for (int b = 0; b < nprob; ++b) {
       BatchState& x = hst[b];
       if (first) x = BatchState{};
+      x.phase = mixed ? 0 : 1;
       x.active = 1;
       x.sweep = 0;
       for (int g = 0; g < kMaxGroups; ++g) {
@@ -1747,75 +1755,98 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
   }
   HIPCHK(hipStreamSynchronize(st));   // host arrays may go once the uploads are done
 
-  // ---- phases ------------------------------------------------------------------
+  // ---- sweeps ------------------------------------------------------------------
+  // Each problem moves from the FP32 to the FP64 phase on the device as soon as
+  // all its restarts have left the FP32 phase (batch_rules), so the two phases
+  // of different problems run side by side: every chunk launches the FP32
+  // tiles of the problems in phase 0 and the FP64 tiles of those in phase 1.
+  // Launch lists cover the problems active at the start of a chunk; a problem
+  // that stops (or changes phase) inside a chunk leaves its tiles early.  Few
+  // active problems: longer chunks between host checks (the rules themselves
+  // are applied on the device after every sweep).
   const int kinds[3] = {1, 2, 3};
-  for (int ph = 0; ph < nphase; ++ph) {
-    const bool fp32 = mixed && ph == 0;
-    if (ph > 0) {
-      // the FP64 phase restarts every restart of every problem
-      HIPCHK(hipMemcpy(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost));
-      init_states(1, false);
-      HIPCHK(hipMemcpyAsync(states, hst.data(), hst.size() * sizeof(BatchState), hipMemcpyHostToDevice, st));
-      HIPCHK(hipStreamSynchronize(st));
+  int32_t* plist_ph[2] = {plist + nprob, plist + 2 * (size_t)nprob};
+  std::vector<std::vector<int32_t>> act(nphase);
+  std::vector<int32_t> all;
+  for (int b = 0; b < nprob; ++b) act[0].push_back(b);
+  std::vector<std::vector<std::vector<int2>>> cmt(nsets, std::vector<std::vector<int2>>(2));
+  std::vector<std::vector<int2>> cet(N);
+  // a problem sweeps at most max_sweeps + 1 times and idles for at most one
+  // chunk at its phase change
+  const int64_t max_rounds = 2 * (int64_t)prm->max_sweeps + 16 * (int64_t)prm->chunk + 16;
+  for (int64_t rounds = 0; rounds < max_rounds;) {
+    int na = 0;
+    for (int ph = 0; ph < nphase; ++ph) na += (int)act[ph].size();
+    if (na == 0) break;
+    if (mixed && !act[0].empty() && !act[1].empty() && na <= kBatchMergeBelow) {
+      // few problems left: sweeps cost launches, not bytes, so the problems
+      // still in the FP32 phase go on in FP64 and one set of launches remains
+      for (int bb : act[0]) {
+        BatchState& x = hst[bb];
+        x.phase = 1;
+        x.sweep = 0;
+        x.active = 1;
+        for (int g = 0; g < kMaxGroups; ++g) {
+          x.frozen[g] = g < G ? 0 : 1;
+          x.fit_prev[g] = std::numeric_limits<double>::quiet_NaN();
+        }
+        HIPCHK(hipMemcpyAsync(states + bb, &x, sizeof(BatchState), hipMemcpyHostToDevice, st));
+        act[1].push_back(bb);
+      }
+      act[0].clear();
+      std::sort(act[1].begin(), act[1].end());
     }
-    BatchPhase& d = dp[ph];
-    // Launch lists cover the problems still active at the start of a chunk;
-    // problems that stop inside a chunk leave their tiles early.  Few active
-    // problems: longer chunks between host checks (the rules themselves are
-    // applied on the device after every sweep).
-    std::vector<int32_t> act;
-    std::vector<std::vector<std::vector<int2>>> cmt(nsets, std::vector<std::vector<int2>>(2));
-    std::vector<std::vector<int2>> cet(N);
-    for (int b = 0; b < nprob; ++b) act.push_back(b);
-    for (int done = 0; done < prm->max_sweeps;) {
-      const int na = (int)act.size();
-      int K = na <= 8 ? prm->chunk * 8 : (na <= 64 ? prm->chunk * 2 : prm->chunk);
-      K = std::min(K, prm->max_sweeps - done);
-      if (na < nprob) {
-        std::vector<char> on(nprob, 0);
-        for (int b : act) on[b] = 1;
-        for (int set = 0; set < nsets; ++set)
-          for (int q = 0; q < 2; ++q) {
+    int K = na <= 8 ? prm->chunk * 8 : (na <= 64 ? prm->chunk * 2 : prm->chunk);
+    K = (int)std::min<int64_t>(K, max_rounds - rounds);
+    all.clear();
+    for (int ph = 0; ph < nphase; ++ph) {
+      BatchPhase& d = dp[ph];
+      all.insert(all.end(), act[ph].begin(), act[ph].end());
+      const bool full = (int)act[ph].size() == nprob;
+      std::vector<char> on(nprob, 0);
+      for (int bb : act[ph]) on[bb] = 1;
+      for (int set = 0; set < nsets; ++set)
+        for (int q = 0; q < 2; ++q) {
+          const std::vector<int2>* src = &hp[ph].mt[set][q];
+          if (!full) {
             cmt[set][q].clear();
             for (const int2& t : hp[ph].mt[set][q])
               if (on[t.x % nprob]) cmt[set][q].push_back(t);
-            d.mcount[set][q] = (int)cmt[set][q].size();
-            if (!cmt[set][q].empty())
-              HIPCHK(hipMemcpyAsync(d.mtiles[set][q], cmt[set][q].data(), cmt[set][q].size() * sizeof(int2),
-                                    hipMemcpyHostToDevice, st));
+            src = &cmt[set][q];
           }
-        for (int n = 0; n < N; ++n) {
+          d.mcount[set][q] = (int)src->size();
+          if (!src->empty())
+            HIPCHK(hipMemcpyAsync(d.mtiles[set][q], src->data(), src->size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, st));
+        }
+      for (int n = 0; n < N; ++n) {
+        const std::vector<int2>* src = &hp[ph].et[n];
+        if (!full) {
           cet[n].clear();
           for (const int2& t : hp[ph].et[n])
             if (on[t.x % nprob]) cet[n].push_back(t);
-          d.ecount[n] = (int)cet[n].size();
-          if (!cet[n].empty())
-            HIPCHK(hipMemcpyAsync(d.etiles[n], cet[n].data(), cet[n].size() * sizeof(int2),
-                                  hipMemcpyHostToDevice, st));
+          src = &cet[n];
         }
-      } else {
-        for (int set = 0; set < nsets; ++set)
-          for (int q = 0; q < 2; ++q) {
-            d.mcount[set][q] = (int)hp[ph].mt[set][q].size();
-            if (!hp[ph].mt[set][q].empty())
-              HIPCHK(hipMemcpyAsync(d.mtiles[set][q], hp[ph].mt[set][q].data(),
-                                    hp[ph].mt[set][q].size() * sizeof(int2), hipMemcpyHostToDevice, st));
-          }
-        for (int n = 0; n < N; ++n) {
-          d.ecount[n] = (int)hp[ph].et[n].size();
-          if (!hp[ph].et[n].empty())
-            HIPCHK(hipMemcpyAsync(d.etiles[n], hp[ph].et[n].data(), hp[ph].et[n].size() * sizeof(int2),
-                                  hipMemcpyHostToDevice, st));
-        }
+        d.ecount[n] = (int)src->size();
+        if (!src->empty())
+          HIPCHK(hipMemcpyAsync(d.etiles[n], src->data(), src->size() * sizeof(int2), hipMemcpyHostToDevice, st));
       }
-      HIPCHK(hipMemcpyAsync(plist, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-      {
-        ProfScope ps(ctx, CP_PROF_GRAM);
-        HIPCHK(gram_batched_launch(jobs, plist, na, N, st));
-      }
-      for (int k = 0; k < K; ++k)
-        for (int n = 0; n < N; ++n) {
-          const int set = (k == 0 && n == 0) ? 0 : n + 1;
+      if (!act[ph].empty())
+        HIPCHK(hipMemcpyAsync(plist_ph[ph], act[ph].data(), act[ph].size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(plist, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    {
+      ProfScope ps(ctx, CP_PROF_GRAM);
+      HIPCHK(gram_batched_launch(jobs, plist, na, N, st));
+    }
+    for (int k = 0; k < K; ++k)
+      for (int n = 0; n < N; ++n) {
+        const int set = (k == 0 && n == 0) ? 0 : n + 1;
+        for (int ph = 0; ph < nphase; ++ph) {
+          if (act[ph].empty()) continue;
+          BatchPhase& d = dp[ph];
+          const bool fp32 = mixed && ph == 0;
           {
             ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + kinds[std::min(n, 2)] - 1);
             for (int q = 0; q < 2; ++q)
@@ -1825,18 +1856,18 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
           ProfScope ps(ctx, CP_PROF_UPDATE);
           HIPCHK(epi_batched_launch(d.ed, d.etiles[n], d.ecount[n], st));
         }
-      {
-        ProfScope ps(ctx, CP_PROF_NORMALIZE);
-        HIPCHK(finalize_batched_launch(d.fin, plist, na, smem_fin, st));
       }
-      done += K;
-      HIPCHK(hipMemcpyAsync(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));   // also retires the host tile lists uploaded above
-      act.clear();
-      for (int b = 0; b < nprob; ++b)
-        if (hst[b].active) act.push_back(b);
-      if (act.empty()) break;
+    for (int ph = 0; ph < nphase; ++ph) {
+      if (act[ph].empty()) continue;
+      ProfScope ps(ctx, CP_PROF_NORMALIZE);
+      HIPCHK(finalize_batched_launch(dp[ph].fin, plist_ph[ph], (int)act[ph].size(), smem_fin, st));
     }
+    rounds += K;
+    HIPCHK(hipMemcpyAsync(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));   // also retires the host tile lists uploaded above
+    for (int ph = 0; ph < nphase; ++ph) act[ph].clear();
+    for (int bb = 0; bb < nprob; ++bb)
+      if (hst[bb].active) act[mixed ? hst[bb].phase : 0].push_back(bb);
   }
 
   // ---- outputs -------------------------------------------------------------------

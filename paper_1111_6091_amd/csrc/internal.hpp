@@ -55,6 +55,7 @@ struct BatchRule {
 };
 
 struct BatchState {
+  int32_t phase;                  // rule the problem is under: 0 FP32 window rule, 1 FP64 rule
   int32_t active;                 // some group still iterates in the current phase
   int32_t sweep;                  // sweeps completed in the current phase
   int32_t frozen[kMaxGroups];     // group stopped in the current phase
@@ -100,6 +101,7 @@ struct PrepArgs {
   int32_t groups;           // column groups (independent restarts); 0 or 1: one group
   BatchState* st;           // batched solves: stopping state (NULL otherwise)
   const BatchRule* rule;
+  int32_t run_phase;        // batched solves: the phase (rule index) this launch runs
   int32_t lds;              // doubles of LDS the launch provides (set by the launchers)
 };
 
@@ -224,6 +226,7 @@ struct EpiDesc {
   double* scal_part;          // [nwg] workspace (x groups for EPI_UPDATE with want_obj)
   int32_t groups;             // EPI_UPDATE: column groups (0 or 1: one group)
   const BatchState* st;       // EPI_UPDATE in a batched solve: skip frozen groups
+  int32_t run_phase;          // ... and problems not in this launch's phase
   int32_t* counter;           // last-block counter (zero between launches)
   double* scalar_out;         // objective: f_hist slot; grad: accumulator
   const double* norm2;        // ||Z||^2 (device)

@@ -18,7 +18,7 @@ void mttkrp_batched(const MttkrpDesc* __restrict__ descs, const int2* __restrict
   extern __shared__ double smem[];
   const int2 t = tiles[blockIdx.x];
   const MttkrpDesc& d = descs[t.x];
-  if (d.pa.st && !d.pa.st->active) return;
+  if (d.pa.st && (!d.pa.st->active || d.pa.st->phase != d.pa.run_phase)) return;
   if (KIND == 1) {
     if (d.vec) kind1_body<T, NT, 4, true, true, true>(d, t.y, smem);
     else kind1_body<T, NT, 4, false, true, true>(d, t.y, smem);

@@ -205,6 +205,17 @@ __device__ inline void batch_rules(BatchState* st, const BatchRule& ru, const do
   }
   st->sweep = idx + 1;
   st->active = any ? 1 : 0;
+  if (!any && ru.phase == 0) {
+    // every restart left the FP32 phase: the problem goes on with FP64 sweeps
+    // at once (every restart at least one, then the FP64 rule and the cap)
+    st->phase = 1;
+    st->sweep = 0;
+    for (int g = 0; g < NG; ++g) {
+      st->frozen[g] = 0;
+      st->fit_prev[g] = __builtin_nan("");
+    }
+    st->active = 1;
+  }
 }
 
 // End of a sweep, by one thread: the objective values into the history and the
@@ -240,7 +251,7 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   const int NG = a.groups > 1 ? a.groups : 1;
   const int Rg = R / NG;
   BatchState* st = a.st;
-  const bool active = !st || st->active;
+  const bool active = !st || (st->active && st->phase == a.run_phase);
   if (!active && !finalize) return;   // nothing left to do in this phase
   auto col_frozen = [&](int r) -> bool { return st && st->frozen[r / Rg]; };
   double* G = smem;

@@ -210,7 +210,8 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
   __shared__ double sC[2 * kMaxRank];
   __shared__ double sred[8];
   __shared__ int s_flag;
-  if (d.st && !d.st->active) return;   // batched solve: nothing left in this phase
+  // batched solve: nothing left in this phase, or the problem is in the other phase
+  if (d.st && (!d.st->active || d.st->phase != d.run_phase)) return;
   const int R = d.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blk * EPI_ROWS;
