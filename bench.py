@@ -84,6 +84,9 @@ def parse():
     p.add_argument("--mttkrp-only", action="store_true",
                    help="launch each MTTKRP kernel --steps times and a 64 MiB device copy "
                         "(byte-counter calibration), then exit; for profiler runs")
+    p.add_argument("--vcycles-only", action="store_true",
+                   help="time CP-FAS V-cycles on the 128^3 R=5 4-level hierarchy (FP64 and mixed, graph "
+                        "replay off and on), then exit; for profiler runs")
     p.add_argument("--sweeps-only", action="store_true",
                    help="time the mixed and FP64 sweeps only, then exit; for profiler runs")
     p.add_argument("--cold", action="store_true",
@@ -154,6 +157,9 @@ def main():
     torch.cuda.set_device(0)
     ctx = api.Context()
     K, W = args.steps, args.warmup
+    if args.vcycles_only:
+        vcycle_timing(ctx, api, drivers, synth)
+        return
     Z, _, spec = synth.workload(args.workload)
     dims, R = tuple(spec["dims"]), spec["R"]
     A0 = synth.uniform_start(dims, R, spec["seed"])
@@ -464,6 +470,38 @@ def fas_leg(ctx, api, drivers, synth):
         out["als"]["rel_fit_err_vs_oracle"] = abs(fit_als - g["als_fit"]) / abs(g["als_fit"])
     log(f"128^3 FAS: {r.sweeps} V-cycles in {tf:.3f} s ({1e3 * tf / r.sweeps:.2f} ms/cycle), fit {r.final_fit:.13f}; "
         f"ALS: {ra.sweeps} sweeps in {ta:.3f} s, fit {fit_als:.13f}")
+    return out
+
+
+def vcycle_timing(ctx, api, drivers, synth, cycles=50):
+    """ms per CP-FAS V-cycle on the 128^3 R=5 4-level hierarchy of the oracle's
+    setup phase, FP64 and mixed, with the graph replay off and on (one untimed
+    cycle first in each case)."""
+    import numpy as np
+    import torch
+    from paper_1111_6091_amd._lib import CP_FP64, CP_MIXED, CP_OPT_GRAPHS
+    with open(os.path.join(HERE, "tests", "golden", "fas_c2_128cube_r5.json")) as f:
+        g = json.load(f)
+    Z, _, spec = synth.workload("c2_128cube_r5")
+    Zd = api.DeviceTensor.from_numpy(ctx, Z, fp32=True)
+    weights = [[None if w is None else np.asarray(w) for w in lv] for lv in g["weights"]]
+    levels = drivers.build_hierarchy(ctx, Zd, weights, prec=CP_MIXED, fp32=True, fp64=True)
+    A0 = [np.asarray(a) for a in g["A_setup"]]
+    out = {}
+    for graphs in (0, 1):
+        ctx.set_option(CP_OPT_GRAPHS, graphs)
+        for prec, tag in ((CP_FP64, "fp64"), (CP_MIXED, "mixed")):
+            A = api.DeviceFactors.from_numpy(ctx, A0, fp32=True)
+            api.cp_fas_vcycle(ctx, levels, A, prec=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(cycles):
+                api.cp_fas_vcycle(ctx, levels, A, prec=prec)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / cycles * 1e3
+            out[f"{tag}_graphs{graphs}"] = round(ms, 3)
+            log(f"V-cycle {tag}, graph replay {graphs}: {ms:.3f} ms")
+    ctx.set_option(CP_OPT_GRAPHS, 1)
     return out
 
 
