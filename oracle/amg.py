@@ -12,7 +12,9 @@ Readings of the paper taken here (each one is listed in the design notes):
 * Coarse Gram of Sec. 4.1 is read as A_c^T B A_c (the printed formula mixes
   A_c and A, which is dimensionally impossible).
 * Least-squares weights eq. (20) use the gradient of each block at its current
-  iterate (after the nu_1 relaxations); ||G|| is clamped to 1e-300.
+  iterate (after the nu_1 relaxations); ||G^(n)|| is floored at
+  1e-8 ||Z_(n) Phi^(n)|| (the mode an ALS sweep solved last has a gradient that
+  vanishes identically, so its computed value is rounding noise).
 * Coarse right-hand side for modes that are not coarsened: Algorithm 2 writes
   F_c = F, which loses the FAS fixed point unless A lies in range(P) for every
   other mode; the default here is the tau-corrected form
@@ -92,10 +94,23 @@ def ls_interp_weights(U, wts):
     return w
 
 
+# ||G^(n)|| below this fraction of ||Z_(n) Phi^(n)|| is taken at that level
+GRAD_FLOOR = 1e-8
+
+
 def block_weight(Z, A, n):
-    """w_r = ||A^(n)||^2 / ||G^(n)||^2 for one block of factor matrices, eq. (20)."""
-    G = cp.gradient(Z, A)[n]
-    gn2 = max(float(np.sum(G * G)), 1e-300 ** 2)
+    """w_r = ||A^(n)||^2 / ||G^(n)||^2 for one block of factor matrices, eq. (20),
+    G^(n) = A^(n) Gamma^(n) - Z_(n) Phi^(n) (eq. (6)).
+
+    After an ALS sweep the gradient of the mode solved last vanishes identically
+    (the update solves G^(n) = 0 and the rescaling of eq. (10) keeps it zero), so
+    its computed norm is rounding noise and the ratio would be arbitrary.  The
+    norm is therefore floored at GRAD_FLOOR * ||Z_(n) Phi^(n)||, far below any
+    gradient the setup phase acts on and far above rounding.
+    """
+    M = cp.mttkrp(Z, A, n)
+    G = A[n] @ cp.gamma(cp.grams(A), n) - M
+    gn2 = max(float(np.sum(G * G)), GRAD_FLOOR * GRAD_FLOOR * float(np.sum(M * M)))
     return float(np.sum(A[n] * A[n])) / gn2
 
 

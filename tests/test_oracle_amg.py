@@ -136,7 +136,25 @@ def test_block_weight_definition():
     A = [rng.standard_normal((d, 2)) for d in (4, 5, 6)]
     G = cp.gradient(Z, A)
     for n in range(3):
-        assert amg.block_weight(Z, A, n) == pytest.approx(np.sum(A[n] ** 2) / np.sum(G[n] ** 2), rel=1e-14)
+        assert amg.block_weight(Z, A, n) == pytest.approx(np.sum(A[n] ** 2) / np.sum(G[n] ** 2), rel=1e-12)
+
+
+def test_block_weight_floor_after_an_als_sweep():
+    """After an ALS sweep the last mode's gradient vanishes identically (its
+    computed norm is rounding noise): the weight takes the floor
+    ||A||^2 / (1e-8 ||M||)^2 whatever the rounding; the other modes keep their
+    true gradients."""
+    from paper_1111_6091_amd import synth
+    Z, _ = synth.collinear_tensor((9, 8, 7), 2, 0.5, 0.05, 0.0, seed=3)
+    A = cp.als_sweep(Z, synth.uniform_start((9, 8, 7), 2, 3))
+    G = cp.gradient(Z, A)
+    M2 = cp.mttkrp(Z, A, 2)
+    assert np.linalg.norm(G[2]) < 1e-12 * np.linalg.norm(M2)
+    w2 = amg.block_weight(Z, A, 2)
+    assert w2 == pytest.approx(np.sum(A[2] ** 2) / (amg.GRAD_FLOOR ** 2 * np.sum(M2 ** 2)), rel=1e-12)
+    for n in (0, 1):
+        assert np.linalg.norm(G[n]) > 1e-6 * np.linalg.norm(cp.mttkrp(Z, A, n))
+        assert amg.block_weight(Z, A, n) == pytest.approx(np.sum(A[n] ** 2) / np.sum(G[n] ** 2), rel=1e-12)
 
 
 def test_fas_operator_is_gradient():
