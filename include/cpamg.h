@@ -226,6 +226,24 @@ cp_status cp_prolong(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const double*
 cp_status cp_restrict_factor(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const double* phat,
                              const double* A, double* Ac);
 
+/* Least-squares interpolation weights of the setup phase (Section 4.4,
+ * eqs. (19)-(20); Algorithm 1 step 3) for mode n.  A holds `groups` factor
+ * sets side by side as column groups (group k: columns [k R_g, (k+1) R_g) of
+ * every factor, R_g = A->rank / groups): the relaxed test blocks and, last,
+ * the boot factors.  Groups 0..nfit-1 are fitted, group k with weight
+ * ||A_k^(n)||^2 / ||G_k^(n)||^2 for the gradient G_k^(n) = A_k^(n) Gamma_k^(n) -
+ * M_k^(n), M_k^(n) = Z_(n) Phi_k^(n), of f at that block (eq. (23)); ||G_k^(n)|| is
+ * floored at 1e-8 ||M_k^(n)|| (the mode an ALS sweep solved last has a gradient
+ * that vanishes identically: its computed norm is rounding noise).  For every fine point i (odd
+ * 0-based index) w[i][0], w[i][1] (I_n x 2 row-major, device) are the weights of
+ * the coarse points (i-1)/2 and (i+1)/2 (the latter absent at the right end of
+ * an even extent: w[i][1] = 0) minimizing the weighted misfit of every fitted
+ * column at i against its injected values at i - 1 and i + 1; rows of coarse
+ * points are zero.  The output feeds cp_transfer_build.  FP64 (Z->z64).
+ * Errors: bad group split, nfit outside [1, groups], mode extent < 2. */
+cp_status cp_interp_weights(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t groups,
+                            int32_t nfit, int32_t n, double* w);
+
 /* Transfer operator of Section 4.1 / Algorithm 1 steps 4-6 for geometric
  * coarsening (Section 4.3): from per-row weights w (I x 2; row i odd (0-based)
  * interpolates from coarse points (i-1)/2 and (i+1)/2 with weights w[i][0],

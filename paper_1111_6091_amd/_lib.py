@@ -93,6 +93,8 @@ SIGNATURES = {
     "cp_prolong": [c_vp, c_i64, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp],
     "cp_restrict_factor": [c_vp, c_i64, c_i64, c_i32, c_vp, c_vp, c_vp],
     "cp_transfer_build": [c_vp, c_i64, c_vp, c_vp],
+    "cp_interp_weights": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_i32, c_i32,
+                          c_vp],
     "cp_fas_vcycle": [c_vp, ctypes.POINTER(CpLevel), c_i32, ctypes.POINTER(CpFactors),
                       ctypes.POINTER(CpFasParams), c_i32],
     "cp_sort": [c_vp, ctypes.POINTER(c_i64), c_i32, ctypes.POINTER(CpFactors)],

@@ -243,6 +243,12 @@ def cp_restrict_factor(ctx, phat, A, Ac):
     ctx.check(ctx._lib.cp_restrict_factor(ctx.handle, I, Ic, R, _ptr(phat), _ptr(A), _ptr(Ac)))
 
 
+def cp_interp_weights(ctx, Z, A, groups, nfit, n, w):
+    zs, fs = Z.struct(), A.struct()
+    ctx.check(ctx._lib.cp_interp_weights(ctx.handle, ctypes.byref(zs), ctypes.byref(fs), int(groups),
+                                         int(nfit), int(n), _ptr(w)))
+
+
 def cp_transfer_build(ctx, w, phat):
     I = w.shape[0]
     ctx.check(ctx._lib.cp_transfer_build(ctx.handle, I, _ptr(w), _ptr(phat)))

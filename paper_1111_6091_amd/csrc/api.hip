@@ -919,6 +919,54 @@ cp_status cp_restrict_factor(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const
   return CP_OK;
 }
 
+cp_status cp_interp_weights(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t groups,
+                            int32_t nfit, int32_t n, double* w) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_tensor(ctx, Z, true, false, "Z");
+  if (s != CP_OK) return s;
+  const int N = Z->order;
+  if ((s = check_factors(ctx, A, N, false, "A")) != CP_OK) return s;
+  if (groups < 1 || groups > kMaxGroups || A->rank % groups != 0)
+    return set_err(ctx, CP_ERR_INVALID, "cp_interp_weights: %d groups do not split rank %d (at most %d groups)",
+                   groups, A->rank, kMaxGroups);
+  if (nfit < 1 || nfit > groups)
+    return set_err(ctx, CP_ERR_INVALID, "cp_interp_weights: nfit %d outside [1, %d]", nfit, groups);
+  if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_interp_weights: mode %d outside [0, %d)", n, N);
+  if (Z->dims[n] < 2) return set_err(ctx, CP_ERR_SHAPE, "cp_interp_weights: mode %d has extent < 2", n);
+  if (!w) return set_err(ctx, CP_ERR_INVALID, "cp_interp_weights: w is NULL");
+  const int Rt = A->rank;
+  const int64_t In = Z->dims[n];
+  const MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, Rt, false);
+  Sizer sz;
+  sz.take<double>((size_t)N * Rt * Rt);
+  sz.take<double>((size_t)In * Rt);
+  sz.take<double>(plan.partial_doubles);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  double* grams = ar.take<double>((size_t)N * Rt * Rt);
+  double* M = ar.take<double>((size_t)In * Rt);
+  double* part = ar.take<double>(plan.partial_doubles);
+  TRY(enqueue_gram(ctx, A->a, nullptr, Z->dims, N, Rt, grams));
+  if (plan.nsplit == 1) {
+    TRY(enqueue_mttkrp(ctx, Z->dims, N, n, Rt, Z->z64, false, A->a, nullptr, plan, M));
+  } else {
+    TRY(enqueue_mttkrp(ctx, Z->dims, N, n, Rt, Z->z64, false, A->a, nullptr, plan, part));
+    EpiDesc d{};
+    d.op = EPI_STORE_M;
+    d.R = Rt;
+    d.N = N;
+    d.n = n;
+    d.nsplit = plan.nsplit;
+    d.In = In;
+    d.partial = part;
+    d.outbuf = M;
+    TRY(enqueue_epi(ctx, d));
+  }
+  ProfScope ps(ctx, CP_PROF_OTHER);
+  HIPCHK(interp_weights_launch(A->a[n], M, grams, N, n, In, Rt, Rt / groups, nfit, w, ctx->stream));
+  return CP_OK;
+}
+
 cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat) {
   if (!ctx) return CP_ERR_INVALID;
   if (!w || !phat) return set_err(ctx, CP_ERR_INVALID, "cp_transfer_build: NULL pointer");

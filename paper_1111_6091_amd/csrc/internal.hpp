@@ -298,6 +298,11 @@ bool small_eligible(const SmallDesc& d, bool fp32);
 size_t small_lds_bytes(const SmallDesc& d, bool fp32);
 hipError_t relax_small_launch(const SmallDesc& d, bool fp32, hipStream_t st);
 
+// LS interpolation weights of one mode from the column groups of a factor set
+// (setup.hip): A, M (I x Rt), Grams of the set, fitted groups 0..nfit-1 of Rg columns.
+hipError_t interp_weights_launch(const double* A, const double* M, const double* grams, int N, int n,
+                                 int64_t I, int Rt, int Rg, int nfit, double* w, hipStream_t st);
+
 // utilities
 hipError_t cast_launch(const double* src, float* dst, int64_t count, hipStream_t st);
 hipError_t norm2_launch(const double* z, int64_t count, double* part, int32_t* counter,

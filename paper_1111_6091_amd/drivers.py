@@ -215,3 +215,213 @@ def fas_solve(ctx, levels, Z, A, fit_tol=1e-12, max_cycles=500, nu1=1, nu2=1, nu
         prev = fit
     res.final_fit = res.fits[-1] if res.fits else float("nan")
     return res
+
+
+# ---------------------------------------------------------------------------
+# Setup phase (Section 4, Algorithm 1), FMG (Algorithm 3) and the Section 6.1
+# driver.  Every numeric step is a libcpamg call; the host recurses over the
+# levels, packs factor sets side by side (device copies) and applies the
+# stopping rules.
+# ---------------------------------------------------------------------------
+SETUP_NU1, SETUP_NU2, SETUP_NUC = 5, 5, 100   # Table 1
+
+
+def grad_norm(ctx, Z, A):
+    """g of eq. (30) at A (device call, read back)."""
+    torch = _torch()
+    g = torch.zeros(1, dtype=torch.float64, device=Z.z64.device)
+    api.cp_objective(ctx, Z, A, exact=True, g=g)
+    return float(g.item())
+
+
+def _pack(sets):
+    """One factor set holding `sets` (equal rank) side by side as column groups."""
+    torch = _torch()
+    mats = [torch.cat([s.mats[n] for s in sets], dim=1).contiguous() for n in range(len(sets[0].mats))]
+    return api.DeviceFactors(mats)
+
+
+def _unpack(packed, k, R, dst):
+    for n, m in enumerate(dst.mats):
+        m.copy_(packed.mats[n][:, k * R:(k + 1) * R])
+
+
+def _relax_groups(ctx, Z, sets, sweeps):
+    """`sweeps` ALS sweeps (Section 3, normalized, eq. (10)) on each factor set,
+    all sets sharing every pass over Z as column groups (cp_als_batched)."""
+    if sweeps <= 0 or not sets:
+        return
+    R = sets[0].rank
+    P = _pack(sets)
+    api.cp_als_batched(ctx, [(Z, P)], len(sets), prec=CP_FP64, tol64=0.0, max_sweeps=sweeps, chunk=sweeps)
+    for k, s in enumerate(sets):
+        _unpack(P, k, R, s)
+
+
+def _level_weights(ctx, Z, fit_sets, Ic):
+    """LS weights (device, cp_interp_weights) and P^ (cp_transfer_build) of every
+    coarsened mode from the column groups `fit_sets`."""
+    torch = _torch()
+    P = _pack(fit_sets)
+    phat, weights = [None] * Z.order, [None] * Z.order
+    for n in Ic:
+        d = Z.dims[n]
+        w = torch.empty((d, 2), dtype=torch.float64, device=Z.z64.device)
+        api.cp_interp_weights(ctx, Z, P, len(fit_sets), len(fit_sets), n, w)
+        ph = torch.empty((d, (d + 1) // 2), dtype=torch.float64, device=w.device)
+        api.cp_transfer_build(ctx, w, ph)
+        phat[n], weights[n] = ph, w
+    return phat, weights
+
+
+def _restrict_tensor(ctx, Z, phat):
+    cdims = tuple((d + 1) // 2 if phat[n] is not None else d for n, d in enumerate(Z.dims))
+    Zc = api.DeviceTensor.empty(cdims, fp64=True)
+    api.cp_restrict(ctx, Z, phat, Zc, CP_FP64)
+    torch = _torch()
+    Zc.norm2 = torch.zeros(1, dtype=torch.float64, device=Z.z64.device)
+    api.cp_norm2(ctx, Zc, Zc.norm2)
+    return Zc
+
+
+def _restrict_factors(ctx, phat, A):
+    """A~_c^(n) = R^^(n) A^(n) (eq. (21)); a copy for modes that are not coarsened."""
+    torch = _torch()
+    mats = []
+    for n, a in enumerate(A.mats):
+        if phat[n] is None:
+            mats.append(a.clone())
+        else:
+            out = torch.empty(((a.shape[0] + 1) // 2, a.shape[1]), dtype=torch.float64, device=a.device)
+            api.cp_restrict_factor(ctx, phat[n], a, out)
+            mats.append(out)
+    return api.DeviceFactors(mats)
+
+
+def _prolong_into(ctx, phat, Ac, A):
+    """A^(n) = P^^(n) A_c^(n) (eq. (22)); a copy for modes that are not coarsened."""
+    for n, (ac, a) in enumerate(zip(Ac.mats, A.mats)):
+        if phat[n] is None:
+            a.copy_(ac)
+        else:
+            api.cp_prolong(ctx, phat[n], ac, None, a)
+
+
+def _coarsened(Z, coarsest):
+    return [n for n, d in enumerate(Z.dims) if d > coarsest[n]]
+
+
+def mult_vcycle(ctx, Z, A, tfms, coarsest, first_cycle, nu1=SETUP_NU1, nu2=SETUP_NU2, nuc=SETUP_NUC,
+                levels_out=None, weights_out=None):
+    """Algorithm 1 (CP-AMG-mult) from level Z: nu1 ALS sweeps on every TFM block
+    and on the BFMs (one multi-block pass per sweep), LS weights from the TFMs
+    (and, after the first cycle, the BFMs), P^ of every coarsened mode, the
+    coarse tensor and restricted blocks, recursion, coarse-grid correction
+    A = P^ A^_c and nu2 ALS sweeps.  On the coarsest level: nuc ALS sweeps on
+    the BFMs.  A (BFMs) and the fine TFMs are updated in place; returns the level
+    list [(tensor, phat per mode)] for cp_fas_vcycle (finest first)."""
+    if levels_out is None:
+        levels_out, weights_out = [], []
+    N = Z.order
+    Ic = _coarsened(Z, coarsest)
+    if not Ic:
+        api.cp_als_sweep(ctx, Z, A, None, nuc, CP_SOLVE_CHOL, 10, True, CP_FP64)
+        levels_out.append((Z, [None] * N))
+        weights_out.append([None] * N)
+        return levels_out, weights_out
+    _relax_groups(ctx, Z, list(tfms) + [A], nu1)
+    phat, weights = _level_weights(ctx, Z, list(tfms) + ([] if first_cycle else [A]), Ic)
+    levels_out.append((Z, phat))
+    weights_out.append(weights)
+    Zc = _restrict_tensor(ctx, Z, phat)
+    Ac = _restrict_factors(ctx, phat, A)
+    tfms_c = [_restrict_factors(ctx, phat, T) for T in tfms]
+    mult_vcycle(ctx, Zc, Ac, tfms_c, coarsest, first_cycle, nu1, nu2, nuc, levels_out, weights_out)
+    _prolong_into(ctx, phat, Ac, A)
+    api.cp_als_sweep(ctx, Z, A, None, nu2, CP_SOLVE_CHOL, 10, True, CP_FP64)
+    return levels_out, weights_out
+
+
+def setup_phase(ctx, Z, A, tfms, coarsest, max_cycles=5, check_after=3, eps=0.1, **mult):
+    """Setup cycles of Section 6.1: Algorithm 1 cycles until g_new > (1 - eps) g_old
+    (eq. (32)), checked once `check_after` cycles have completed, at most
+    `max_cycles`.  A and the TFMs are updated in place.  Returns (levels, weights,
+    g history)."""
+    g_old = grad_norm(ctx, Z, A)
+    levels = weights = None
+    hist = []
+    for c in range(max_cycles):
+        levels, weights = mult_vcycle(ctx, Z, A, tfms, coarsest, first_cycle=(c == 0), **mult)
+        g_new = grad_norm(ctx, Z, A)
+        hist.append(g_new)
+        if c + 1 >= check_after and g_new > (1.0 - eps) * g_old:
+            break
+        g_old = g_new
+    return levels, weights, hist
+
+
+def down_sweep(ctx, Z, A_boot, tfms, coarsest, nu1=SETUP_NU1, use_bfm=True):
+    """Downward half of Algorithm 1 (the rebuild of Section 6.1): the TFMs are
+    relaxed (nu1 ALS sweeps per level), the boot factors only restricted, and
+    the transfer operators rebuilt.  The fine TFMs are updated in place; the boot
+    factors are left unchanged.  Returns (levels, weights)."""
+    levels, weights = [], []
+    cur, B, T = Z, A_boot, list(tfms)
+    while True:
+        N = cur.order
+        Ic = _coarsened(cur, coarsest)
+        if not Ic:
+            levels.append((cur, [None] * N))
+            weights.append([None] * N)
+            break
+        _relax_groups(ctx, cur, T, nu1)   # on the finest level: the caller's TFMs, in place
+        phat, w = _level_weights(ctx, cur, T + ([B] if use_bfm else []), Ic)
+        levels.append((cur, phat))
+        weights.append(w)
+        B = _restrict_factors(ctx, phat, B)
+        T = [_restrict_factors(ctx, phat, t) for t in T]
+        cur = _restrict_tensor(ctx, cur, phat)
+    return levels, weights
+
+
+def fmg_cycle(ctx, levels, A_coarse, nu=SETUP_NUC, **fas):
+    """Algorithm 3 (FMG-CP-FAS): nu ALS sweeps on the coarsest level from
+    A_coarse, then, level by level towards the finest, A = P^ A_c and one CP-FAS
+    V-cycle with F = 0 from that level.  Returns the finest-level factors."""
+    L = len(levels)
+    A = A_coarse
+    api.cp_als_sweep(ctx, levels[L - 1][0], A, None, nu, CP_SOLVE_CHOL, 10, True, CP_FP64)
+    torch = _torch()
+    for l in range(L - 1, 0, -1):
+        Zf, phat = levels[l - 1]
+        Af = api.DeviceFactors([torch.empty((d, A.rank), dtype=torch.float64, device=A.mats[0].device)
+                                for d in Zf.dims])
+        _prolong_into(ctx, phat, A, Af)
+        api.cp_fas_vcycle(ctx, levels[l - 1:], Af, **fas)
+        A = Af
+    return A
+
+
+def solve_phase(ctx, Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500, stagnation_after=5,
+                nu1_setup=SETUP_NU1, **fas):
+    """Solve cycles of Section 6.1: CP-FAS V-cycles until g < tau; once five
+    cycles have completed, a cycle with g_new >= g_old is discarded and the
+    transfer operators are rebuilt by one down-sweep from the previous iterate
+    (once).  A is updated in place.  Returns (levels, g history, rebuilt)."""
+    g_old = grad_norm(ctx, Z, A)
+    rebuilt = False
+    hist = []
+    for c in range(max_cycles):
+        An = A.clone()
+        api.cp_fas_vcycle(ctx, levels, An, **fas)
+        g_new = grad_norm(ctx, Z, An)
+        if c + 1 > stagnation_after and g_new >= g_old and not rebuilt:
+            levels, _ = down_sweep(ctx, Z, A, tfms, coarsest, nu1=nu1_setup)
+            rebuilt = True
+            continue
+        _copy_factors(A, An)
+        g_old = g_new
+        hist.append(g_new)
+        if g_new < tau:
+            break
+    return levels, hist, rebuilt
