@@ -87,6 +87,10 @@ def parse():
     p.add_argument("--vcycles-only", action="store_true",
                    help="time CP-FAS V-cycles on the 128^3 R=5 4-level hierarchy (FP64 and mixed, graph "
                         "replay off and on), then exit; for profiler runs")
+    p.add_argument("--no-dense", action="store_true",
+                   help="skip the dense (i^2+j^2+k^2)^(-1/2) Multilevel + FMG vs ALS leg")
+    p.add_argument("--dense-only", action="store_true",
+                   help="run only the dense Multilevel + FMG vs ALS leg and print its JSON")
     p.add_argument("--sweeps-only", action="store_true",
                    help="time the mixed and FP64 sweeps only, then exit; for profiler runs")
     p.add_argument("--cold", action="store_true",
@@ -159,6 +163,9 @@ def main():
     K, W = args.steps, args.warmup
     if args.vcycles_only:
         vcycle_timing(ctx, api, drivers, synth)
+        return
+    if args.dense_only:
+        print(json.dumps({"dense_table4": dense_leg(ctx, api, drivers, synth)}), flush=True)
         return
     Z, _, spec = synth.workload(args.workload)
     dims, R = tuple(spec["dims"]), spec["R"]
@@ -383,6 +390,9 @@ def main():
     if not args.no_multilevel:
         multilevel = fas_leg(ctx, api, drivers, synth)
         order4 = order4_leg(ctx, api, drivers, synth, K)
+    dense = None
+    if not args.no_dense:
+        dense = dense_leg(ctx, api, drivers, synth)
 
     cpu = None
     if not args.no_cpu:
@@ -422,6 +432,7 @@ def main():
         "batched": batched,
         "multilevel_128cube_r5": multilevel,
         "order4_64quart_r8": order4,
+        "dense_table4": dense,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -470,6 +481,65 @@ def fas_leg(ctx, api, drivers, synth):
         out["als"]["rel_fit_err_vs_oracle"] = abs(fit_als - g["als_fit"]) / abs(g["als_fit"])
     log(f"128^3 FAS: {r.sweeps} V-cycles in {tf:.3f} s ({1e3 * tf / r.sweeps:.2f} ms/cycle), fit {r.final_fit:.13f}; "
         f"ALS: {ra.sweeps} sweeps in {ta:.3f} s, fit {fit_als:.13f}")
+    return out
+
+
+# Table 4 (dense problem, averages over the paper's successful runs; MATLAB on a
+# 2.5 GHz Core 2 Duo): test -> ALS iterations, ALS seconds, Multilevel + FMG
+# iterations, seconds, levels.
+TABLE4 = {2: dict(als_it=2435, als_s=11.8, ml_it=15, ml_s=2.7, levs=5),
+          6: dict(als_it=1695, als_s=80.2, ml_it=9, ml_s=8.1, levs=6)}
+
+
+def dense_leg(ctx, api, drivers, synth, tests=(2, 6)):
+    """Section 6.3's dense tensor (i^2+j^2+k^2)^(-1/2), FP64, first seeded run of
+    Table 4's tests: 'Multilevel + FMG' (Section 6.1, Table 1 parameters) and
+    standalone ALS from the same boot factors, both to g < 1e-10 (eq. (31)).
+    The multilevel time includes its g evaluations (they drive the stagnation
+    rules); the ALS time is that of exactly the sweep count found by a first run
+    with g after every sweep (the paper's times leave the stopping test out)."""
+    import torch
+    out = []
+    for t in tests:
+        s, R = synth.DENSE_TESTS[t]
+        d = synth.dense_case(s, R)
+        Zd = api.DeviceTensor.from_numpy(ctx, d["Z"])
+        cdims = [s] * 3
+        while any(x > d["coarsest"][n] for n, x in enumerate(cdims)):
+            cdims = [(x + 1) // 2 if x > d["coarsest"][n] else x for n, x in enumerate(cdims)]
+        cs = synth.dense_coarse_start(cdims, R, d["seed"])
+        A = api.DeviceFactors.from_numpy(ctx, d["boot"])
+        T = [api.DeviceFactors.from_numpy(ctx, x) for x in d["tfms"]]
+        Cd = api.DeviceFactors.from_numpy(ctx, cs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = drivers.multilevel_fmg(ctx, Zd, A, T, d["coarsest"], Cd,
+                                      fas=dict(nu1=1, nu2=1, nuc=50, gs_iters=10))
+        torch.cuda.synchronize()
+        t_ml = time.perf_counter() - t0
+        fit_ml = drivers.exact_fit(ctx, Zd, A)
+        B = api.DeviceFactors.from_numpy(ctx, d["boot"])
+        sweeps, gh = drivers.als_solve_g(ctx, Zd, B, tau=1e-10, max_sweeps=10000)
+        fit_als = drivers.exact_fit(ctx, Zd, B)
+        B = api.DeviceFactors.from_numpy(ctx, d["boot"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.cp_als_sweep(ctx, Zd, B, None, sweeps, 0, 10, True, 0)
+        torch.cuda.synchronize()
+        t_als = time.perf_counter() - t0
+        row = {"test": t, "s": s, "R": R, "levels": info["levels"],
+               "multilevel_fmg": {"iterations": info["iterations"], "setup_cycles": len(info["setup"]),
+                                  "solve_cycles": len(info["solve"]), "rebuilt": info["rebuilt"],
+                                  "g": info["solve"][-1] if info["solve"] else None,
+                                  "seconds": round(t_ml, 4), "fit": fit_ml},
+               "als": {"sweeps": sweeps, "converged": bool(gh and gh[-1] < 1e-10), "g": gh[-1] if gh else None,
+                       "seconds": round(t_als, 4), "us_per_sweep": round(1e6 * t_als / max(sweeps, 1), 1),
+                       "fit": fit_als},
+               "speedup": round(t_als / t_ml, 3),
+               "paper_table4": TABLE4.get(t)}
+        log(f"dense test {t} (s={s}, R={R}, {info['levels']} levels): Multilevel+FMG {info['iterations']} it "
+            f"in {t_ml:.3f} s; ALS {sweeps} sweeps in {t_als:.3f} s; speedup {t_als / t_ml:.2f}")
+        out.append(row)
     return out
 
 

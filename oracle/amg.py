@@ -349,8 +349,9 @@ def setup_phase(Z, A0, tfms0, coarsest, max_cycles=5, check_after=3, eps=0.1,
 
 
 def solve_phase(Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500,
-                stagnation_after=5, nu1_setup=5, **fas):
-    """FAS cycles until g < tau with one stagnation-triggered rebuild (Section 6.1)."""
+                stagnation_after=5, nu1_setup=5, info=None, **fas):
+    """FAS cycles until g < tau with one stagnation-triggered rebuild (Section 6.1).
+    If ``info`` is a dict, info["rebuilt"] tells whether the rebuild happened."""
     g_old = cp.grad_norm(Z, A)
     rebuilt = False
     hist = []
@@ -365,7 +366,42 @@ def solve_phase(Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500,
         hist.append(g_new)
         if g_new < tau:
             break
+    if info is not None:
+        info["rebuilt"] = rebuilt
     return A, levels, hist
+
+
+def multilevel_fmg(Z, A0, tfms0, coarsest, coarse_start, tau=1e-10, max_cycles=500,
+                   fmg_nu=100, setup=None, fas=None):
+    """'Multilevel + FMG' of Section 6.1.
+
+    1. Setup cycles (Algorithm 1) from the boot factors A0 and test blocks tfms0,
+       stopped by eq. (32) as in ``setup_phase``.
+    2. One FMG-CP-FAS cycle (Algorithm 3) over the setup's levels, started from
+       ``coarse_start`` on the coarsest level: its result is the new
+       approximation to the boot factors.
+    3. The transfer operators are rebuilt by one down-sweep of Algorithm 1 with
+       these boot factors (the test blocks are relaxed, the boot factors are not).
+    4. Solve cycles (``solve_phase``) from the FMG result until g < tau.
+
+    Returns (A, info) with info = dict(setup=g after each setup cycle,
+    fmg=g after the FMG cycle, solve=g after each kept solve cycle,
+    rebuilt=whether the solve phase rebuilt its operators, levels=level count,
+    iterations=setup cycles + solve cycles)."""
+    setup = dict(setup or {})
+    fas = dict(fas or {})
+    A, tfms, levels, shist = setup_phase(Z, A0, tfms0, coarsest, **setup)
+    A = fmg_cycle(levels, coarse_start, nu=fmg_nu, **fas)
+    g_fmg = cp.grad_norm(Z, A)
+    nu1 = setup.get("nu1", 5)
+    levels, tfms = down_sweep(Z, A, tfms, coarsest, nu1=nu1)
+    out = {}
+    A, levels, hist = solve_phase(Z, A, levels, tfms, coarsest, tau, max_cycles,
+                                  nu1_setup=nu1, info=out, **fas)
+    rebuilt = out["rebuilt"]
+    info = dict(setup=shist, fmg=g_fmg, solve=hist, rebuilt=rebuilt, levels=len(levels),
+                iterations=len(shist) + len(hist))
+    return A, info
 
 
 def default_coarsest(dims, R, target=None):

@@ -425,3 +425,60 @@ def solve_phase(ctx, Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500, st
         if g_new < tau:
             break
     return levels, hist, rebuilt
+
+
+def multilevel_fmg(ctx, Z, A, tfms, coarsest, coarse_start, tau=1e-10, max_cycles=500, fmg_nu=SETUP_NUC,
+                   setup=None, fas=None):
+    """'Multilevel + FMG' of Section 6.1: setup cycles (stopped by eq. (32)), one
+    FMG-CP-FAS cycle (Algorithm 3) from `coarse_start` on the coarsest level whose
+    result replaces the boot factors, one down-sweep rebuild of the transfer
+    operators with those boot factors (test blocks relaxed, boot factors not),
+    then CP-FAS solve cycles until g < tau.  A (the boot factors) and the TFMs are
+    updated in place; `coarse_start` is overwritten by the coarsest-level ALS.
+    Returns a dict: g after each setup cycle, after the FMG cycle and after each
+    kept solve cycle, whether the solve phase rebuilt its operators, the level
+    count and the iteration count (setup plus solve cycles)."""
+    setup = dict(setup or {})
+    fas = dict(fas or {})
+    levels, _, shist = setup_phase(ctx, Z, A, tfms, coarsest, **setup)
+    Af = fmg_cycle(ctx, levels, coarse_start, nu=fmg_nu, **fas)
+    _copy_factors(A, Af)
+    g_fmg = grad_norm(ctx, Z, A)
+    nu1 = setup.get("nu1", SETUP_NU1)
+    levels, _ = down_sweep(ctx, Z, A, tfms, coarsest, nu1=nu1)
+    levels, hist, rebuilt = solve_phase(ctx, Z, A, levels, tfms, coarsest, tau, max_cycles,
+                                        nu1_setup=nu1, **fas)
+    return dict(setup=shist, fmg=g_fmg, solve=hist, rebuilt=rebuilt, levels=len(levels),
+                iterations=len(shist) + len(hist))
+
+
+def als_solve_g(ctx, Z, A, tau=1e-10, max_sweeps=10000, chunk=32, prec=CP_FP64):
+    """Standalone ALS stopped by eq. (31): g < tau, with g of eq. (30) evaluated
+    on the device after every sweep and read back once per chunk.  When the rule
+    holds after sweep j of a chunk, the factors are put back as they were before
+    the chunk and exactly j sweeps are run again (the kernels are deterministic).
+    Returns (sweeps, g history)."""
+    torch = _torch()
+    dev = A.mats[0].device
+    gbuf = torch.zeros(chunk, dtype=torch.float64, device=dev)
+    snap = A.clone()
+    sweeps, hist = 0, []
+    while sweeps < max_sweeps:
+        k = min(chunk, max_sweeps - sweeps)
+        _copy_factors(snap, A)
+        for j in range(k):
+            api.cp_als_sweep(ctx, Z, A, None, 1, CP_SOLVE_CHOL, 10, True, prec)
+            api.cp_objective(ctx, Z, A, exact=True, g=gbuf[j:j + 1])
+        gv = gbuf[:k].cpu().numpy()
+        hit = next((j for j in range(k) if gv[j] < tau), None)
+        if hit is None:
+            hist.extend(float(x) for x in gv)
+            sweeps += k
+            continue
+        hist.extend(float(x) for x in gv[:hit + 1])
+        sweeps += hit + 1
+        if hit + 1 < k:
+            _copy_factors(A, snap)
+            api.cp_als_sweep(ctx, Z, A, None, hit + 1, CP_SOLVE_CHOL, 10, True, prec)
+        break
+    return sweeps, hist

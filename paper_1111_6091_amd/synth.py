@@ -29,6 +29,7 @@ import numpy as np
 __all__ = [
     "collinear_factors", "outer_sum", "collinear_tensor", "uniform_start",
     "linear_interp_weights", "WORKLOADS", "workload", "batched_problems",
+    "dense_ijk", "DENSE_TESTS", "dense_case", "dense_coarse_start",
 ]
 
 
@@ -142,3 +143,52 @@ def batched_problems(count=512, seed=5, restarts=4, lo=16, hi=96, rmin=2, rmax=8
             d["starts"] = [uniform_start(dims, R, 5000 + b, k) for k in range(restarts)]
         probs.append(d)
     return probs
+
+
+# ---------------------------------------------------------------------------
+# Dense closed-form test problem of Section 6.3 (Table 4)
+# ---------------------------------------------------------------------------
+def dense_ijk(s):
+    """The s x s x s tensor with entries (i^2 + j^2 + k^2)^(-1/2), i, j, k = 1..s
+    (1-based), in Fortran order.  It is symmetric, so the layout of the modes
+    does not matter."""
+    i = np.arange(1, s + 1, dtype=np.float64)
+    sq = i * i
+    Z = 1.0 / np.sqrt(sq[:, None, None] + sq[None, :, None] + sq[None, None, :])
+    return np.asfortranarray(Z)
+
+
+# Table 4's problem parameters: test number -> (s, R).
+DENSE_TESTS = {1: (50, 2), 2: (50, 3), 3: (50, 4), 4: (50, 5),
+               5: (100, 2), 6: (100, 3), 7: (100, 4), 8: (100, 5),
+               9: (200, 2), 10: (200, 3), 11: (200, 4), 12: (200, 5)}
+
+
+def dense_case(s, R, run=0, n_t=2):
+    """Inputs of one run of the dense problem, as a dict:
+
+    - ``Z``: the tensor;
+    - ``boot``: the boot factor matrices, also the start of standalone ALS;
+    - ``tfms``: ``n_t`` test blocks;
+    - ``coarsest``: the coarsening thresholds I_{n,coarsest} = 2R of every mode
+      (with modes coarsened while larger than the threshold, this gives the level
+      counts that Table 4 lists for all twelve tests);
+    - ``seed``: the run's seed; the random coarsest-level start of the FMG cycle
+      comes from ``dense_coarse_start(dims, R, seed)``.
+
+    Every start is U(0,1) (the paper's initial guesses are standard uniform); the
+    run's generator is ``default_rng(7000 + 100 s + 10 R + run)`` and draws the
+    boot factors, then the test blocks in order."""
+    Z = dense_ijk(s)
+    seed = 7000 + 100 * s + 10 * R + run
+    rng = np.random.default_rng(seed)
+    dims = (s, s, s)
+    boot = [np.ascontiguousarray(rng.random((s, R))) for _ in dims]
+    tfms = [[np.ascontiguousarray(rng.random((s, R))) for _ in dims] for _ in range(n_t)]
+    return dict(Z=Z, boot=boot, tfms=tfms, coarsest=[2 * R] * 3, seed=seed, s=s, R=R, run=run)
+
+
+def dense_coarse_start(dims_coarse, R, seed):
+    """U(0,1) start on the coarsest level for the FMG cycle (generator seed + 1)."""
+    rng = np.random.default_rng(seed + 1)
+    return [np.ascontiguousarray(rng.random((d, R))) for d in dims_coarse]

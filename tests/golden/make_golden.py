@@ -149,6 +149,36 @@ def batch_reference(sample=BATCH_SAMPLE, restarts=4, fit_tol=1e-12, max_sweeps=1
     return out
 
 
+def dense_reference(s, R, run=0, tau=1e-10, max_sweeps=10000):
+    """The dense problem of Section 6.3 (one run of a Table 4 test): the oracle's
+    'Multilevel + FMG' (Section 6.1, Table 1 parameters) and standalone ALS from
+    the same boot factors, both stopped by g < tau (eq. (31))."""
+    from oracle import amg
+    d = synth.dense_case(s, R, run)
+    Z = d["Z"]
+    levels = amg.n_levels(Z.shape, d["coarsest"])
+    dims = list(Z.shape)
+    while any(x > d["coarsest"][n] for n, x in enumerate(dims)):
+        dims = [amg.coarse_size(x) if x > d["coarsest"][n] else x for n, x in enumerate(dims)]
+    cs = synth.dense_coarse_start(dims, R, d["seed"])
+    t = time.time()
+    A, info = amg.multilevel_fmg(Z, d["boot"], d["tfms"], d["coarsest"], cs, tau=tau,
+                                 setup=amg.SETUP_PARAMS_NO_NT, fas=amg.FAS_PARAMS)
+    t_ml = time.time() - t
+    t = time.time()
+    B, h = cp.als(Z, d["boot"], max_sweeps=max_sweeps, fit_tol=None, g_tol=tau)
+    t_als = time.time() - t
+    return {
+        "s": s, "R": R, "run": run, "tau": tau, "levels": levels, "coarsest": d["coarsest"],
+        "multilevel": {"setup_g": [float(x) for x in info["setup"]], "fmg_g": float(info["fmg"]),
+                       "solve_g": [float(x) for x in info["solve"]], "rebuilt": info["rebuilt"],
+                       "iterations": info["iterations"], "fit": cp.fit(Z, A), "oracle_seconds": t_ml},
+        "als": {"sweeps": h["sweeps"], "g_last": h["g"][-1], "g_tail": h["g"][-4:],
+                "converged": bool(h["g"][-1] < tau), "fit": cp.fit(Z, B),
+                "oracle_seconds_with_g": t_als},
+    }
+
+
 def _dump(obj, name):
     with open(os.path.join(HERE, name), "w") as f:
         json.dump(obj, f, indent=1)
@@ -160,6 +190,12 @@ if __name__ == "__main__":
         main_fas(args[1:] or ["c2_128cube_r5"])
     elif args and args[0] == "c1":
         _dump(c1_pipeline(), "c1_20cube_r3_pipeline.json")
+    elif args and args[0] == "dense":
+        for sr in (args[1:] or ["50,3"]):
+            s_, r_ = (int(x) for x in sr.split(","))
+            ref = dense_reference(s_, r_)
+            _dump(ref, f"dense_s{s_}_r{r_}_run0.json")
+            print(sr, ref["multilevel"]["iterations"], ref["als"]["sweeps"], flush=True)
     elif args and args[0] == "batch":
         _dump(batch_reference(), "batch_sampled_final_fits.json")
     else:
