@@ -371,6 +371,22 @@ def solve_phase(Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500,
     return A, levels, hist
 
 
+def multilevel(Z, A0, tfms0, coarsest, tau=1e-10, max_cycles=500, setup=None, fas=None):
+    """'Multilevel' of Section 6.1 (no FMG): setup cycles stopped by eq. (32),
+    then solve cycles from the setup's boot factors on the setup's levels until
+    g < tau, with the one stagnation rebuild.  Returns (A, info) with the fields
+    of ``multilevel_fmg`` except 'fmg'."""
+    setup = dict(setup or {})
+    fas = dict(fas or {})
+    A, tfms, levels, shist = setup_phase(Z, A0, tfms0, coarsest, **setup)
+    out = {}
+    A, levels, hist = solve_phase(Z, A, levels, tfms, coarsest, tau, max_cycles,
+                                  nu1_setup=setup.get("nu1", 5), info=out, **fas)
+    info = dict(setup=shist, solve=hist, rebuilt=out["rebuilt"], levels=len(levels),
+                iterations=len(shist) + len(hist))
+    return A, info
+
+
 def multilevel_fmg(Z, A0, tfms0, coarsest, coarse_start, tau=1e-10, max_cycles=500,
                    fmg_nu=100, setup=None, fas=None):
     """'Multilevel + FMG' of Section 6.1.

@@ -97,6 +97,22 @@ def mttkrp(Z, A, n):
     return unfold(Z, n) @ phi(A, n)
 
 
+def mttkrp_coo(idx, vals, shape, A, n):
+    """Z_(n) Phi^(n) of a tensor given by its nonzero entries (Section 6.2):
+    M(i_n, r) = sum over the stored entries z_{i_1..i_N} of
+    z prod_{m != n} A^(m)(i_m, r); every other entry is zero and adds nothing.
+    ``idx``: nnz x N 0-based indices (no index stored twice), ``vals``: nnz."""
+    idx = np.asarray(idx, dtype=np.int64)
+    R = A[0].shape[1]
+    W = np.asarray(vals, dtype=np.float64)[:, None] * np.ones((1, R))
+    for m in range(len(shape)):
+        if m != n:
+            W = W * A[m][idx[:, m], :]
+    M = np.zeros((shape[n], R))
+    np.add.at(M, idx[:, n], W)
+    return M
+
+
 def full(A):
     """[[A^(1), ..., A^(N)]] = sum_r a_r^(1) o ... o a_r^(N), eq. (1)."""
     R = A[0].shape[1]

@@ -30,6 +30,7 @@ __all__ = [
     "collinear_factors", "outer_sum", "collinear_tensor", "uniform_start",
     "linear_interp_weights", "WORKLOADS", "workload", "batched_problems",
     "dense_ijk", "DENSE_TESTS", "dense_case", "dense_coarse_start",
+    "laplacian_coo", "coo_to_dense", "LAPLACIAN_TESTS", "LAPLACIAN_COARSEST", "laplacian_case",
 ]
 
 
@@ -192,3 +193,69 @@ def dense_coarse_start(dims_coarse, R, seed):
     """U(0,1) start on the coarsest level for the FMG cycle (generator seed + 1)."""
     rng = np.random.default_rng(seed + 1)
     return [np.ascontiguousarray(rng.random((d, R))) for d in dims_coarse]
+
+
+# ---------------------------------------------------------------------------
+# Sparse test problem of Section 6.2 (Tables 2 and 3)
+# ---------------------------------------------------------------------------
+def laplacian_coo(d, s):
+    """The finite-difference Laplacian on an s^d grid as an N = 2d mode tensor.
+
+    The s^d x s^d matrix sum_k I_{s^(d-k)} (x) D (x) I_{s^(k-1)}, D = tridiag
+    (-1, 2, -1) of size s, reshaped column-major to s x ... x s: modes 1..d are
+    the digits of the row index and modes d+1..2d those of the column index
+    (first digit fastest), so the entry at (i_1..i_d, j_1..j_d) is
+    sum_k D(i_k, j_k) prod_{m != k} [i_m == j_m].  Returns (idx, vals, shape):
+    0-based indices (nnz x N, int32) and values of the nonzero entries in
+    increasing linear order (mode 1 fastest)."""
+    rows = np.indices((s,) * d).reshape(d, -1, order="F").T   # row digits, first fastest
+    idx_parts, val_parts = [], []
+    idx_parts.append(np.concatenate([rows, rows], axis=1))
+    val_parts.append(np.full(rows.shape[0], 2.0 * d))
+    for k in range(d):
+        for step in (-1, 1):
+            ok = (rows[:, k] + step >= 0) & (rows[:, k] + step < s)
+            r = rows[ok]
+            c = r.copy()
+            c[:, k] += step
+            idx_parts.append(np.concatenate([r, c], axis=1))
+            val_parts.append(np.full(r.shape[0], -1.0))
+    idx = np.concatenate(idx_parts).astype(np.int64)
+    vals = np.concatenate(val_parts)
+    lin = np.zeros(idx.shape[0], dtype=np.int64)
+    for m in range(2 * d - 1, -1, -1):
+        lin = lin * s + idx[:, m]
+    order = np.argsort(lin, kind="stable")
+    return np.ascontiguousarray(idx[order].astype(np.int32)), np.ascontiguousarray(vals[order]), (s,) * (2 * d)
+
+
+def coo_to_dense(idx, vals, shape):
+    """Dense Fortran-order array holding the coordinate entries (zeros elsewhere)."""
+    Z = np.zeros(shape, order="F")
+    Z[tuple(np.asarray(idx, dtype=np.int64).T)] = vals
+    return Z
+
+
+# Table 2's problem parameters: test number -> (N, s, R).
+LAPLACIAN_TESTS = {1: (4, 20, 4), 2: (4, 20, 5), 3: (4, 20, 6), 4: (4, 50, 2), 5: (4, 50, 3),
+                   6: (4, 50, 4), 7: (6, 20, 2), 8: (6, 20, 3), 9: (6, 20, 4), 10: (8, 10, 2),
+                   11: (8, 10, 3)}
+
+# Coarsening thresholds I_{n,coarsest} by order: with modes coarsened while
+# larger than the threshold they give the level counts Table 3 lists.
+LAPLACIAN_COARSEST = {4: 10, 6: 5, 8: 3}
+
+
+def laplacian_case(N, s, R, run=0, n_t=2):
+    """Inputs of one run of the sparse problem, as a dict: ``idx``, ``vals``,
+    ``shape`` (coordinate form), ``boot`` (boot factors, also the start of
+    standalone ALS), ``tfms`` (n_t test blocks), ``coarsest`` and ``seed``.
+    Starts are U(0,1) from ``default_rng(9000 + 1000 N + 10 s + R + 100000 run)``:
+    boot factors first, then the test blocks in order."""
+    idx, vals, shape = laplacian_coo(N // 2, s)
+    seed = 9000 + 1000 * N + 10 * s + R + 100000 * run
+    rng = np.random.default_rng(seed)
+    boot = [np.ascontiguousarray(rng.random((s, R))) for _ in shape]
+    tfms = [[np.ascontiguousarray(rng.random((s, R))) for _ in shape] for _ in range(n_t)]
+    return dict(idx=idx, vals=vals, shape=shape, boot=boot, tfms=tfms,
+                coarsest=[LAPLACIAN_COARSEST[N]] * N, seed=seed, N=N, s=s, R=R, run=run)
