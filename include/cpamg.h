@@ -71,16 +71,36 @@ typedef enum { CP_SOLVE_CHOL = 0, CP_SOLVE_GS = 1 } cp_solver;
 
 typedef struct cp_ctx_s* cp_ctx;
 
-/* Dense tensor.  z64: FP64 master (required by CP_FP64 calls); z32: FP32
- * shadow (required by CP_MIXED contractions; fill it with cp_cast_f32).
- * norm2: device scalar holding ||Z||^2 in FP64 (cp_norm2 writes it); it is
- * needed only where a call says so, NULL otherwise. */
+/* Tensor.  Dense form (nnz == 0): z64: FP64 master (required by CP_FP64
+ * calls); z32: FP32 shadow (required by CP_MIXED contractions; fill it with
+ * cp_cast_f32).  norm2: device scalar holding ||Z||^2 in FP64 (cp_norm2
+ * writes it); it is needed only where a call says so, NULL otherwise.
+ *
+ * Sparse form (nnz >= 1; Section 6.2: a relaxation then costs about N R nnz
+ * operations): the tensor is given by its nonzero entries, FP64 only, and
+ * z64 / z32 are ignored.
+ *   idx:  nnz x order int32, row-major (entry k has indices idx[k*order + m]),
+ *         0-based; no index tuple may appear twice.
+ *   vals: nnz FP64 values.
+ *   rowptr[m], perm[m] (m < order): the entries ordered by their mode-m index:
+ *         perm[m][rowptr[m][i] .. rowptr[m][i+1]-1] are the ids k of the
+ *         entries with index i in mode m, in increasing k (rowptr[m] has
+ *         I_m + 1 int64 offsets, perm[m] nnz int32 ids); cp_sparse_index
+ *         builds both on the host.
+ * Calls that accept the sparse form say so; the others return
+ * CP_ERR_UNSUPPORTED for it.  Every sparse call runs in FP64 (CP_MIXED:
+ * CP_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t order;
   int64_t dims[CP_MAX_ORDER];
   const double* z64;
   const float* z32;
   const double* norm2;
+  int64_t nnz;
+  const int32_t* idx;
+  const double* vals;
+  const int64_t* rowptr[CP_MAX_ORDER];
+  const int32_t* perm[CP_MAX_ORDER];
 } cp_tensor;
 
 /* Kruskal factors A^(0..N-1), each I_n x R row-major (FP64 master).  a32[n] is
@@ -155,8 +175,21 @@ cp_status cp_get_status(cp_ctx ctx, int32_t* flags);
 
 /* dst[i] = (float)src[i], i < count (FP32 shadow of a tensor or factor). */
 cp_status cp_cast_f32(cp_ctx ctx, const double* src, float* dst, int64_t count);
-/* *out (device) = ||Z||^2 accumulated in FP64 from Z->z64. */
+/* *out (device) = ||Z||^2 accumulated in FP64 from Z->z64 (sparse form: from
+ * the stored values). */
 cp_status cp_norm2(cp_ctx ctx, const cp_tensor* Z, double* out);
+
+/* Mode orderings of a sparse tensor (host only, no device work).  idx (host):
+ * nnz x order int32 0-based indices as in cp_tensor; dims (host): order
+ * extents.  Writes rowptr (host, sum over m of dims[m] + 1 int64: the rowptr
+ * arrays of modes 0, 1, ... back to back) and perm (host, order x nnz int32:
+ * perm of mode m at perm + m*nnz), ordering each mode's entries by index and,
+ * within one index, by entry id.  ctx may be NULL (no device is touched; the
+ * error message is then not kept).  Errors: CP_ERR_SHAPE for an order or extent
+ * outside the supported range or nnz outside [1, 2^31 - 1]; CP_ERR_INVALID for
+ * NULL pointers, an index outside its extent or an index tuple stored twice. */
+cp_status cp_sparse_index(cp_ctx ctx, int32_t order, const int64_t* dims, int64_t nnz,
+                          const int32_t* idx, int64_t* rowptr, int32_t* perm);
 
 /* ---- hot path (the calls named by the method) -------------------------- */
 
@@ -164,7 +197,11 @@ cp_status cp_norm2(cp_ctx ctx, const cp_tensor* Z, double* out);
  * factors but n in the order of eq. (7).  Computed as a matrix-core GEMM that
  * contracts one mode with its factor, followed by a Hadamard-reduce over the
  * remaining modes; the Khatri-Rao matrix is never formed.  M: I_n x R
- * row-major FP64 (written, not accumulated).  CP_MIXED reads z32/a32. */
+ * row-major FP64 (written, not accumulated).  CP_MIXED reads z32/a32.  Sparse
+ * form (FP64): the workgroups of output row i of mode n sum their share of the
+ * entries with index i (in perm[n] order) into per-split partial sums that a
+ * second launch adds in a fixed order; no atomics, so results repeat bit for
+ * bit. */
 cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
                     double* M, cp_prec prec);
 
@@ -185,6 +222,7 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
 #define CP_NOALLOC_SCRATCH_BYTES (32u << 20)
 cp_status cp_mttkrp_noalloc(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n,
                             double* M, cp_prec prec);
+/* (Dense form only.) */
 
 /* `nsweeps` iterations of block nonlinear Gauss-Seidel (Section 3 ALS, or the
  * FAS relaxation of Section 5.2 when F != NULL) on A^(n) Gamma^(n) =
@@ -195,7 +233,8 @@ cp_status cp_mttkrp_noalloc(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A,
  * the current A^(n).  normalize != 0 applies eq. (10) after every sweep.
  * F: NULL for plain ALS, else F->a[n] (I_n x R FP64).  f_hist (optional,
  * device, nsweeps doubles): f = 1/2||Z - [[A]]||^2 after each sweep from the
- * fused identity (needs Z->norm2; with CP_MIXED it uses the FP32 MTTKRP). */
+ * fused identity (needs Z->norm2; with CP_MIXED it uses the FP32 MTTKRP).
+ * Accepts the sparse form (FP64). */
 cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_factors* F,
                        int32_t nsweeps, cp_solver solver, int32_t gs_iters, int32_t normalize,
                        cp_prec prec, double* f_hist);
@@ -204,14 +243,19 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
  * f from one streaming pass over Z->z64 forming the residual on the fly;
  * exact == 0: fused identity 1/2(||Z||^2 - 2<A^(N), M^(N)> + 1^T(*Upsilon)1)
  * (needs Z->norm2).  f (device scalar, optional), g (device scalar, optional;
- * needs Z->norm2; N MTTKRPs in precision `prec`). */
+ * needs Z->norm2; N MTTKRPs in precision `prec`).  Sparse form (FP64): g as
+ * above; f from the fused identity whatever `exact` says (the residual has
+ * prod I_n entries, most of them outside the stored ones), with its relative
+ * rounding error of about eps ||Z||^2 / f. */
 cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t exact,
                        double* f, double* g, cp_prec prec);
 
 /* Coarse tensor eq. (15): Zc = Z x_{n : phat[n] != NULL} phat[n]^T, applied as
  * one mode-n matrix-core GEMM after another.  phat[n]: I_n x I_{n,c}
  * row-major, or NULL (identity).  Zc->dims must equal the coarse dims; CP_FP64
- * writes Zc->z64 from Z->z64, CP_MIXED writes Zc->z32 from Z->z32. */
+ * writes Zc->z64 from Z->z64, CP_MIXED writes Zc->z32 from Z->z32.  A sparse Z
+ * (FP64) is first scattered into a dense workspace copy (the coarse tensor is
+ * dense anyway: P^ = P L^{-T} has no zero entries). */
 cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[CP_MAX_ORDER],
                       cp_tensor* Zc, cp_prec prec);
 
@@ -239,7 +283,8 @@ cp_status cp_restrict_factor(cp_ctx ctx, int64_t I, int64_t Ic, int32_t R, const
  * the coarse points (i-1)/2 and (i+1)/2 (the latter absent at the right end of
  * an even extent: w[i][1] = 0) minimizing the weighted misfit of every fitted
  * column at i against its injected values at i - 1 and i + 1; rows of coarse
- * points are zero.  The output feeds cp_transfer_build.  FP64 (Z->z64).
+ * points are zero.  The output feeds cp_transfer_build.  FP64 (Z->z64, or the
+ * sparse form).
  * Errors: bad group split, nfit outside [1, groups], mode extent < 2. */
 cp_status cp_interp_weights(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t groups,
                             int32_t nfit, int32_t n, double* w);
@@ -254,7 +299,8 @@ cp_status cp_transfer_build(cp_ctx ctx, int64_t I, const double* w, double* phat
 
 /* One CP-FAS V-cycle (Algorithm 2) from level 0 with F = 0 there, updating A
  * (level-0 factors, and shadows) in place.  levels[0..nlevels-1]: finest to
- * coarsest; each level tensor needs z64 (CP_FP64) or z32 (CP_MIXED).
+ * coarsest; each level tensor needs z64 (CP_FP64) or z32 (CP_MIXED).  Level 0
+ * may be in the sparse form (CP_FP64; the coarser levels are dense).
  * Relaxation is BNGS with Gauss-Seidel inner solves; eq. (10) normalization is
  * applied on level 0 only.  params NULL = Table 1 defaults. */
 cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t nlevels, cp_factors* A,

@@ -47,7 +47,8 @@ c_vp = ctypes.c_void_p
 
 class CpTensor(ctypes.Structure):
     _fields_ = [("order", c_i32), ("dims", c_i64 * CP_MAX_ORDER), ("z64", c_vp),
-                ("z32", c_vp), ("norm2", c_vp)]
+                ("z32", c_vp), ("norm2", c_vp), ("nnz", c_i64), ("idx", c_vp), ("vals", c_vp),
+                ("rowptr", c_vp * CP_MAX_ORDER), ("perm", c_vp * CP_MAX_ORDER)]
 
 
 class CpFactors(ctypes.Structure):
@@ -81,6 +82,7 @@ SIGNATURES = {
     "cp_get_status": [c_vp, ctypes.POINTER(c_i32)],
     "cp_cast_f32": [c_vp, c_vp, c_vp, c_i64],
     "cp_norm2": [c_vp, ctypes.POINTER(CpTensor), c_vp],
+    "cp_sparse_index": [c_vp, c_i32, ctypes.POINTER(c_i64), c_i64, c_vp, c_vp, c_vp],
     "cp_mttkrp": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_vp, c_i32],
     "cp_mttkrp_noalloc": [c_vp, ctypes.POINTER(CpTensor), ctypes.POINTER(CpFactors), c_i32, c_vp,
                           c_i32],

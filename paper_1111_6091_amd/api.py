@@ -95,6 +95,10 @@ class DeviceTensor:
     def numel(self):
         return int(np.prod(self.dims))
 
+    @property
+    def device(self):
+        return (self.z64 if self.z64 is not None else self.z32).device
+
     @classmethod
     def from_numpy(cls, ctx, Z, fp32=False, device="cuda"):
         torch = _torch()
@@ -128,6 +132,66 @@ class DeviceTensor:
     def to_numpy(self, which="z64"):
         buf = getattr(self, which)
         return buf.detach().cpu().numpy().astype(np.float64).reshape(self.dims, order="F")
+
+
+class SparseTensor:
+    """Sparse tensor in device memory (cp_tensor's sparse form): coordinate
+    entries (idx nnz x N int32, vals nnz FP64) and the per-mode orderings that
+    cp_sparse_index builds on the host."""
+
+    def __init__(self, dims, idx, vals, rowptr, perm, norm2=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.idx, self.vals, self.rowptr, self.perm, self.norm2 = idx, vals, rowptr, perm, norm2
+        self.z64 = self.z32 = None
+
+    @property
+    def order(self):
+        return len(self.dims)
+
+    @property
+    def nnz(self):
+        return int(self.vals.numel())
+
+    @property
+    def device(self):
+        return self.vals.device
+
+    @classmethod
+    def from_coo(cls, ctx, idx, vals, dims, device="cuda"):
+        torch = _torch()
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+        vals = np.ascontiguousarray(np.asarray(vals, dtype=np.float64))
+        N, nnz = len(dims), vals.shape[0]
+        if idx.shape != (nnz, N):
+            raise ValueError(f"idx has shape {idx.shape}, expected ({nnz}, {N})")
+        dd = (ctypes.c_int64 * N)(*[int(d) for d in dims])
+        rowptr = np.zeros(sum(int(d) + 1 for d in dims), dtype=np.int64)
+        perm = np.zeros(N * nnz, dtype=np.int32)
+        ctx.check(ctx._lib.cp_sparse_index(ctx.handle, N, dd, nnz, idx.ctypes.data_as(ctypes.c_void_p),
+                                           rowptr.ctypes.data_as(ctypes.c_void_p),
+                                           perm.ctypes.data_as(ctypes.c_void_p)))
+        t = cls(dims, torch.from_numpy(idx).to(device), torch.from_numpy(vals).to(device),
+                torch.from_numpy(rowptr).to(device), torch.from_numpy(perm).to(device))
+        t.norm2 = torch.zeros(1, dtype=torch.float64, device=device)
+        cp_norm2(ctx, t, t.norm2)
+        return t
+
+    def struct(self):
+        s = CpTensor()
+        s.order = self.order
+        for i, d in enumerate(self.dims):
+            s.dims[i] = d
+        s.norm2 = _ptr(self.norm2).value
+        s.nnz = self.nnz
+        s.idx = _ptr(self.idx).value
+        s.vals = _ptr(self.vals).value
+        rp0, pm0 = int(self.rowptr.data_ptr()), int(self.perm.data_ptr())
+        off = 0
+        for m, d in enumerate(self.dims):
+            s.rowptr[m] = rp0 + 8 * off
+            s.perm[m] = pm0 + 4 * m * self.nnz
+            off += d + 1
+        return s
 
 
 class DeviceFactors:

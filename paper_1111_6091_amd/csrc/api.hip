@@ -189,6 +189,22 @@ int64_t numel(const cp_tensor* Z) {
   return p;
 }
 
+bool is_sparse(const cp_tensor* Z) { return Z->nnz > 0; }
+
+SpTensor sp_view(const cp_tensor* Z) {
+  SpTensor t{};
+  t.N = Z->order;
+  t.nnz = Z->nnz;
+  t.idx = Z->idx;
+  t.vals = Z->vals;
+  for (int m = 0; m < Z->order; ++m) {
+    t.dims[m] = Z->dims[m];
+    t.rowptr[m] = Z->rowptr[m];
+    t.perm[m] = Z->perm[m];
+  }
+  return t;
+}
+
 cp_status check_ctx(cp_ctx ctx) { return ctx ? CP_OK : CP_ERR_INVALID; }
 
 cp_status check_tensor(cp_ctx ctx, const cp_tensor* Z, bool need64, bool need32, const char* name) {
@@ -198,8 +214,24 @@ cp_status check_tensor(cp_ctx ctx, const cp_tensor* Z, bool need64, bool need32,
   for (int m = 0; m < Z->order; ++m)
     if (Z->dims[m] < 1 || Z->dims[m] > (int64_t(1) << 31))
       return set_err(ctx, CP_ERR_SHAPE, "%s: dims[%d] = %lld out of range", name, m, (long long)Z->dims[m]);
+  if (Z->nnz < 0) return set_err(ctx, CP_ERR_SHAPE, "%s: nnz < 0", name);
+  if (Z->nnz > 0) {
+    if (need32)
+      return set_err(ctx, CP_ERR_UNSUPPORTED, "%s: the sparse form is FP64 only (no CP_MIXED)", name);
+    if (Z->nnz > INT32_MAX) return set_err(ctx, CP_ERR_SHAPE, "%s: nnz above 2^31 - 1", name);
+    if (!Z->idx || !Z->vals) return set_err(ctx, CP_ERR_INVALID, "%s: sparse idx or vals is NULL", name);
+    for (int m = 0; m < Z->order; ++m)
+      if (!Z->rowptr[m] || !Z->perm[m])
+        return set_err(ctx, CP_ERR_INVALID, "%s: sparse rowptr[%d] or perm[%d] is NULL", name, m, m);
+    return CP_OK;
+  }
   if (need64 && !Z->z64) return set_err(ctx, CP_ERR_INVALID, "%s: z64 is NULL", name);
   if (need32 && !Z->z32) return set_err(ctx, CP_ERR_INVALID, "%s: z32 is NULL (CP_MIXED needs the FP32 shadow)", name);
+  return CP_OK;
+}
+
+cp_status require_dense(cp_ctx ctx, const cp_tensor* Z, const char* what) {
+  if (Z && Z->nnz > 0) return set_err(ctx, CP_ERR_UNSUPPORTED, "%s: the sparse form is not supported here", what);
   return CP_OK;
 }
 
@@ -223,7 +255,14 @@ cp_status check_prec(cp_ctx ctx, cp_prec p) {
 // Enqueue M^(n) partials for tensor Z (precision prec); returns the plan.
 cp_status enqueue_mttkrp(cp_ctx ctx, const int64_t* dims, int N, int n, int R, const void* z,
                          bool fp32, const double* const* a64, const float* const* a32,
-                         const MttkrpPlan& plan, double* out, const PrepArgs* prep = nullptr) {
+                         const MttkrpPlan& plan, double* out, const PrepArgs* prep = nullptr,
+                         const SpTensor* sp = nullptr) {
+  if (plan.kind == kSparseKind) {
+    if (!sp) return set_err(ctx, CP_ERR_INVALID, "internal: sparse plan without a sparse tensor");
+    ProfScope ps(ctx, CP_PROF_MTTKRP_MODE0_F64 + std::min(n, 2));
+    HIPCHK(sp_mttkrp_launch(*sp, n, R, a64, out, plan.nsplit, prep, ctx->stream));
+    return CP_OK;
+  }
   ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + (plan.kind - 1));
   HIPCHK(mttkrp_launch(plan, dims, N, n, R, z, fp32, a64, a32, out, prep, ctx->stream));
   return CP_OK;
@@ -286,11 +325,20 @@ MttkrpPlan get_plan(cp_ctx ctx, int N, const int64_t* dims, int n, int R, bool f
   return p;
 }
 
+// Launch plan of a sparse MTTKRP of mode n (not cached: it depends on nnz).
+MttkrpPlan sparse_plan(const SpTensor& t, int n, int R) {
+  MttkrpPlan p{};
+  p.kind = kSparseKind;
+  p.nsplit = sp_mttkrp_nsplit(t, n);
+  p.partial_doubles = (size_t)p.nsplit * t.dims[n] * R;
+  return p;
+}
+
 size_t max_partial(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32,
-                   std::vector<MttkrpPlan>* plans) {
+                   std::vector<MttkrpPlan>* plans, const SpTensor* sp = nullptr) {
   size_t mx = 0;
   for (int n = 0; n < N; ++n) {
-    MttkrpPlan p = get_plan(ctx, N, dims, n, R, fp32);
+    MttkrpPlan p = sp ? sparse_plan(*sp, n, R) : get_plan(ctx, N, dims, n, R, fp32);
     if (plans) plans->push_back(p);
     mx = std::max(mx, p.partial_doubles);
   }
@@ -342,10 +390,11 @@ struct SweepPlan {
   size_t ydoubles = 0;
 };
 
-SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32) {
+SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32,
+                     const SpTensor* spt = nullptr) {
   SweepPlan sp;
-  sp.partial = max_partial(ctx, dims, N, R, fp32, &sp.p);
-  if (!ctx->dimtree || N < 3) return sp;
+  sp.partial = max_partial(ctx, dims, N, R, fp32, &sp.p, spt);
+  if (!ctx->dimtree || N < 3 || spt) return sp;
   int64_t S = 1, P = 1;
   for (int m = 2; m < N; ++m) S *= dims[m];
   for (int m = 0; m < N; ++m) P *= dims[m];
@@ -399,7 +448,7 @@ cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const vo
                          double* const* A, float* const* A32, double* const* F,
                          const SweepPlan& sp, const SweepWS& w, cp_solver solver,
                          int gs_iters, int normalize, int nsweeps, double* f_hist,
-                         const double* norm2) {
+                         const double* norm2, const SpTensor* spt = nullptr) {
   if (nsweeps <= 0) return CP_OK;
   TRY(enqueue_gram(ctx, A, A32, dims, N, R, w.grams, w.sigma));
   auto base_args = [&](int n) {
@@ -447,7 +496,7 @@ cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const vo
         nsplit = sp.p1y.nsplit;
       } else {
         cp_status s = enqueue_mttkrp(ctx, dims, N, n, R, z, fp32, (const double* const*)A,
-                                     (const float* const*)A32, sp.p[n], w.partial, &pa);
+                                     (const float* const*)A32, sp.p[n], w.partial, &pa, spt);
         if (s != CP_OK) return s;
       }
       EpiDesc d{};
@@ -485,6 +534,25 @@ cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const vo
   }
   ProfScope ps(ctx, CP_PROF_NORMALIZE);
   HIPCHK(finalize_launch(fa, ctx->stream));
+  return CP_OK;
+}
+
+
+// One strided batched GEMM as launches that keep the grid's y and z extents
+// within 65535 (column tiles of 64, batch entries).
+cp_status gemm_chunked(cp_ctx ctx, const GemmDesc& g, bool fp32) {
+  const int64_t esz = fp32 ? 4 : 8;
+  const int64_t ncols = 65535LL * 64, nbat = 65535;
+  for (int64_t b0 = 0; b0 < g.batch; b0 += nbat)
+    for (int64_t n0 = 0; n0 < g.N; n0 += ncols) {
+      GemmDesc h = g;
+      h.batch = std::min(nbat, g.batch - b0);
+      h.N = std::min(ncols, g.N - n0);
+      h.A = (const char*)g.A + b0 * g.a_bs * esz;
+      h.B = (const char*)g.B + (b0 * g.b_bs + n0 * g.b_cs) * esz;
+      h.C = (char*)g.C + (b0 * g.c_bs + n0 * g.c_cs) * esz;
+      HIPCHK(gemm_launch(h, fp32, ctx->stream));
+    }
   return CP_OK;
 }
 
@@ -607,8 +675,21 @@ cp_status cp_norm2(cp_ctx ctx, const cp_tensor* Z, double* out) {
   if (!out) return set_err(ctx, CP_ERR_INVALID, "cp_norm2: out is NULL");
   s = ensure_ws(ctx, align_up(2048 * sizeof(double)));
   if (s != CP_OK) return s;
-  HIPCHK(norm2_launch(Z->z64, numel(Z), (double*)ctx->ws, ctx->counters + CNT_DOT, out, ctx->stream));
+  if (is_sparse(Z))
+    HIPCHK(norm2_launch(Z->vals, Z->nnz, (double*)ctx->ws, ctx->counters + CNT_DOT, out, ctx->stream));
+  else
+    HIPCHK(norm2_launch(Z->z64, numel(Z), (double*)ctx->ws, ctx->counters + CNT_DOT, out, ctx->stream));
   return CP_OK;
+}
+
+cp_status cp_sparse_index(cp_ctx ctx, int32_t order, const int64_t* dims, int64_t nnz,
+                          const int32_t* idx, int64_t* rowptr, int32_t* perm) {
+  if (!dims || !idx || !rowptr || !perm)
+    return ctx ? set_err(ctx, CP_ERR_INVALID, "cp_sparse_index: NULL pointer") : CP_ERR_INVALID;
+  std::string msg;
+  const cp_status s = sparse_index_host(order, dims, nnz, idx, rowptr, perm, &msg);
+  if (s != CP_OK && ctx) return set_err(ctx, s, "cp_sparse_index: %s", msg.c_str());
+  return s;
 }
 
 cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t n, double* M,
@@ -623,14 +704,17 @@ cp_status cp_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: mode %d outside [0, %d)", n, N);
   if (!M) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp: M is NULL");
   const int R = A->rank;
-  MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, R, mixed);
+  const SpTensor spv = is_sparse(Z) ? sp_view(Z) : SpTensor{};
+  const SpTensor* spt = is_sparse(Z) ? &spv : nullptr;
+  MttkrpPlan plan = spt ? sparse_plan(spv, n, R) : get_plan(ctx, N, Z->dims, n, R, mixed);
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   if (plan.nsplit == 1)
-    return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M);
+    return enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan, M,
+                          nullptr, spt);
   if ((s = ensure_ws(ctx, align_up(plan.partial_doubles * sizeof(double)))) != CP_OK) return s;
   double* part = (double*)ctx->ws;
   if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, plan,
-                          part)) != CP_OK)
+                          part, nullptr, spt)) != CP_OK)
     return s;
   EpiDesc d{};
   d.op = EPI_STORE_M;
@@ -652,6 +736,7 @@ cp_status cp_mttkrp_noalloc(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A,
   if (s != CP_OK) return s;
   const bool mixed = prec == CP_MIXED;
   if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  if ((s = require_dense(ctx, Z, "cp_mttkrp_noalloc")) != CP_OK) return s;
   const int N = Z->order;
   if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_mttkrp_noalloc: mode %d outside [0, %d)", n, N);
@@ -711,16 +796,18 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   if (f_hist && !Z->norm2) return set_err(ctx, CP_ERR_INVALID, "f_hist needs Z->norm2");
   if (nsweeps == 0) return CP_OK;
   const int R = A->rank;
+  const SpTensor spv = is_sparse(Z) ? sp_view(Z) : SpTensor{};
+  const SpTensor* spt = is_sparse(Z) ? &spv : nullptr;
   {
     bool h32 = true;
     for (int m = 0; m < N; ++m) h32 = h32 && A->a32[m];
     cp_status st = CP_OK;
-    if (solver == CP_SOLVE_GS && !normalize && !f_hist &&
+    if (solver == CP_SOLVE_GS && !normalize && !f_hist && !spt &&
         try_small_relax(ctx, Z->dims, N, R, mixed ? (const void*)Z->z32 : (const void*)Z->z64, mixed, A->a,
                         h32 ? A->a32 : nullptr, F ? F->a : nullptr, gs_iters, nsweeps, &st))
       return st;
   }
-  const SweepPlan sp = sweep_plan(ctx, Z->dims, N, R, mixed);
+  const SweepPlan sp = sweep_plan(ctx, Z->dims, N, R, mixed, spt);
   Sizer sz;
   SweepWS w{};
   carve_sweep(sz, N, R, sp.partial, max_dim(Z->dims, N), &w, sp.ydoubles);
@@ -732,7 +819,7 @@ cp_status cp_als_sweep(cp_ctx ctx, const cp_tensor* Z, cp_factors* A, const cp_f
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   return enqueue_sweeps(ctx, Z->dims, N, R, z, mixed, A->a, have32 ? A->a32 : nullptr,
                         F ? F->a : nullptr, sp, w, solver, gs_iters, normalize, nsweeps, f_hist,
-                        Z->norm2);
+                        Z->norm2, spt);
 }
 
 cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int32_t exact,
@@ -746,11 +833,14 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
   const int N = Z->order;
   if ((s = check_factors(ctx, A, N, mixed && (g || (f && !exact)), "A")) != CP_OK) return s;
   if (!f && !g) return CP_OK;
+  const SpTensor spv = is_sparse(Z) ? sp_view(Z) : SpTensor{};
+  const SpTensor* spt = is_sparse(Z) ? &spv : nullptr;
+  if (spt) exact = 0;   // the sparse form has no residual pass: fused identity
   if ((g || (f && !exact)) && !Z->norm2)
     return set_err(ctx, CP_ERR_INVALID, "cp_objective: g and the fused f need Z->norm2");
   const int R = A->rank;
   std::vector<MttkrpPlan> plans;
-  const size_t part = max_partial(ctx, Z->dims, N, R, mixed, &plans);
+  const size_t part = max_partial(ctx, Z->dims, N, R, mixed, &plans, spt);
   const int64_t In_last = Z->dims[N - 1];
   Sizer sz;
   SweepWS w{};
@@ -768,7 +858,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
   if (g) {
     for (int n = 0; n < N; ++n) {
       if ((s = enqueue_mttkrp(ctx, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32,
-                              plans[n], w.partial)) != CP_OK)
+                              plans[n], w.partial, nullptr, spt)) != CP_OK)
         return s;
       EpiDesc d{};
       d.op = EPI_GRAD;
@@ -790,7 +880,7 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
   }
   if (f && !exact) {
     if ((s = enqueue_mttkrp(ctx, Z->dims, N, N - 1, R, z, mixed, A->a, (const float* const*)A->a32,
-                            plans[N - 1], w.partial)) != CP_OK)
+                            plans[N - 1], w.partial, nullptr, spt)) != CP_OK)
       return s;
     EpiDesc d{};
     d.op = EPI_STORE_M;
@@ -821,6 +911,7 @@ cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[C
   const int N = Z->order;
   if (Zc->order != N) return set_err(ctx, CP_ERR_SHAPE, "Zc order %d != %d", Zc->order, N);
   if (mixed ? !Zc->z32 : !Zc->z64) return set_err(ctx, CP_ERR_INVALID, "Zc has no output buffer for this precision");
+  if (Zc->nnz != 0) return set_err(ctx, CP_ERR_INVALID, "Zc must be in the dense form");
   int64_t dc[CP_MAX_ORDER];
   std::vector<int> modes;
   for (int m = 0; m < N; ++m) {
@@ -834,8 +925,14 @@ cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[C
   const void* src = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   void* dst = mixed ? (void*)Zc->z32 : (void*)Zc->z64;
   const int64_t P = numel(Z);
+  const bool sparse = is_sparse(Z);
   if (modes.empty()) {
-    HIPCHK(hipMemcpyAsync(dst, src, P * esz, hipMemcpyDeviceToDevice, ctx->stream));
+    if (sparse) {
+      HIPCHK(fill_launch((double*)dst, 0.0, P, ctx->stream));
+      HIPCHK(sp_densify_launch(sp_view(Z), (double*)dst, ctx->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(dst, src, P * esz, hipMemcpyDeviceToDevice, ctx->stream));
+    }
     return CP_OK;
   }
   // intermediate sizes: after each restricted mode
@@ -849,12 +946,14 @@ cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[C
     maxmid = std::max(maxmid, (size_t)p);
   }
   Sizer sz;
+  if (sparse) sz.take<double>((size_t)P);
   sz.take<char>(maxmid * esz);
   sz.take<char>(maxmid * esz);
   if (mixed)
     for (int m : modes) sz.take<float>((size_t)Z->dims[m] * dc[m]);
   if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
   Arena ar(ctx->ws);
+  double* dense = sparse ? ar.take<double>((size_t)P) : nullptr;
   char* buf[2] = {ar.take<char>(maxmid * esz), ar.take<char>(maxmid * esz)};
   const void* pmat[CP_MAX_ORDER] = {};
   for (int m : modes) {
@@ -865,6 +964,13 @@ cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[C
     } else {
       pmat[m] = phat[m];
     }
+  }
+  if (sparse) {
+    // the entries scattered into a dense copy; the mode products below make
+    // the coarse tensor dense whatever the input's sparsity
+    HIPCHK(fill_launch(dense, 0.0, P, ctx->stream));
+    HIPCHK(sp_densify_launch(sp_view(Z), dense, ctx->stream));
+    src = dense;
   }
   for (int m = 0; m < N; ++m) cur[m] = Z->dims[m];
   const void* in = src;
@@ -883,16 +989,23 @@ cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[C
       g.a_rs = 1; g.a_cs = Ic; g.a_bs = 0;
       g.b_rs = 1; g.b_cs = In; g.b_bs = 0;
       g.c_rs = 1; g.c_cs = Ic; g.c_bs = 0;
-    } else {
+    } else if (L >= 16 || L >= T) {
       // per t: C_t (L x Ic) = X_t (L x In) * P^ (In x Ic)
       g.A = in; g.B = pmat[n]; g.C = outp;
       g.M = L; g.N = Ic; g.K = In; g.batch = T;
       g.a_rs = 1; g.a_cs = L; g.a_bs = L * In;
       g.b_rs = Ic; g.b_cs = 1; g.b_bs = 0;
       g.c_rs = 1; g.c_cs = L; g.c_bs = L * Ic;
+    } else {
+      // few leading entries: per l, C_l (Ic x T) = P^^T (Ic x In) * X_l (In x T)
+      // with X_l(k, t) = X[l + L k + L In t] (fills the 64-row tiles)
+      g.A = pmat[n]; g.B = in; g.C = outp;
+      g.M = Ic; g.N = T; g.K = In; g.batch = L;
+      g.a_rs = 1; g.a_cs = Ic; g.a_bs = 0;
+      g.b_rs = L; g.b_cs = L * In; g.b_bs = 1;
+      g.c_rs = L; g.c_cs = L * Ic; g.c_bs = 1;
     }
-    if (g.batch > 65535) return set_err(ctx, CP_ERR_UNSUPPORTED, "cp_restrict: batch %lld too large", (long long)g.batch);
-    HIPCHK(gemm_launch(g, mixed, ctx->stream));
+    TRY(gemm_chunked(ctx, g, mixed));
     cur[n] = Ic;
     in = outp;
   }
@@ -936,7 +1049,9 @@ cp_status cp_interp_weights(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A,
   if (!w) return set_err(ctx, CP_ERR_INVALID, "cp_interp_weights: w is NULL");
   const int Rt = A->rank;
   const int64_t In = Z->dims[n];
-  const MttkrpPlan plan = get_plan(ctx, N, Z->dims, n, Rt, false);
+  const SpTensor spv = is_sparse(Z) ? sp_view(Z) : SpTensor{};
+  const SpTensor* spt = is_sparse(Z) ? &spv : nullptr;
+  const MttkrpPlan plan = spt ? sparse_plan(spv, n, Rt) : get_plan(ctx, N, Z->dims, n, Rt, false);
   Sizer sz;
   sz.take<double>((size_t)N * Rt * Rt);
   sz.take<double>((size_t)In * Rt);
@@ -948,9 +1063,9 @@ cp_status cp_interp_weights(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A,
   double* part = ar.take<double>(plan.partial_doubles);
   TRY(enqueue_gram(ctx, A->a, nullptr, Z->dims, N, Rt, grams));
   if (plan.nsplit == 1) {
-    TRY(enqueue_mttkrp(ctx, Z->dims, N, n, Rt, Z->z64, false, A->a, nullptr, plan, M));
+    TRY(enqueue_mttkrp(ctx, Z->dims, N, n, Rt, Z->z64, false, A->a, nullptr, plan, M, nullptr, spt));
   } else {
-    TRY(enqueue_mttkrp(ctx, Z->dims, N, n, Rt, Z->z64, false, A->a, nullptr, plan, part));
+    TRY(enqueue_mttkrp(ctx, Z->dims, N, n, Rt, Z->z64, false, A->a, nullptr, plan, part, nullptr, spt));
     EpiDesc d{};
     d.op = EPI_STORE_M;
     d.R = Rt;
@@ -1010,6 +1125,7 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   if (s != CP_OK) return s;
   const bool mixed = prec == CP_MIXED;
   if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  if ((s = require_dense(ctx, Z, "timing and tuning calls")) != CP_OK) return s;
   const int N = Z->order;
   if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
   if (n < 0 || n >= N) return set_err(ctx, CP_ERR_INVALID, "cp_time_mttkrp: bad mode %d", n);
@@ -1067,6 +1183,7 @@ cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_pr
   if (s != CP_OK) return s;
   const bool mixed = prec == CP_MIXED;
   if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  if ((s = require_dense(ctx, Z, "timing and tuning calls")) != CP_OK) return s;
   const int N = Z->order;
   if ((s = check_factors(ctx, A, N, mixed, "A")) != CP_OK) return s;
   if (reps < 1 || reps > 10000) return set_err(ctx, CP_ERR_INVALID, "cp_autotune: reps outside [1, 10000]");
@@ -1249,6 +1366,9 @@ struct FasLevel {
   double* grams = nullptr;
   SweepPlan sp;
   bool has32 = false;
+  bool sparse = false;   // level tensor in the sparse form (level 0 only)
+  SpTensor spt{};
+  const SpTensor* spp() const { return sparse ? &spt : nullptr; }
 };
 
 struct FasRun {
@@ -1274,7 +1394,7 @@ cp_status fas_relax(FasRun& r, int l, int times) {
   SweepWS w{L.grams, r.sigma, r.partial, r.gram_part, r.scal_part, L.sp.dimtree ? r.y : nullptr};
   return enqueue_sweeps(ctx, L.dims, r.N, r.R, L.z, r.mixed, L.A, L.has32 ? L.A32 : nullptr,
                         l == 0 ? nullptr : L.F, L.sp, w, CP_SOLVE_GS, r.p.gs_iters,
-                        l == 0 ? 1 : 0, times, nullptr, nullptr);
+                        l == 0 ? 1 : 0, times, nullptr, nullptr, L.spp());
 }
 
 // H^(n)(A) = A^(n) Gamma^(n) - Z_(n) Phi^(n) for every mode of level l.
@@ -1284,7 +1404,7 @@ cp_status fas_H(FasRun& r, int l, double* const* A, float* const* A32, double* c
   TRY(enqueue_gram(ctx, A, A32, L.dims, r.N, r.R, L.grams));
   for (int n = 0; n < r.N; ++n) {
     cp_status s = enqueue_mttkrp(ctx, L.dims, r.N, n, r.R, L.z, r.mixed, (const double* const*)A,
-                                 (const float* const*)A32, L.sp.p[n], r.partial);
+                                 (const float* const*)A32, L.sp.p[n], r.partial, nullptr, L.spp());
     if (s != CP_OK) return s;
     EpiDesc d{};
     d.op = EPI_H;
@@ -1392,6 +1512,8 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
     char name[32];
     snprintf(name, sizeof(name), "levels[%d].z", l);
     if ((s = check_tensor(ctx, &levels[l].z, !mixed, mixed, name)) != CP_OK) return s;
+    if (l > 0 && levels[l].z.nnz != 0)
+      return set_err(ctx, CP_ERR_UNSUPPORTED, "level %d: only level 0 may be in the sparse form", l);
     if (levels[l].z.order != N) return set_err(ctx, CP_ERR_SHAPE, "level %d has order %d != %d", l, levels[l].z.order, N);
     if (l + 1 < nlevels) {
       for (int n = 0; n < N; ++n) {
@@ -1422,7 +1544,9 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
       L.phat[n] = (l + 1 < nlevels) ? levels[l].phat[n] : nullptr;
     }
     L.z = mixed ? (const void*)levels[l].z.z32 : (const void*)levels[l].z.z64;
-    L.sp = sweep_plan(ctx, L.dims, N, R, mixed);
+    L.sparse = is_sparse(&levels[l].z);
+    if (L.sparse) L.spt = sp_view(&levels[l].z);
+    L.sp = sweep_plan(ctx, L.dims, N, R, mixed, L.spp());
     maxpart = std::max(maxpart, L.sp.partial);
     maxy = std::max(maxy, L.sp.ydoubles);
     maxI = std::max(maxI, max_dim(L.dims, N));
@@ -1478,6 +1602,11 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
       << ctx->dimtree;
   for (int l = 0; l < nlevels; ++l) {
     key << "|" << r.lv[l].z;
+    if (r.lv[l].sparse) {
+      const SpTensor& t = r.lv[l].spt;
+      key << ",sp" << t.nnz << "," << (const void*)t.idx << "," << (const void*)t.vals;
+      for (int n = 0; n < N; ++n) key << "," << (const void*)t.rowptr[n] << "," << (const void*)t.perm[n];
+    }
     for (int n = 0; n < N; ++n) key << "," << r.lv[l].dims[n] << "," << (const void*)r.lv[l].phat[n];
   }
   for (int n = 0; n < N; ++n) key << "|" << (const void*)A->a[n] << "," << (const void*)A->a32[n];
@@ -1527,6 +1656,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
   for (int b = 0; b < nprob; ++b) {
     const cp_batch_problem& pb = probs[b];
     if ((s = check_tensor(ctx, &pb.z, true, mixed, "problem tensor")) != CP_OK) return s;
+    if ((s = require_dense(ctx, &pb.z, "cp_als_batched")) != CP_OK) return s;
     if (b == 0) N = pb.z.order;
     if (pb.z.order != N)
       return set_err(ctx, CP_ERR_SHAPE, "cp_als_batched: problem %d has order %d, problem 0 has %d", b,

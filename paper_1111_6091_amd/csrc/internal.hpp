@@ -303,6 +303,31 @@ hipError_t relax_small_launch(const SmallDesc& d, bool fp32, hipStream_t st);
 hipError_t interp_weights_launch(const double* A, const double* M, const double* grams, int N, int n,
                                  int64_t I, int Rt, int Rg, int nfit, double* w, hipStream_t st);
 
+// Sparse tensors (sparse.hip): coordinate entries with per-mode orderings
+// (cp_tensor's sparse form).
+struct SpTensor {
+  int32_t N;
+  int64_t nnz;
+  int64_t dims[kMaxOrder];
+  const int32_t* idx;                 // [nnz][N]
+  const double* vals;                 // [nnz]
+  const int64_t* rowptr[kMaxOrder];   // per mode: I_m + 1 offsets into perm[m]
+  const int32_t* perm[kMaxOrder];     // per mode: entry ids by (index, id)
+};
+// MTTKRP of mode n over the stored entries: workgroup (row i, split q) sums
+// the q-th share of row i's entries into partials [nsplit][I_n][R]; with a
+// bookkeeping workgroup in front when prep != NULL (as the dense launches).
+constexpr int32_t kSparseKind = 4;     // MttkrpPlan::kind of a sparse launch
+int sp_mttkrp_nsplit(const SpTensor& t, int n);
+hipError_t sp_mttkrp_launch(const SpTensor& t, int n, int R, const double* const* a64, double* out,
+                            int nsplit, const PrepArgs* prep, hipStream_t st);
+// dense[lin(idx_k)] = vals[k] (dense must hold zeros elsewhere)
+hipError_t sp_densify_launch(const SpTensor& t, double* dense, hipStream_t st);
+// host: per-mode orderings of the entries (cp_sparse_index); returns an error
+// code and message for bad input
+cp_status sparse_index_host(int order, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                            int64_t* rowptr, int32_t* perm, std::string* msg);
+
 // utilities
 hipError_t cast_launch(const double* src, float* dst, int64_t count, hipStream_t st);
 hipError_t norm2_launch(const double* z, int64_t count, double* part, int32_t* counter,

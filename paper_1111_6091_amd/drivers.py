@@ -61,7 +61,7 @@ def als_solve(ctx, Z, A, max_sweeps=10000, fit_tol=1e-12, chunk=16, prec=CP_FP64
     """
     torch = _torch()
     norm2 = float(Z.norm2.item())
-    fh = torch.zeros(chunk, dtype=torch.float64, device=Z.z64.device if Z.z64 is not None else "cuda")
+    fh = torch.zeros(chunk, dtype=torch.float64, device=Z.device)
     res = SolveResult()
     prev = None
     snap = A.clone() if (exact_stop and fit_tol) else None
@@ -101,7 +101,7 @@ def als_solve(ctx, Z, A, max_sweeps=10000, fit_tol=1e-12, chunk=16, prec=CP_FP64
 
 def exact_fit(ctx, Z, A):
     torch = _torch()
-    f = torch.zeros(1, dtype=torch.float64, device=Z.z64.device)
+    f = torch.zeros(1, dtype=torch.float64, device=Z.device)
     api.cp_objective(ctx, Z, A, exact=True, f=f)
     return fit_from_f(float(f.item()), float(Z.norm2.item()))
 
@@ -116,7 +116,7 @@ def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000
     """
     torch = _torch()
     norm2 = float(Z.norm2.item())
-    fh = torch.zeros(chunk32, dtype=torch.float64, device=Z.z64.device)
+    fh = torch.zeros(chunk32, dtype=torch.float64, device=Z.device)
     res = SolveResult()
     while res.sweeps < max_sweeps:
         k = min(chunk32, max_sweeps - res.sweeps)
@@ -154,8 +154,7 @@ def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False, fp64=True):
             if wl[n] is None:
                 ph.append(None)
                 continue
-            w = torch.from_numpy(np.ascontiguousarray(wl[n], dtype=np.float64)).to(cur.z64.device
-                                                                                   if cur.z64 is not None else "cuda")
+            w = torch.from_numpy(np.ascontiguousarray(wl[n], dtype=np.float64)).to(cur.device)
             p = torch.empty((d, (d + 1) // 2), dtype=torch.float64, device=w.device)
             api.cp_transfer_build(ctx, w, p)
             ph.append(p)
@@ -164,7 +163,7 @@ def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False, fp64=True):
                                      fp32=fp32 or prec == CP_MIXED)
         if prec == CP_MIXED:
             api.cp_restrict(ctx, cur, ph, nxt, CP_MIXED)
-        if nxt.z64 is not None and cur.z64 is not None:
+        if nxt.z64 is not None and (cur.z64 is not None or isinstance(cur, api.SparseTensor)):
             api.cp_restrict(ctx, cur, ph, nxt, CP_FP64)
         levels.append((cur, ph))
         cur = nxt
@@ -229,7 +228,7 @@ SETUP_NU1, SETUP_NU2, SETUP_NUC = 5, 5, 100   # Table 1
 def grad_norm(ctx, Z, A):
     """g of eq. (30) at A (device call, read back)."""
     torch = _torch()
-    g = torch.zeros(1, dtype=torch.float64, device=Z.z64.device)
+    g = torch.zeros(1, dtype=torch.float64, device=Z.device)
     api.cp_objective(ctx, Z, A, exact=True, g=g)
     return float(g.item())
 
@@ -251,6 +250,11 @@ def _relax_groups(ctx, Z, sets, sweeps):
     all sets sharing every pass over Z as column groups (cp_als_batched)."""
     if sweeps <= 0 or not sets:
         return
+    if isinstance(Z, api.SparseTensor):
+        # the batched solve takes dense tensors only: one set after the other
+        for s in sets:
+            api.cp_als_sweep(ctx, Z, s, None, sweeps, CP_SOLVE_CHOL, 10, True, CP_FP64)
+        return
     R = sets[0].rank
     P = _pack(sets)
     api.cp_als_batched(ctx, [(Z, P)], len(sets), prec=CP_FP64, tol64=0.0, max_sweeps=sweeps, chunk=sweeps)
@@ -266,7 +270,7 @@ def _level_weights(ctx, Z, fit_sets, Ic):
     phat, weights = [None] * Z.order, [None] * Z.order
     for n in Ic:
         d = Z.dims[n]
-        w = torch.empty((d, 2), dtype=torch.float64, device=Z.z64.device)
+        w = torch.empty((d, 2), dtype=torch.float64, device=Z.device)
         api.cp_interp_weights(ctx, Z, P, len(fit_sets), len(fit_sets), n, w)
         ph = torch.empty((d, (d + 1) // 2), dtype=torch.float64, device=w.device)
         api.cp_transfer_build(ctx, w, ph)
@@ -279,7 +283,7 @@ def _restrict_tensor(ctx, Z, phat):
     Zc = api.DeviceTensor.empty(cdims, fp64=True)
     api.cp_restrict(ctx, Z, phat, Zc, CP_FP64)
     torch = _torch()
-    Zc.norm2 = torch.zeros(1, dtype=torch.float64, device=Z.z64.device)
+    Zc.norm2 = torch.zeros(1, dtype=torch.float64, device=Z.device)
     api.cp_norm2(ctx, Zc, Zc.norm2)
     return Zc
 
@@ -482,3 +486,17 @@ def als_solve_g(ctx, Z, A, tau=1e-10, max_sweeps=10000, chunk=32, prec=CP_FP64):
             api.cp_als_sweep(ctx, Z, A, None, hit + 1, CP_SOLVE_CHOL, 10, True, prec)
         break
     return sweeps, hist
+
+
+def multilevel(ctx, Z, A, tfms, coarsest, tau=1e-10, max_cycles=500, setup=None, fas=None):
+    """'Multilevel' of Section 6.1 (no FMG): setup cycles stopped by eq. (32),
+    then CP-FAS solve cycles from the setup's boot factors on the setup's levels
+    until g < tau, with the one stagnation rebuild.  A and the TFMs are updated
+    in place.  Returns the dict of `multilevel_fmg` without 'fmg'."""
+    setup = dict(setup or {})
+    fas = dict(fas or {})
+    levels, _, shist = setup_phase(ctx, Z, A, tfms, coarsest, **setup)
+    levels, hist, rebuilt = solve_phase(ctx, Z, A, levels, tfms, coarsest, tau, max_cycles,
+                                        nu1_setup=setup.get("nu1", SETUP_NU1), **fas)
+    return dict(setup=shist, solve=hist, rebuilt=rebuilt, levels=len(levels),
+                iterations=len(shist) + len(hist))
