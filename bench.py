@@ -88,9 +88,10 @@ def parse():
                    help="time CP-FAS V-cycles on the 128^3 R=5 4-level hierarchy (FP64 and mixed, graph "
                         "replay off and on), then exit; for profiler runs")
     p.add_argument("--no-dense", action="store_true",
-                   help="skip the dense (i^2+j^2+k^2)^(-1/2) Multilevel + FMG vs ALS leg")
+                   help="skip the Table 3/4 legs (dense (i^2+j^2+k^2)^(-1/2) and sparse Laplacian "
+                        "tensors: Multilevel (+ FMG) vs ALS)")
     p.add_argument("--dense-only", action="store_true",
-                   help="run only the dense Multilevel + FMG vs ALS leg and print its JSON")
+                   help="run only the Table 3/4 legs and print their JSON")
     p.add_argument("--sweeps-only", action="store_true",
                    help="time the mixed and FP64 sweeps only, then exit; for profiler runs")
     p.add_argument("--cold", action="store_true",
@@ -165,7 +166,8 @@ def main():
         vcycle_timing(ctx, api, drivers, synth)
         return
     if args.dense_only:
-        print(json.dumps({"dense_table4": dense_leg(ctx, api, drivers, synth)}), flush=True)
+        print(json.dumps({"dense_table4": dense_leg(ctx, api, drivers, synth),
+                          "laplacian_table3": laplacian_leg(ctx, api, drivers, synth)}), flush=True)
         return
     Z, _, spec = synth.workload(args.workload)
     dims, R = tuple(spec["dims"]), spec["R"]
@@ -390,9 +392,10 @@ def main():
     if not args.no_multilevel:
         multilevel = fas_leg(ctx, api, drivers, synth)
         order4 = order4_leg(ctx, api, drivers, synth, K)
-    dense = None
+    dense = laplacian = None
     if not args.no_dense:
         dense = dense_leg(ctx, api, drivers, synth)
+        laplacian = laplacian_leg(ctx, api, drivers, synth)
 
     cpu = None
     if not args.no_cpu:
@@ -433,6 +436,7 @@ def main():
         "multilevel_128cube_r5": multilevel,
         "order4_64quart_r8": order4,
         "dense_table4": dense,
+        "laplacian_table3": laplacian,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -539,6 +543,70 @@ def dense_leg(ctx, api, drivers, synth, tests=(2, 6)):
                "paper_table4": TABLE4.get(t)}
         log(f"dense test {t} (s={s}, R={R}, {info['levels']} levels): Multilevel+FMG {info['iterations']} it "
             f"in {t_ml:.3f} s; ALS {sweeps} sweeps in {t_als:.3f} s; speedup {t_als / t_ml:.2f}")
+        out.append(row)
+    return out
+
+
+# Table 3 (sparse problem; same machine and averaging as Table 4): test -> ALS
+# iterations and seconds, Multilevel and Multilevel + FMG iterations and
+# seconds, levels.
+TABLE3 = {1: dict(als_it=1897, als_s=24.0, ml_it=37, ml_s=7.6, fmg_it=36, fmg_s=8.0, levs=2),
+          5: dict(als_it=5508, als_s=150.3, ml_it=182, ml_s=64.9, fmg_it=99, fmg_s=40.9, levs=4),
+          8: dict(als_it=3481, als_s=610.0, ml_it=72, ml_s=164.8, fmg_it=70, fmg_s=177.9, levs=3),
+          11: dict(als_it=1743, als_s=943.3, ml_it=39, ml_s=402.3, fmg_it=43, fmg_s=474.0, levs=3)}
+
+
+def laplacian_leg(ctx, api, drivers, synth, tests=(1, 5, 8, 11)):
+    """Section 6.2's sparse Laplacian tensors (the finest level in the sparse
+    form, coarse levels dense), FP64, first seeded run of Table 3's tests:
+    'Multilevel' and 'Multilevel + FMG' (Section 6.1, Table 1 parameters) and
+    standalone ALS from the same boot factors, all to g < 1e-10 (eq. (31)),
+    timed as in the dense leg."""
+    import torch
+    fas = dict(nu1=1, nu2=1, nuc=50, gs_iters=10)
+    out = []
+    for t in tests:
+        N, s, R = synth.LAPLACIAN_TESTS[t]
+        c = synth.laplacian_case(N, s, R)
+        Zs = api.SparseTensor.from_coo(ctx, c["idx"], c["vals"], c["shape"])
+        cdims = [s] * N
+        while any(x > c["coarsest"][n] for n, x in enumerate(cdims)):
+            cdims = [(x + 1) // 2 if x > c["coarsest"][n] else x for n, x in enumerate(cdims)]
+        row = {"test": t, "N": N, "s": s, "R": R, "nnz": int(c["vals"].shape[0])}
+        for name, fmg in (("multilevel", False), ("multilevel_fmg", True)):
+            A = api.DeviceFactors.from_numpy(ctx, c["boot"])
+            T = [api.DeviceFactors.from_numpy(ctx, x) for x in c["tfms"]]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if fmg:
+                Cd = api.DeviceFactors.from_numpy(ctx, synth.dense_coarse_start(cdims, R, c["seed"]))
+                info = drivers.multilevel_fmg(ctx, Zs, A, T, c["coarsest"], Cd, fas=fas)
+            else:
+                info = drivers.multilevel(ctx, Zs, A, T, c["coarsest"], fas=fas)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            row["levels"] = info["levels"]
+            row[name] = {"iterations": info["iterations"], "setup_cycles": len(info["setup"]),
+                         "solve_cycles": len(info["solve"]), "rebuilt": info["rebuilt"],
+                         "converged": bool(info["solve"] and info["solve"][-1] < 1e-10),
+                         "seconds": round(el, 4), "fit": drivers.exact_fit(ctx, Zs, A)}
+        B = api.DeviceFactors.from_numpy(ctx, c["boot"])
+        sweeps, gh = drivers.als_solve_g(ctx, Zs, B, tau=1e-10, max_sweeps=10000)
+        fit_als = drivers.exact_fit(ctx, Zs, B)
+        B = api.DeviceFactors.from_numpy(ctx, c["boot"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.cp_als_sweep(ctx, Zs, B, None, sweeps, 0, 10, True, 0)
+        torch.cuda.synchronize()
+        t_als = time.perf_counter() - t0
+        row["als"] = {"sweeps": sweeps, "converged": bool(gh and gh[-1] < 1e-10), "seconds": round(t_als, 4),
+                      "us_per_sweep": round(1e6 * t_als / max(sweeps, 1), 1), "fit": fit_als}
+        row["speedup"] = {k: round(t_als / row[k]["seconds"], 3) for k in ("multilevel", "multilevel_fmg")}
+        row["paper_table3"] = TABLE3.get(t)
+        log(f"laplacian test {t} (N={N}, s={s}, R={R}, nnz={row['nnz']}, {row['levels']} levels): "
+            f"Multilevel {row['multilevel']['iterations']} it {row['multilevel']['seconds']:.3f} s; "
+            f"+FMG {row['multilevel_fmg']['iterations']} it {row['multilevel_fmg']['seconds']:.3f} s; "
+            f"ALS {sweeps} sweeps {t_als:.3f} s")
         out.append(row)
     return out
 
