@@ -6,8 +6,8 @@
 // thousand entries, so one sweep is a few microseconds of arithmetic while the
 // general path spends two kernel launches per mode on it.  This kernel runs all
 // the sweeps of one relaxation in a single workgroup: it loads the level tensor
-// into LDS once, keeps the factors, their Gram matrices and Gamma in LDS, and
-// writes the factors back at the end.
+// into LDS once, keeps the factors, the right-hand sides, their Gram matrices
+// and Gamma in LDS, and writes the factors back at the end.
 //
 // Per sweep and mode n (in the order of the oracle's BNGS sweep):
 //   Gamma^(n) = Hadamard product of the Grams of the other modes (eq. (8)),
@@ -29,7 +29,7 @@ constexpr int kSmallThreads = 512;    // 8 waves, two per SIMD; leaves room for 
 
 // LDS layout (in doubles unless noted); the host computes the same offsets
 struct SmallLayout {
-  int64_t a, grams, gam, m, red, t0, dig, perm, z;   // dig: uint16, perm: int32, z: T
+  int64_t a, f, grams, gam, m, red, t0, dig, perm, z;   // dig: uint16, perm: int32, z: T
   int64_t bytes;
 };
 
@@ -44,6 +44,7 @@ __host__ __device__ inline SmallLayout small_layout(const SmallDesc& d, int esz)
   const int64_t S0 = d.P / d.dims[0];
   int64_t o = 0;
   L.a = o;      o += sumIR;
+  L.f = o;      o += sumIR;                                // right-hand sides F (zeros when absent)
   L.grams = o;  o += d.N * RR;
   L.gam = o;    o += RR;
   L.m = o;      o += imax * d.R;
@@ -56,48 +57,66 @@ __host__ __device__ inline SmallLayout small_layout(const SmallDesc& d, int esz)
   return L;
 }
 
+// p[0] + p[stride] + ... + p[(count-1) stride] from LDS with four partial sums
+// (fixed order), so that several loads are in flight instead of one.
+__device__ __forceinline__ double sum4(const double* p, int count, int stride) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+  for (; k + 3 < count; k += 4) {
+    s0 += p[k * stride];
+    s1 += p[(k + 1) * stride];
+    s2 += p[(k + 2) * stride];
+    s3 += p[(k + 3) * stride];
+  }
+  for (; k < count; ++k) s0 += p[k * stride];
+  return (s0 + s1) + (s2 + s3);
+}
+
 // Gauss-Seidel iterations on the rows i < I of X (LDS, row-major, ld R), one
-// thread per row: x Gamma = b with b = M (LDS) + F (global, optional),
+// thread per row: x Gamma = b with b = M + F (both LDS),
 //   x_r <- (b_r - sum_{k != r} x_k Gamma_kr) / Gamma_rr, r = 0..R-1, newest values,
 // a zero pivot leaving x_r as is.  RM >= R: register arrays of exactly RM
-// entries with static indices only (entries r >= R are zero and never change).
-// Per iteration the sums over k > r use the previous iterate and are formed
-// first, side by side; each new x_r is then added into the pending sums of the
-// later components, so the serial chain per component is one product, a
-// subtraction and a scaling (the division applied as a product with the
-// reciprocal pivot).
+// entries with static indices only (entries r >= R are zero and never change),
+// Gamma held in registers.  The equations are scaled by the reciprocal pivots
+// once; per iteration the terms of the previous iterate are formed first, side
+// by side, and each new x_r is then subtracted into the pending values of the
+// later components, so the serial chain per component is one product and one
+// subtraction.
 template <int RM, int NT>
-__device__ __forceinline__ void gs_rows(double* X, const double* sM, const double* __restrict__ F,
+__device__ __forceinline__ void gs_rows(double* X, const double* sM, const double* sF,
                                         const double* sG, int I, int R, int iters) {
   for (int i = threadIdx.x; i < I; i += NT) {
-    double x[RM], b[RM], dinv[RM], g[RM][RM];
+    // the equations scaled by the reciprocal pivots: c_r = b_r / Gamma_rr,
+    // h[k][r] = Gamma_kr / Gamma_rr, so that x_r = c_r - sum_{k != r} x_k h[k][r]
+    double x[RM], c[RM], h[RM][RM];
+    bool piv[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       x[r] = r < R ? X[i * R + r] : 0.0;
-      b[r] = r < R ? sM[i * R + r] + (F ? F[(int64_t)i * R + r] : 0.0) : 0.0;
       const double dg = r < R ? sG[r * R + r] : 0.0;
-      dinv[r] = dg != 0.0 ? 1.0 / dg : 0.0;
+      piv[r] = dg != 0.0;
+      const double dinv = piv[r] ? 1.0 / dg : 0.0;
+      c[r] = r < R ? (sM[i * R + r] + sF[i * R + r]) * dinv : 0.0;
+#pragma unroll
+      for (int k = 0; k < RM; ++k) h[k][r] = (k < R && r < R) ? sG[k * R + r] * dinv : 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < RM; ++k)
-#pragma unroll
-      for (int r = 0; r < RM; ++r) g[k][r] = (k < R && r < R) ? sG[k * R + r] : 0.0;
     for (int it = 0; it < iters; ++it) {
-      double up[RM], lo[RM];
+      // t_r = c_r - (terms of the previous iterate, k > r), side by side;
+      // then each new x_r enters the pending t_j, j > r (one product and
+      // subtraction per step of the serial chain)
+      double t[RM];
 #pragma unroll
       for (int r = 0; r < RM; ++r) {
-        double t = 0.0;
+        double u = 0.0;
 #pragma unroll
-        for (int k = r + 1; k < RM; ++k) t += x[k] * g[k][r];
-        up[r] = t;
-        lo[r] = 0.0;
+        for (int k = r + 1; k < RM; ++k) u += x[k] * h[k][r];
+        t[r] = c[r] - u;
       }
 #pragma unroll
       for (int r = 0; r < RM; ++r) {
-        const double v = (b[r] - (up[r] + lo[r])) * dinv[r];
-        x[r] = (r < R && dinv[r] != 0.0) ? v : x[r];
+        x[r] = piv[r] ? t[r] : x[r];
 #pragma unroll
-        for (int j = r + 1; j < RM; ++j) lo[j] += x[r] * g[r][j];
+        for (int j = r + 1; j < RM; ++j) t[j] -= x[r] * h[r][j];
       }
     }
 #pragma unroll
@@ -106,18 +125,38 @@ __device__ __forceinline__ void gs_rows(double* X, const double* sM, const doubl
   }
 }
 
+// The same iterations for 8 < R <= 16 with plain loops over LDS (x in place
+// in X): register arrays of 12 or 16 entries would push the whole kernel's
+// register count into spills.
 template <int NT>
-__device__ __forceinline__ void gs_rows_any(double* X, const double* sM, const double* F,
+__device__ __forceinline__ void gs_rows_lds(double* X, const double* sM, const double* sF,
+                                            const double* sG, int I, int R, int iters) {
+  for (int i = threadIdx.x; i < I; i += NT) {
+    double* x = X + i * R;
+    for (int it = 0; it < iters; ++it)
+      for (int r = 0; r < R; ++r) {
+        const double dg = sG[r * R + r];
+        if (dg == 0.0) continue;
+        const double dinv = 1.0 / dg;
+        double t = (sM[i * R + r] + sF[i * R + r]) * dinv;
+        for (int k = 0; k < R; ++k)
+          if (k != r) t -= x[k] * (sG[k * R + r] * dinv);
+        x[r] = t;
+      }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void gs_rows_any(double* X, const double* sM, const double* sF,
                                             const double* sG, int I, int R, int iters) {
   switch (R) {
-    case 1: case 2: gs_rows<2, NT>(X, sM, F, sG, I, R, iters); break;
-    case 3: gs_rows<3, NT>(X, sM, F, sG, I, R, iters); break;
-    case 4: gs_rows<4, NT>(X, sM, F, sG, I, R, iters); break;
-    case 5: gs_rows<5, NT>(X, sM, F, sG, I, R, iters); break;
-    case 6: gs_rows<6, NT>(X, sM, F, sG, I, R, iters); break;
-    case 7: case 8: gs_rows<8, NT>(X, sM, F, sG, I, R, iters); break;
-    case 9: case 10: case 11: case 12: gs_rows<12, NT>(X, sM, F, sG, I, R, iters); break;
-    default: gs_rows<16, NT>(X, sM, F, sG, I, R, iters); break;
+    case 1: case 2: gs_rows<2, NT>(X, sM, sF, sG, I, R, iters); break;
+    case 3: gs_rows<3, NT>(X, sM, sF, sG, I, R, iters); break;
+    case 4: gs_rows<4, NT>(X, sM, sF, sG, I, R, iters); break;
+    case 5: gs_rows<5, NT>(X, sM, sF, sG, I, R, iters); break;
+    case 6: gs_rows<6, NT>(X, sM, sF, sG, I, R, iters); break;
+    case 7: case 8: gs_rows<8, NT>(X, sM, sF, sG, I, R, iters); break;
+    default: gs_rows_lds<NT>(X, sM, sF, sG, I, R, iters); break;
   }
 }
 
@@ -127,6 +166,7 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
   const SmallLayout L = small_layout(d, (int)sizeof(T));
   const int N = d.N, R = d.R, RR = R * R, tid = threadIdx.x;
   double* sA = sm + L.a;
+  double* sF = sm + L.f;
   double* sGr = sm + L.grams;
   double* sG = sm + L.gam;
   double* sM = sm + L.m;
@@ -169,7 +209,10 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
     }
   }
   for (int m = 0; m < N; ++m)
-    for (int idx = tid; idx < I[m] * R; idx += kSmallThreads) sA[offA[m] + idx] = d.A[m][idx];
+    for (int idx = tid; idx < I[m] * R; idx += kSmallThreads) {
+      sA[offA[m] + idx] = d.A[m][idx];
+      sF[offA[m] + idx] = d.F[m] ? d.F[m][idx] : 0.0;
+    }
   // index tables, built once: the digits of every fibre, and for each mode
   // n >= 1 the fibres listed by their digit s_n (the other digits in
   // increasing mixed-radix order)
@@ -202,16 +245,19 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
       double acc = 0.0;
       if (idx < RR && g < GG) {
         const int r = idx / R, c = idx % R;
-        for (int i = g; i < I[m]; i += GG) acc += a[i * R + r] * a[i * R + c];
+        double a2 = 0.0;
+        int i = g;
+        for (; i + GG < I[m]; i += 2 * GG) {
+          acc += a[i * R + r] * a[i * R + c];
+          a2 += a[(i + GG) * R + r] * a[(i + GG) * R + c];
+        }
+        if (i < I[m]) acc += a[i * R + r] * a[i * R + c];
+        acc += a2;
       }
       if (GG > 1) {
         if (idx < RR && g < GG) sRed[g * RR + idx] = acc;
         __syncthreads();
-        if (tid < RR) {
-          double t = 0.0;
-          for (int gg = 0; gg < GG; ++gg) t += sRed[gg * RR + tid];
-          sGr[m * RR + tid] = t;
-        }
+        if (tid < RR) sGr[m * RR + tid] = sum4(sRed + tid, GG, RR);
         __syncthreads();
       } else if (idx < RR) {
         sGr[m * RR + idx] = acc;
@@ -252,41 +298,43 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
         if (live) {
           const int i = q % I[n], r = q / I[n];
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
+          // four accumulators with static indices (a runtime index would
+          // move the array out of registers)
           if (n == 0) {
             int s = g;
             for (; s + 3 * G < S0; s += 4 * G)
 #pragma unroll
               for (int u = 0; u < 4; ++u)
                 a4[u] += (double)sZ[(s + u * G) * I0 + i] * sT0[(s + u * G) * R + r];
-            for (int u = 0; s < S0; s += G, ++u) a4[u] += (double)sZ[s * I0 + i] * sT0[s * R + r];
+            for (; s < S0; s += G) a4[0] += (double)sZ[s * I0 + i] * sT0[s * R + r];
           } else {
             const int32_t* pr = sPerm + (n - 1) * S0 + i * rest;
-            int k = g;
-            for (int u = 0; k < rest; k += G, u = (u + 1) & 3) {
+            auto term = [&](int k) {
               const int s = pr[k];
               double w = sT0[s * R + r];
               for (int m = 1; m < N; ++m)
                 if (m != n) w *= sA[offA[m] + sDig[s * NM + m - 1] * R + r];
-              a4[u] += w;
-            }
+              return w;
+            };
+            int k = g;
+            for (; k + 3 * G < rest; k += 4 * G)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) a4[u] += term(k + u * G);
+            for (; k < rest; k += G) a4[0] += term(k);
           }
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
         if (pairs < kSmallThreads) {
           if (live) sRed[g * pairs + q] = acc;
           __syncthreads();
-          if (tid < pairs) {
-            double t = 0.0;
-            for (int gg = 0; gg < G; ++gg) t += sRed[gg * pairs + tid];
-            sM[(tid % I[n]) * R + tid / I[n]] = t;
-          }
+          if (tid < pairs) sM[(tid % I[n]) * R + tid / I[n]] = sum4(sRed + tid, G, pairs);
         } else if (q < pairs) {
           sM[(q % I[n]) * R + q / I[n]] = acc;
         }
       }
       __syncthreads();
       // Gauss-Seidel on the rows of A^(n), one thread per row
-      gs_rows_any<kSmallThreads>(sA + offA[n], sM, d.F[n], sG, I[n], R, d.gs_iters);
+      gs_rows_any<kSmallThreads>(sA + offA[n], sM, sF + offA[n], sG, I[n], R, d.gs_iters);
       __syncthreads();
       gram(n);
       if (n == 0 && N > 1) {
@@ -295,14 +343,16 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
           const int s = idx / R, r = idx - (idx / R) * R;
           const T* zf = sZ + s * I0;
           const double* a0 = sA + offA[0];
-          double t0 = 0.0, t1 = 0.0;
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
           int i0 = 0;
-          for (; i0 + 1 < I0; i0 += 2) {
+          for (; i0 + 3 < I0; i0 += 4) {
             t0 += (double)zf[i0] * a0[i0 * R + r];
             t1 += (double)zf[i0 + 1] * a0[(i0 + 1) * R + r];
+            t2 += (double)zf[i0 + 2] * a0[(i0 + 2) * R + r];
+            t3 += (double)zf[i0 + 3] * a0[(i0 + 3) * R + r];
           }
-          if (i0 < I0) t0 += (double)zf[i0] * a0[i0 * R + r];
-          sT0[idx] = t0 + t1;
+          for (; i0 < I0; ++i0) t0 += (double)zf[i0] * a0[i0 * R + r];
+          sT0[idx] = (t0 + t1) + (t2 + t3);
         }
       }
       __syncthreads();
