@@ -92,6 +92,8 @@ def parse():
                         "tensors: Multilevel (+ FMG) vs ALS)")
     p.add_argument("--dense-only", action="store_true",
                    help="run only the Table 3/4 legs and print their JSON")
+    p.add_argument("--restrict-only", action="store_true",
+                   help="time only the coarse-tensor restrictions and print their JSON")
     p.add_argument("--sweeps-only", action="store_true",
                    help="time the mixed and FP64 sweeps only, then exit; for profiler runs")
     p.add_argument("--cold", action="store_true",
@@ -164,6 +166,9 @@ def main():
     K, W = args.steps, args.warmup
     if args.vcycles_only:
         vcycle_timing(ctx, api, drivers, synth)
+        return
+    if args.restrict_only:
+        print(json.dumps({"restriction": restrict_leg(ctx, api, synth)}), flush=True)
         return
     if args.dense_only:
         print(json.dumps({"dense_table4": dense_leg(ctx, api, drivers, synth),
@@ -389,7 +394,9 @@ def main():
 
     multilevel = None
     order4 = None
+    restriction = None
     if not args.no_multilevel:
+        restriction = restrict_leg(ctx, api, synth)
         multilevel = fas_leg(ctx, api, drivers, synth)
         order4 = order4_leg(ctx, api, drivers, synth, K)
     dense = laplacian = None
@@ -435,6 +442,7 @@ def main():
         "batched": batched,
         "multilevel_128cube_r5": multilevel,
         "order4_64quart_r8": order4,
+        "restriction": restriction,
         "dense_table4": dense,
         "laplacian_table3": laplacian,
         "cpu_baseline": cpu,
@@ -608,6 +616,66 @@ def laplacian_leg(ctx, api, drivers, synth, tests=(1, 5, 8, 11)):
             f"+FMG {row['multilevel_fmg']['iterations']} it {row['multilevel_fmg']['seconds']:.3f} s; "
             f"ALS {sweeps} sweeps {t_als:.3f} s")
         out.append(row)
+    return out
+
+
+def restrict_leg(ctx, api, synth, reps=20):
+    """Coarse-tensor construction eq. (15) as dense P^T GEMMs on the matrix
+    cores, every mode coarsened: 256^3 -> 128^3 (FP32, the 256^3 tensor's
+    shadow) and 128^3 -> 64^3 (FP64), linear-interpolation P^.  Algorithmic
+    flops: sum over modes of 2 I_c I (rest of the current tensor); algorithmic
+    bytes: each mode product reads its input and writes its output once."""
+    import numpy as np
+    import torch
+    from paper_1111_6091_amd._lib import CP_FP64, CP_MIXED
+    out = {}
+    for name, prec, b, peak in (("c3_256cube_r10", CP_MIXED, 4, 157.3), ("c2_128cube_r5", CP_FP64, 8, 78.6)):
+        Z, _, spec = synth.workload(name)
+        dims = list(Z.shape)
+        Zd = api.DeviceTensor.from_numpy(ctx, Z, fp32=prec == CP_MIXED)
+        phat = []
+        for d in dims:
+            w = torch.from_numpy(synth.linear_interp_weights(d)).cuda()
+            ph = torch.empty((d, (d + 1) // 2), dtype=torch.float64, device="cuda")
+            api.cp_transfer_build(ctx, w, ph)
+            phat.append(ph)
+        cdims = [(d + 1) // 2 for d in dims]
+        Zc = api.DeviceTensor.empty(cdims, fp64=prec == CP_FP64, fp32=prec == CP_MIXED)
+        flops, byts, cur = 0.0, 0.0, list(dims)
+        for n in range(len(dims)):
+            rest = float(np.prod(cur)) / cur[n]
+            flops += 2.0 * cdims[n] * cur[n] * rest
+            byts += b * (np.prod(cur) + cdims[n] * rest)
+            cur[n] = cdims[n]
+        wd = [torch.from_numpy(synth.linear_interp_weights(d)).cuda() for d in dims]
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e3 / reps
+
+        us = timed(lambda: api.cp_restrict(ctx, Zd, phat, Zc, prec))
+        usf = timed(lambda: api.cp_restrict_factored(ctx, Zd, wd, Zc, prec))
+        tf = flops / (us * 1e-6) / 1e12
+        out[name] = {"dims": dims, "coarse": cdims, "prec": "mixed (FP32 storage)" if prec == CP_MIXED else "fp64",
+                     "dense_gemm": {"us": round(us, 2), "gflop": round(flops / 1e9, 3), "tflops": round(tf, 2),
+                                    "frac_of_mfma_peak": round(tf / peak, 4),
+                                    "gbs": round(byts / (us * 1e-6) / 1e9, 1)},
+                     "factored": {"us": round(usf, 2), "gbs": round(byts / (usf * 1e-6) / 1e9, 1),
+                                  "frac_of_hbm_peak": round(byts / (usf * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "mb": round(byts / 1e6, 1),
+                     "note": "mb: each mode product reads its input and writes its output once; the dense "
+                             "form does 2 I_c flops per input entry (matrix cores), the factored form about 5 "
+                             "flops per coarse entry (HBM-bound)"}
+        log(f"restriction {name}: dense GEMM {us:.1f} us ({tf:.1f} TFLOP/s, {tf / peak:.3f} of {peak}), "
+            f"factored {usf:.1f} us ({byts / (usf * 1e-6) / 1e9:.0f} GB/s)")
     return out
 
 

@@ -259,6 +259,18 @@ cp_status cp_objective(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, int3
 cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[CP_MAX_ORDER],
                       cp_tensor* Zc, cp_prec prec);
 
+/* The same coarse tensor eq. (15) in factored form: with P^^T = L^{-1} P^T
+ * (Section 4.1), each coarsened mode applies the interpolation stencil P^T
+ * (three terms per coarse entry) and then forward substitution with the
+ * bidiagonal Cholesky factor L of B = P^T P: one pass over the tensor and
+ * about five flops per coarse entry, against 2 I_c flops of the dense GEMM.
+ * w[n]: the interpolation weights of mode n as taken by cp_transfer_build
+ * (I_n x 2, device), or NULL (identity).  Arithmetic is FP64 whatever the
+ * storage; CP_MIXED reads Z->z32 and writes Zc->z32.  Sparse Z (FP64): as
+ * cp_restrict.  Errors: as cp_restrict; a coarsened mode of extent < 2. */
+cp_status cp_restrict_factored(cp_ctx ctx, const cp_tensor* Z, const double* const w[CP_MAX_ORDER],
+                               cp_tensor* Zc, cp_prec prec);
+
 /* Prolongation.  Ac_tilde == NULL: A = P^ Ac (eq. (18), coarse-grid correction
  * of the setup phase); else A += P^ (Ac - Ac_tilde) (eq. (28), FAS).  phat:
  * I x Ic row-major; Ac, Ac_tilde: Ic x R; A: I x R; all FP64.  With phat ==

@@ -92,6 +92,8 @@ SIGNATURES = {
                      c_vp, c_i32],
     "cp_restrict": [c_vp, ctypes.POINTER(CpTensor), c_vp * CP_MAX_ORDER, ctypes.POINTER(CpTensor),
                     c_i32],
+    "cp_restrict_factored": [c_vp, ctypes.POINTER(CpTensor), c_vp * CP_MAX_ORDER, ctypes.POINTER(CpTensor),
+                             c_i32],
     "cp_prolong": [c_vp, c_i64, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp],
     "cp_restrict_factor": [c_vp, c_i64, c_i64, c_i32, c_vp, c_vp, c_vp],
     "cp_transfer_build": [c_vp, c_i64, c_vp, c_vp],

@@ -295,6 +295,13 @@ def cp_restrict(ctx, Z, phat, Zc, prec=CP_FP64):
                                    prec))
 
 
+def cp_restrict_factored(ctx, Z, w, Zc, prec=CP_FP64):
+    """w: per mode (I_n x 2) device weights or None (identity)."""
+    zs, cs = Z.struct(), Zc.struct()
+    ctx.check(ctx._lib.cp_restrict_factored(ctx.handle, ctypes.byref(zs), _phat_array(w), ctypes.byref(cs),
+                                            prec))
+
+
 def cp_prolong(ctx, phat, Ac, Ac_tilde, A):
     I, R = A.shape
     Ic = Ac.shape[0]

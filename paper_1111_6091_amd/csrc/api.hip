@@ -400,12 +400,14 @@ SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32,
   for (int m = 0; m < N; ++m) P *= dims[m];
   const size_t yd = (size_t)S * dims[1] * R;
   if (yd * 8 * 4 > (size_t)P * (fp32 ? 4 : 8)) return sp;
-  sp.dimtree = true;
-  sp.ydoubles = yd;
   PlanOpts o = sp.p[1].opts;
   o.ksplit = 1;
   o.nostage = 0;   // the tile-storing variant is tuned with the factor staged
-  sp.p1y = mttkrp_plan(N, dims, 1, R, fp32, o);
+  const MttkrpPlan p1y = mttkrp_plan(N, dims, 1, R, fp32, o);
+  if (p1y.ksplit != 1) return sp;   // Y needs the whole contraction in one piece
+  sp.dimtree = true;
+  sp.ydoubles = yd;
+  sp.p1y = p1y;
   sp.partial = std::max(sp.partial, sp.p1y.partial_doubles);
   sp.ynsplit.assign(N, 0);
   for (int n = 2; n < N; ++n) {
@@ -1007,6 +1009,93 @@ cp_status cp_restrict(cp_ctx ctx, const cp_tensor* Z, const double* const phat[C
     }
     TRY(gemm_chunked(ctx, g, mixed));
     cur[n] = Ic;
+    in = outp;
+  }
+  return CP_OK;
+}
+
+cp_status cp_restrict_factored(cp_ctx ctx, const cp_tensor* Z, const double* const w[CP_MAX_ORDER],
+                               cp_tensor* Zc, cp_prec prec) {
+  if (!ctx) return CP_ERR_INVALID;
+  cp_status s = check_prec(ctx, prec);
+  if (s != CP_OK) return s;
+  const bool mixed = prec == CP_MIXED;
+  if ((s = check_tensor(ctx, Z, !mixed, mixed, "Z")) != CP_OK) return s;
+  if (!Zc) return set_err(ctx, CP_ERR_INVALID, "Zc is NULL");
+  if (!w) return set_err(ctx, CP_ERR_INVALID, "weights array is NULL");
+  const int N = Z->order;
+  if (Zc->order != N) return set_err(ctx, CP_ERR_SHAPE, "Zc order %d != %d", Zc->order, N);
+  if (mixed ? !Zc->z32 : !Zc->z64) return set_err(ctx, CP_ERR_INVALID, "Zc has no output buffer for this precision");
+  if (Zc->nnz != 0) return set_err(ctx, CP_ERR_INVALID, "Zc must be in the dense form");
+  int64_t dc[CP_MAX_ORDER];
+  std::vector<int> modes;
+  for (int m = 0; m < N; ++m) {
+    if (w[m] && Z->dims[m] < 2)
+      return set_err(ctx, CP_ERR_SHAPE, "mode %d: extent %lld cannot be coarsened", m, (long long)Z->dims[m]);
+    dc[m] = w[m] ? (Z->dims[m] + 1) / 2 : Z->dims[m];
+    if (Zc->dims[m] != dc[m])
+      return set_err(ctx, CP_ERR_SHAPE, "Zc->dims[%d] = %lld, expected %lld", m,
+                     (long long)Zc->dims[m], (long long)dc[m]);
+    if (w[m]) modes.push_back(m);
+  }
+  const size_t esz = mixed ? 4 : 8;
+  const void* src = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
+  void* dst = mixed ? (void*)Zc->z32 : (void*)Zc->z64;
+  const int64_t P = numel(Z);
+  const bool sparse = is_sparse(Z);
+  if (modes.empty()) {
+    if (sparse) {
+      HIPCHK(fill_launch((double*)dst, 0.0, P, ctx->stream));
+      HIPCHK(sp_densify_launch(sp_view(Z), (double*)dst, ctx->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(dst, src, P * esz, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return CP_OK;
+  }
+  int64_t cur[CP_MAX_ORDER];
+  for (int m = 0; m < N; ++m) cur[m] = Z->dims[m];
+  size_t maxmid = 0;
+  for (size_t q = 0; q + 1 < modes.size(); ++q) {
+    cur[modes[q]] = dc[modes[q]];
+    int64_t p = 1;
+    for (int m = 0; m < N; ++m) p *= cur[m];
+    maxmid = std::max(maxmid, (size_t)p);
+  }
+  Sizer sz;
+  if (sparse) sz.take<double>((size_t)P);
+  sz.take<char>(maxmid * esz);
+  sz.take<char>(maxmid * esz);
+  for (int m : modes) sz.take<double>((size_t)6 * dc[m]);
+  if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
+  Arena ar(ctx->ws);
+  double* dense = sparse ? ar.take<double>((size_t)P) : nullptr;
+  char* buf[2] = {ar.take<char>(maxmid * esz), ar.take<char>(maxmid * esz)};
+  double* coef[CP_MAX_ORDER] = {};
+  RCoefJobs jobs{};
+  for (int m : modes) {
+    coef[m] = ar.take<double>((size_t)6 * dc[m]);   // 4 Ic coefficients + 2 Ic scratch
+    const int q = jobs.count++;
+    jobs.I[q] = Z->dims[m];
+    jobs.w[q] = w[m];
+    jobs.coef[q] = coef[m];
+    jobs.scratch[q] = coef[m] + 4 * dc[m];
+  }
+  HIPCHK(restrict_coef_launch(jobs, ctx->stream));
+  if (sparse) {
+    HIPCHK(fill_launch(dense, 0.0, P, ctx->stream));
+    HIPCHK(sp_densify_launch(sp_view(Z), dense, ctx->stream));
+    src = dense;
+  }
+  for (int m = 0; m < N; ++m) cur[m] = Z->dims[m];
+  const void* in = src;
+  for (size_t q = 0; q < modes.size(); ++q) {
+    const int n = modes[q];
+    void* outp = (q + 1 == modes.size()) ? dst : (void*)buf[q & 1];
+    int64_t L = 1, T = 1;
+    for (int m = 0; m < n; ++m) L *= cur[m];
+    for (int m = n + 1; m < N; ++m) T *= cur[m];
+    HIPCHK(restrict_factored_launch(in, outp, L, cur[n], T, coef[n], mixed, ctx->stream));
+    cur[n] = dc[n];
     in = outp;
   }
   return CP_OK;

@@ -342,6 +342,19 @@ hipError_t prolong_launch(int64_t I, int64_t Ic, int R, const double* phat, cons
                           const double* Act, double* A, hipStream_t st);
 hipError_t restrict_factor_launch(int64_t I, int64_t Ic, int R, const double* phat,
                                   const double* A, double* Ac, hipStream_t st);
+// factored restriction (transfer.hip): coefficients of every coarsened mode
+// from its interpolation weights (one launch), then per mode the stencil +
+// bidiagonal solve over a tensor viewed as (Lead, I, Tail)
+struct RCoefJobs {                 // one entry per coarsened mode
+  int32_t count;
+  int64_t I[kMaxOrder];
+  const double* w[kMaxOrder];
+  void* coef[kMaxOrder];           // 4 Ic doubles
+  double* scratch[kMaxOrder];      // 2 Ic doubles
+};
+hipError_t restrict_coef_launch(const RCoefJobs& jobs, hipStream_t st);
+hipError_t restrict_factored_launch(const void* in, void* out, int64_t Lead, int64_t I, int64_t Tail,
+                                    const void* coef, bool fp32, hipStream_t st);
 // Fc = Hc + P^^T (F - H)   (F may be NULL = 0)
 hipError_t fas_rhs_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* F,
                           const double* H, const double* Hc, double* Fc, hipStream_t st);

@@ -204,7 +204,10 @@ MttkrpPlan mttkrp_plan(int N, const int64_t* dims, int n, int R, bool fp32, cons
       ks = ceil_div(target * 4, (int64_t)p.ngroups * base_units);
   }
   ks = std::max<int64_t>(1, std::min<int64_t>(ks, kchunks));
-  const int64_t kchunk = ceil_div(kchunks, ks) * kgran;
+  int64_t kchunk = ceil_div(kchunks, ks) * kgran;
+  // FP32 accumulates one contraction piece in the matrix cores and adds the
+  // pieces in FP64: pieces of at most 256 keep the error within 256 u32
+  while (fp32 && kchunk > 256 && ks < kchunks) kchunk = ceil_div(kchunks, ++ks) * kgran;
   ks = ceil_div(K, kchunk);
   p.ksplit = (int32_t)ks;
   p.kchunk = (int32_t)kchunk;

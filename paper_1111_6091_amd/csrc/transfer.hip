@@ -17,26 +17,72 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // when i+1 < I, from (i+1)/2 (weight w[i][1]).  B = P^T P is tridiagonal:
 //   B_jj = 1 + w[2j-1][1]^2 + w[2j+1][0]^2,   B_{j,j+1} = w[2j+1][0] w[2j+1][1]
 // (terms whose row does not exist or has a single neighbour vanish).
+// B, then its bidiagonal Cholesky factor L (diagonal ldiag[j], subdiagonal
+// lsub[j] = L_{j, j-1}; lsub[0] = 0).  Every thread of the block calls it: the
+// entries of B are formed side by side (into sB, 2 Ic doubles, or read from w
+// on the fly when sB is NULL), then one thread runs the sequential recurrence
+// l_jj = sqrt(B_jj - l_{j,j-1}^2), l_{j+1,j} = B_{j,j+1} / l_jj with the
+// entries of B eight at a time ahead of the chain; the block is synchronized
+// on return.
+__device__ inline double bdiag(int64_t I, const double* w, int64_t j) {
+  double b = 1.0;
+  if (j >= 1) b += w[(2 * j - 1) * 2 + 1] * w[(2 * j - 1) * 2 + 1];
+  if (2 * j + 1 < I) b += w[(2 * j + 1) * 2 + 0] * w[(2 * j + 1) * 2 + 0];
+  return b;
+}
+__device__ inline double boff(int64_t I, const double* w, int64_t j) {   // B_{j, j+1}
+  return 2 * j + 2 < I ? w[(2 * j + 1) * 2 + 0] * w[(2 * j + 1) * 2 + 1] : 0.0;
+}
+
+__device__ inline void bidiag_chol(int64_t I, const double* __restrict__ w, double* __restrict__ ldiag,
+                                   double* __restrict__ lsub, double* sB) {
+  const int64_t Ic = (I + 1) / 2;
+  if (sB) {
+    for (int64_t j = threadIdx.x; j < Ic; j += blockDim.x) {
+      sB[j] = bdiag(I, w, j);
+      sB[Ic + j] = boff(I, w, j);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double prev_sub = 0.0;
+    lsub[0] = 0.0;
+    for (int64_t j0 = 0; j0 < Ic; j0 += 8) {
+      double bd[8], bo[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + u;
+        bd[u] = j < Ic ? (sB ? sB[j] : bdiag(I, w, j)) : 1.0;
+        bo[u] = j < Ic ? (sB ? sB[Ic + j] : boff(I, w, j)) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + u;
+        if (j >= Ic) break;
+        const double ljj = sqrt(bd[u] - prev_sub * prev_sub);
+        ldiag[j] = ljj;
+        prev_sub = (j + 1 < Ic) ? bo[u] / ljj : 0.0;
+        if (j + 1 < Ic) lsub[j + 1] = prev_sub;   // L_{j+1, j}
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// LDS for the entries of B when they fit (else they are formed on the fly)
+constexpr int64_t kBidiagLdsMax = 4096;   // coarse extent
+inline size_t bidiag_smem(int64_t I) {
+  const int64_t Ic = (I + 1) / 2;
+  return Ic <= kBidiagLdsMax ? (size_t)(2 * Ic) * sizeof(double) : 0;
+}
+
 __global__ __launch_bounds__(kThreads) void transfer_kernel(int64_t I, const double* __restrict__ w,
                                                             double* __restrict__ phat,
                                                             double* __restrict__ ldiag,
                                                             double* __restrict__ lsub) {
+  extern __shared__ double sB[];
   const int64_t Ic = (I + 1) / 2;
-  // B, then its bidiagonal Cholesky factor (sequential recurrence)
-  if (threadIdx.x == 0) {
-    double prev_sub = 0.0;
-    for (int64_t j = 0; j < Ic; ++j) {
-      double bjj = 1.0;
-      if (j >= 1) bjj += w[(2 * j - 1) * 2 + 1] * w[(2 * j - 1) * 2 + 1];
-      if (2 * j + 1 < I) bjj += w[(2 * j + 1) * 2 + 0] * w[(2 * j + 1) * 2 + 0];
-      const double ljj = sqrt(bjj - prev_sub * prev_sub);
-      ldiag[j] = ljj;
-      double bnext = 0.0;
-      if (2 * j + 2 < I) bnext = w[(2 * j + 1) * 2 + 0] * w[(2 * j + 1) * 2 + 1];
-      prev_sub = (j + 1 < Ic) ? bnext / ljj : 0.0;
-      if (j + 1 < Ic) lsub[j + 1] = prev_sub;   // L_{j+1, j}
-    }
-  }
+  bidiag_chol(I, w, ldiag, lsub, Ic <= kBidiagLdsMax ? sB : nullptr);
   __syncthreads();
   // row i of P^: y = L^{-1} p_i (forward substitution on the bidiagonal L)
   for (int64_t i = threadIdx.x; i < I; i += kThreads) {
@@ -65,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void transfer_kernel(int64_t I, const dou
 hipError_t transfer_build_launch(int64_t I, const double* w, double* phat, double* ws,
                                  hipStream_t st) {
   const int64_t Ic = (I + 1) / 2;
-  hipLaunchKernelGGL(transfer_kernel, dim3(1), dim3(kThreads), 0, st, I, w, phat, ws, ws + Ic);
+  hipLaunchKernelGGL(transfer_kernel, dim3(1), dim3(kThreads), bidiag_smem(I), st, I, w, phat, ws, ws + Ic);
   return hipGetLastError();
 }
 
@@ -252,6 +298,168 @@ hipError_t gemm_launch(const GemmDesc& d, bool fp32, hipStream_t st) {
   dim3 grid((unsigned)((d.M + 63) / 64), (unsigned)((d.N + 63) / 64), (unsigned)d.batch);
   if (fp32) hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(kThreads), 0, st, d);
   else hipLaunchKernelGGL(gemm_kernel<double>, grid, dim3(kThreads), 0, st, d);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Factored restriction along one mode: Zc = Z x_n P^^T with P^^T = L^{-1} P^T,
+// applied as the interpolation stencil (y_j = z_2j + w[2j-1][1] z_2j-1 +
+// w[2j+1][0] z_2j+1) followed by forward substitution with the bidiagonal L:
+//   x_j = a_j x_{j-1} + c0_j z_2j-1 + c1_j z_2j + c2_j z_2j+1,
+// a_j = -L_{j,j-1} / L_jj, c1_j = 1 / L_jj, c0_j = w[2j-1][1] c1_j,
+// c2_j = w[2j+1][0] c1_j (zero where the neighbour does not exist): about five
+// flops per coarse entry and one pass over the input.  The tensor is viewed as
+// (Lead, I, Tail); a column is one (lead, tail) pair.
+//   Lead >= 64: a lane per column (64 consecutive columns per wave, coalesced),
+//               the recurrence run down the column;
+//   Lead < 64:  a wave per column, lanes along j: the stencil values side by
+//               side, then the first-order recurrence as an inclusive scan of
+//               the affine maps x -> a_j x + b_j across the wave (six
+//               shuffle rounds per 64 coarse entries), carried between blocks.
+// coef: Ic entries of {c0, c1, c2, a}.
+struct RCoef {
+  double c0, c1, c2, a;
+};
+
+// one block per coarsened mode
+__global__ __launch_bounds__(kThreads) void restrict_coef_kernel(RCoefJobs jobs) {
+  extern __shared__ double sB[];
+  const int q = blockIdx.x;
+  const int64_t I = jobs.I[q];
+  const double* __restrict__ w = jobs.w[q];
+  RCoef* __restrict__ coef = (RCoef*)jobs.coef[q];
+  const int64_t Ic = (I + 1) / 2;
+  double* ldiag = jobs.scratch[q];
+  double* lsub = ldiag + Ic;
+  bidiag_chol(I, w, ldiag, lsub, Ic <= kBidiagLdsMax ? sB : nullptr);
+  for (int64_t j = threadIdx.x; j < Ic; j += blockDim.x) {
+    const double inv = 1.0 / ldiag[j];
+    RCoef c;
+    c.c1 = inv;
+    c.c0 = j >= 1 ? w[(2 * j - 1) * 2 + 1] * inv : 0.0;
+    c.c2 = 2 * j + 1 < I ? w[(2 * j + 1) * 2 + 0] * inv : 0.0;
+    c.a = j >= 1 ? -lsub[j] * inv : 0.0;
+    coef[j] = c;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void restrict_cols_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                 int64_t Lead, int64_t I, int64_t Ic, int64_t Tail,
+                                                                 const RCoef* __restrict__ coef) {
+  constexpr int JB = 128;   // coarse entries whose coefficients sit in LDS at a time
+  __shared__ RCoef sc[JB];
+  const int64_t col = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool live = col < Lead * Tail;
+  const int64_t l = live ? col % Lead : 0, t = live ? col / Lead : 0;
+  const T* zin = in + l + Lead * I * t;
+  T* zout = out + l + Lead * Ic * t;
+  double x = 0.0, zprev = 0.0;
+  for (int64_t jb = 0; jb < Ic; jb += JB) {
+    const int nj = (int)min((int64_t)JB, Ic - jb);
+    __syncthreads();
+    if (threadIdx.x < nj) sc[threadIdx.x] = coef[jb + threadIdx.x];
+    __syncthreads();
+    if (!live) continue;
+    int k = 0;
+    for (; k + 8 <= nj; k += 8) {
+      double z0[8], z1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = jb + k + u;
+        z0[u] = (double)zin[Lead * (2 * j)];
+        z1[u] = 2 * j + 1 < I ? (double)zin[Lead * (2 * j + 1)] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const RCoef c = sc[k + u];
+        x = c.a * x + (c.c0 * zprev + c.c1 * z0[u] + c.c2 * z1[u]);
+        zprev = z1[u];
+        zout[Lead * (jb + k + u)] = (T)x;
+      }
+    }
+    for (; k < nj; ++k) {
+      const int64_t j = jb + k;
+      const double z0 = (double)zin[Lead * (2 * j)];
+      const double z1 = 2 * j + 1 < I ? (double)zin[Lead * (2 * j + 1)] : 0.0;
+      const RCoef c = sc[k];
+      x = c.a * x + (c.c0 * zprev + c.c1 * z0 + c.c2 * z1);
+      zprev = z1;
+      zout[Lead * j] = (T)x;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void restrict_scan_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                 int64_t Lead, int64_t I, int64_t Ic, int64_t Tail,
+                                                                 const RCoef* __restrict__ coef) {
+  const int lane = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (col >= Lead * Tail) return;   // whole waves leave together
+  const int64_t l = col % Lead, t = col / Lead;
+  const T* zin = in + l + Lead * I * t;
+  T* zout = out + l + Lead * Ic * t;
+  double carry = 0.0;
+  for (int64_t jb = 0; jb < Ic; jb += 64) {
+    const int64_t j = jb + lane;
+    double A = 1.0, B = 0.0;   // identity map for lanes past the end
+    if (j < Ic) {
+      const RCoef c = coef[j];
+      const double zl = j >= 1 ? (double)zin[Lead * (2 * j - 1)] : 0.0;
+      const double z0 = (double)zin[Lead * (2 * j)];
+      const double zr = 2 * j + 1 < I ? (double)zin[Lead * (2 * j + 1)] : 0.0;
+      A = c.a;
+      B = c.c0 * zl + c.c1 * z0 + c.c2 * zr;
+    }
+    // inclusive scan of x -> A x + B over the lanes (composition: later after earlier)
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double Ap = __shfl_up(A, off);
+      const double Bp = __shfl_up(B, off);
+      if (lane >= off) {
+        B = A * Bp + B;
+        A = A * Ap;
+      }
+    }
+    const double xj = A * carry + B;
+    if (j < Ic) zout[Lead * j] = (T)xj;
+    carry = __shfl(xj, 63);
+  }
+}
+
+hipError_t restrict_coef_launch(const RCoefJobs& jobs, hipStream_t st) {
+  size_t smem = 0;
+  for (int q = 0; q < jobs.count; ++q) smem = std::max(smem, bidiag_smem(jobs.I[q]));
+  hipLaunchKernelGGL(restrict_coef_kernel, dim3(jobs.count), dim3(kThreads), smem, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t restrict_factored_launch(const void* in, void* out, int64_t Lead, int64_t I, int64_t Tail,
+                                    const void* coef, bool fp32, hipStream_t st) {
+  const int64_t Ic = (I + 1) / 2;
+  const int64_t cols = Lead * Tail;
+  const RCoef* c = (const RCoef*)coef;
+  if (Lead >= 64) {
+    const int64_t blocks = (cols + kThreads - 1) / kThreads;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (fp32)
+      hipLaunchKernelGGL(restrict_cols_kernel<float>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                         (const float*)in, (float*)out, Lead, I, Ic, Tail, c);
+    else
+      hipLaunchKernelGGL(restrict_cols_kernel<double>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                         (const double*)in, (double*)out, Lead, I, Ic, Tail, c);
+  } else {
+    const int64_t per_block = kThreads / 64;
+    const int64_t blocks = (cols + per_block - 1) / per_block;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (fp32)
+      hipLaunchKernelGGL(restrict_scan_kernel<float>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                         (const float*)in, (float*)out, Lead, I, Ic, Tail, c);
+    else
+      hipLaunchKernelGGL(restrict_scan_kernel<double>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                         (const double*)in, (double*)out, Lead, I, Ic, Tail, c);
+  }
   return hipGetLastError();
 }
 

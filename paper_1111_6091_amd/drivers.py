@@ -149,22 +149,25 @@ def build_hierarchy(ctx, Z, weights, prec=CP_FP64, fp32=False, fp64=True):
     levels = []
     cur = Z
     for wl in weights:
-        ph = []
+        ph, wd = [], []
         for n, d in enumerate(cur.dims):
             if wl[n] is None:
                 ph.append(None)
+                wd.append(None)
                 continue
             w = torch.from_numpy(np.ascontiguousarray(wl[n], dtype=np.float64)).to(cur.device)
             p = torch.empty((d, (d + 1) // 2), dtype=torch.float64, device=w.device)
             api.cp_transfer_build(ctx, w, p)
             ph.append(p)
+            wd.append(w)
         cdims = tuple((d + 1) // 2 if ph[n] is not None else d for n, d in enumerate(cur.dims))
         nxt = api.DeviceTensor.empty(cdims, fp64=fp64 or prec == CP_FP64 or not fp32,
                                      fp32=fp32 or prec == CP_MIXED)
+        # coarse tensors by the factored form of eq. (15) (stencil + bidiagonal solve)
         if prec == CP_MIXED:
-            api.cp_restrict(ctx, cur, ph, nxt, CP_MIXED)
+            api.cp_restrict_factored(ctx, cur, wd, nxt, CP_MIXED)
         if nxt.z64 is not None and (cur.z64 is not None or isinstance(cur, api.SparseTensor)):
-            api.cp_restrict(ctx, cur, ph, nxt, CP_FP64)
+            api.cp_restrict_factored(ctx, cur, wd, nxt, CP_FP64)
         levels.append((cur, ph))
         cur = nxt
     levels.append((cur, [None] * cur.order))
@@ -278,10 +281,11 @@ def _level_weights(ctx, Z, fit_sets, Ic):
     return phat, weights
 
 
-def _restrict_tensor(ctx, Z, phat):
-    cdims = tuple((d + 1) // 2 if phat[n] is not None else d for n, d in enumerate(Z.dims))
+def _restrict_tensor(ctx, Z, weights):
+    """Coarse tensor eq. (15) in factored form from the interpolation weights."""
+    cdims = tuple((d + 1) // 2 if weights[n] is not None else d for n, d in enumerate(Z.dims))
     Zc = api.DeviceTensor.empty(cdims, fp64=True)
-    api.cp_restrict(ctx, Z, phat, Zc, CP_FP64)
+    api.cp_restrict_factored(ctx, Z, weights, Zc, CP_FP64)
     torch = _torch()
     Zc.norm2 = torch.zeros(1, dtype=torch.float64, device=Z.device)
     api.cp_norm2(ctx, Zc, Zc.norm2)
@@ -337,7 +341,7 @@ def mult_vcycle(ctx, Z, A, tfms, coarsest, first_cycle, nu1=SETUP_NU1, nu2=SETUP
     phat, weights = _level_weights(ctx, Z, list(tfms) + ([] if first_cycle else [A]), Ic)
     levels_out.append((Z, phat))
     weights_out.append(weights)
-    Zc = _restrict_tensor(ctx, Z, phat)
+    Zc = _restrict_tensor(ctx, Z, weights)
     Ac = _restrict_factors(ctx, phat, A)
     tfms_c = [_restrict_factors(ctx, phat, T) for T in tfms]
     mult_vcycle(ctx, Zc, Ac, tfms_c, coarsest, first_cycle, nu1, nu2, nuc, levels_out, weights_out)
@@ -384,7 +388,7 @@ def down_sweep(ctx, Z, A_boot, tfms, coarsest, nu1=SETUP_NU1, use_bfm=True):
         weights.append(w)
         B = _restrict_factors(ctx, phat, B)
         T = [_restrict_factors(ctx, phat, t) for t in T]
-        cur = _restrict_tensor(ctx, cur, phat)
+        cur = _restrict_tensor(ctx, cur, w)
     return levels, weights
 
 

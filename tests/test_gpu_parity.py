@@ -50,8 +50,12 @@ def test_mttkrp_fp64_matches_oracle(C, dims, R):
         assert e < 1e-12, (n, e)
 
 
+# the last two shapes contract modes longer than 256 (mode 1 for n = 0, mode 0
+# for n >= 1): the FP32 accumulation runs over pieces of at most 256 entries
+# that are added in FP64, which is what keeps the error within K u32 for K <= 256
 @pytest.mark.parametrize("dims,R", [((20, 20, 20), 3), ((64, 33, 17), 5), ((12, 10, 9, 11), 8),
-                                    ((37, 19, 23), 16), ((16, 16, 16), 20)])
+                                    ((37, 19, 23), 16), ((16, 16, 16), 20), ((900, 700, 3), 5),
+                                    ((600, 300, 4, 3), 4)])
 def test_mttkrp_mixed_matches_oracle(C, dims, R):
     from paper_1111_6091_amd import api
     say(f"mttkrp mixed dims={dims} R={R}")
@@ -260,6 +264,50 @@ def test_restrict_matches_oracle(C, dims, mask):
     scale = amg.restrict_tensor(np.abs(Z), [None if p is None else np.abs(p.T) for p in phs])
     assert scaled_err(Zc.to_numpy("z64"), ref, scale) < 1e-13
     assert scaled_err(Zc.to_numpy("z32"), ref, scale) < 1e-5
+
+
+@pytest.mark.parametrize("dims,mask", [((20, 20, 20), (1, 1, 1)), ((17, 12, 9), (1, 0, 1)),
+                                       ((16, 18, 10, 12), (1, 1, 1, 1)), ((33, 65, 40), (0, 1, 1)),
+                                       ((300, 7, 9), (1, 1, 0)), ((5, 520, 3), (1, 1, 1)), ((2, 3), (1, 1))])
+def test_restrict_factored_matches_oracle(C, dims, mask):
+    """Eq. (15) in factored form (stencil P^T, then forward substitution with the
+    bidiagonal L) against the oracle's mode products with the dense P^, for
+    adaptive-looking weights (linear weights scaled at random), FP64 and the FP32
+    storage of the mixed form; extents above 128 cross the four-segment blocks."""
+    from paper_1111_6091_amd import api
+    say(f"factored restrict dims={dims} mask={mask}")
+    rng = np.random.default_rng(sum(dims) + 5)
+    Z = rng.standard_normal(dims)
+    ws, phs = [], []
+    for d, m in zip(dims, mask):
+        if not m:
+            ws.append(None)
+            phs.append(None)
+            continue
+        w = synth.linear_interp_weights(d) * rng.uniform(0.5, 1.5, size=(d, 2))
+        w[0::2] = 0.0
+        ws.append(w)
+        phs.append(amg.transfer(amg.interp_from_weights(d, w))[2])
+    ref = amg.restrict_tensor(Z, [None if p is None else p.T for p in phs])
+    scale = amg.restrict_tensor(np.abs(Z), [None if p is None else np.abs(p.T) for p in phs])
+    wd = [None if w is None else torch.from_numpy(w).cuda() for w in ws]
+    Zd = api.DeviceTensor.from_numpy(C, Z, fp32=True)
+    Zc = api.DeviceTensor.empty(ref.shape, fp64=True, fp32=True)
+    api.cp_restrict_factored(C, Zd, wd, Zc, api.CP_FP64)
+    api.cp_restrict_factored(C, Zd, wd, Zc, api.CP_MIXED)
+    sync()
+    assert scaled_err(Zc.to_numpy("z64"), ref, scale) < 1e-13
+    # FP32 storage of input and output, FP64 arithmetic: two roundings to FP32
+    Z32 = Z.astype(np.float32).astype(np.float64)
+    ref32 = amg.restrict_tensor(Z32, [None if p is None else p.T for p in phs])
+    assert scaled_err(Zc.to_numpy("z32"), ref32, scale) < 2e-7
+    # the dense form of the same operator agrees
+    phd = [None if p is None else torch.from_numpy(p).cuda() for p in phs]
+    Zg = api.DeviceTensor.empty(ref.shape)
+    api.cp_restrict(C, Zd, phd, Zg, api.CP_FP64)
+    sync()
+    assert scaled_err(Zc.to_numpy("z64"), Zg.to_numpy(), scale) < 1e-13
+    assert C.status() == 0
 
 
 def test_identity_restriction_returns_z(C):

@@ -132,13 +132,18 @@ def test_sparse_restrict_matches_oracle(C, N, s, mask):
     ref = amg.restrict_tensor(Z, [None if p is None else p.T for p in phs])
     Zs = _sp(C, idx, vals, dims)
     Zc = api.DeviceTensor.empty(ref.shape)
+    Zf = api.DeviceTensor.empty(ref.shape)
     api.cp_restrict(C, Zs, phd, Zc, api.CP_FP64)
+    wd = [torch.from_numpy(synth.linear_interp_weights(d)).cuda() if m else None for d, m in zip(dims, mask)]
+    api.cp_restrict_factored(C, Zs, wd, Zf, api.CP_FP64)
     sync()
     if not any(mask):
         np.testing.assert_array_equal(Zc.to_numpy(), Z)
+        np.testing.assert_array_equal(Zf.to_numpy(), Z)
         return
     scale = amg.restrict_tensor(np.abs(Z), [None if p is None else np.abs(p.T) for p in phs])
     assert scaled_err(Zc.to_numpy(), ref, scale) < 1e-13
+    assert scaled_err(Zf.to_numpy(), ref, scale) < 1e-13
 
 
 @pytest.mark.parametrize("dims,mask", [((40, 4, 70000), (1, 1, 0)), ((3, 4400000), (1, 0)),
