@@ -789,10 +789,15 @@ def batched_leg(ctx, api, synth):
             Zd = api.DeviceTensor.from_numpy(ctx, p["Z"], fp32=mixed)
             cat = [np.hstack([p["starts"][k][n] for k in range(4)]) for n in range(3)]
             dev.append((Zd, api.DeviceFactors.from_numpy(ctx, cat, fp32=mixed)))
+        # launch tiles: tensor KiB per streaming workgroup, tuned on the first sweeps
+        from paper_1111_6091_amd import drivers
+        kib, tune_t = drivers.tune_batched(ctx, dev, 4, prec)
+        log(f"batched {tag}: tile tuner {', '.join(f'{k} KiB {v * 1e3:.1f} ms' for k, v in tune_t.items())} "
+            f"-> {kib} KiB")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fits, sweeps = api.cp_als_batched(ctx, dev, 4, prec=prec, window32=16, tol32=1e-9, tol64=1e-12,
-                                          max_sweeps=10000, chunk=16)
+                                          max_sweeps=10000, chunk=16, wg_kib=kib)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sw = sweeps.cpu().numpy()
@@ -814,11 +819,12 @@ def batched_leg(ctx, api, synth):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             api.cp_als_batched(ctx, dev2, 4, prec=prec, window32=16, tol32=1e-9, tol64=1e-12,
-                               max_sweeps=int(uncapped.max()), chunk=16)
+                               max_sweeps=int(uncapped.max()), chunk=16, wg_kib=kib)
             torch.cuda.synchronize()
             t_nocap = time.perf_counter() - t0
             del dev2
         out[tag] = {"seconds": round(dt, 4), "solves_per_s": round(4 * len(probs) / dt, 1),
+                    "tuned_wg_kib": kib, "tuner_ms_per_8_sweeps": {str(k): round(v * 1e3, 2) for k, v in tune_t.items()},
                     "seconds_capped_at_max_converged_sweeps": None if t_nocap is None else round(t_nocap, 4),
                     "capped_tail_seconds": None if t_nocap is None else round(dt - t_nocap, 4),
                     "sweeps_fp32": int(sw[:, :, 0].sum()), "sweeps_fp64": int(sw[:, :, 1].sum()),

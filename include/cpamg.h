@@ -402,6 +402,9 @@ typedef struct {
   double tol64;
   int32_t max_sweeps; /* >= 1 */
   int32_t chunk;      /* >= 1 */
+  int32_t wg_kib;     /* tensor KiB each streaming workgroup of the batched
+                         MTTKRP launches covers: 16..4096, 0 = 192 (the tile
+                         size a tuner such as drivers.tune_batched picks) */
 } cp_batch_params;
 
 /* Batched form of the ALS solve (Section 3, stopping as in cp_batch_params):

@@ -70,7 +70,7 @@ class CpBatchProblem(ctypes.Structure):
 
 class CpBatchParams(ctypes.Structure):
     _fields_ = [("restarts", c_i32), ("prec", c_i32), ("window32", c_i32), ("tol32", ctypes.c_double),
-                ("tol64", ctypes.c_double), ("max_sweeps", c_i32), ("chunk", c_i32)]
+                ("tol64", ctypes.c_double), ("max_sweeps", c_i32), ("chunk", c_i32), ("wg_kib", c_i32)]
 
 
 # name -> (argtypes)

@@ -367,7 +367,7 @@ def cp_sort(ctx, A):
 
 
 def cp_als_batched(ctx, problems, restarts, prec=CP_MIXED, window32=16, tol32=1e-9, tol64=1e-12,
-                   max_sweeps=10000, chunk=16):
+                   max_sweeps=10000, chunk=16, wg_kib=0):
     """Batched ALS solves: ``problems`` is a list of (DeviceTensor, DeviceFactors) where the
     factors have rank restarts * R (restart k in columns k*R..(k+1)*R-1).  Returns device
     tensors (fits [nprob, restarts], sweeps [nprob, restarts, 2])."""
@@ -377,7 +377,7 @@ def cp_als_batched(ctx, problems, restarts, prec=CP_MIXED, window32=16, tol32=1e
     for i, (Z, A) in enumerate(problems):
         arr[i].z = Z.struct()
         arr[i].a = A.struct()
-    prm = CpBatchParams(restarts, prec, window32, tol32, tol64, max_sweeps, chunk)
+    prm = CpBatchParams(restarts, prec, window32, tol32, tol64, max_sweeps, chunk, wg_kib)
     dev = problems[0][0].z64.device
     fits = torch.empty((n, restarts), dtype=torch.float64, device=dev)
     sweeps = torch.empty((n, restarts, 2), dtype=torch.int32, device=dev)

@@ -1708,7 +1708,7 @@ extern "C" cp_status cp_fas_vcycle(cp_ctx ctx, const cp_level* levels, int32_t n
 namespace {
 
 // Tensor bytes one streaming workgroup of a batched MTTKRP aims to cover.
-constexpr int64_t kBatchBytesPerWg = 192 * 1024;
+constexpr int64_t kBatchBytesPerWg = 192 * 1024;   // default of cp_batch_params::wg_kib
 // Mixed form: below this many active problems the FP32-phase ones move to FP64.
 constexpr int kBatchMergeBelow = 64;
 
@@ -1740,6 +1740,9 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
       !(prm->tol64 >= 0.0))
     return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: window32 >= 2, max_sweeps >= 1, chunk >= 1 "
                                         "and non-negative tolerances required");
+  if (prm->wg_kib != 0 && (prm->wg_kib < 16 || prm->wg_kib > 4096))
+    return set_err(ctx, CP_ERR_INVALID, "cp_als_batched: wg_kib %d outside [16, 4096] (0 = default)", prm->wg_kib);
+  const int64_t wg_bytes = prm->wg_kib ? (int64_t)prm->wg_kib * 1024 : kBatchBytesPerWg;
   const bool mixed = prm->prec == CP_MIXED;
   int N = 0;
   for (int b = 0; b < nprob; ++b) {
@@ -1770,8 +1773,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
       int64_t P = 1;
       for (int m = 0; m < N; ++m) P *= pb.z.dims[m];
       const int64_t bytes = P * (fp32 ? 4 : 8);
-      const int target = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (bytes + kBatchBytesPerWg - 1) /
-                                                                                   kBatchBytesPerWg));
+      const int target = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (bytes + wg_bytes - 1) / wg_bytes));
       for (int n = 0; n < N; ++n) {
         MttkrpPlan p = mttkrp_plan(N, pb.z.dims, n, pb.a.rank, fp32, PlanOpts{target, 0, 2, 4});
         if (!p.bl)
@@ -2041,6 +2043,7 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
   // a problem sweeps at most max_sweeps + 1 times and idles for at most one
   // chunk at its phase change
   const int64_t max_rounds = 2 * (int64_t)prm->max_sweeps + 16 * (int64_t)prm->chunk + 16;
+  std::string last_key;
   for (int64_t rounds = 0; rounds < max_rounds;) {
     int na = 0;
     for (int ph = 0; ph < nphase; ++ph) na += (int)act[ph].size();
@@ -2103,32 +2106,56 @@ extern "C" cp_status cp_als_batched(cp_ctx ctx, const cp_batch_problem* probs, i
                               hipMemcpyHostToDevice, st));
     }
     HIPCHK(hipMemcpyAsync(plist, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    {
-      ProfScope ps(ctx, CP_PROF_GRAM);
-      HIPCHK(gram_batched_launch(jobs, plist, na, N, st));
-    }
-    for (int k = 0; k < K; ++k)
-      for (int n = 0; n < N; ++n) {
-        const int set = (k == 0 && n == 0) ? 0 : n + 1;
-        for (int ph = 0; ph < nphase; ++ph) {
-          if (act[ph].empty()) continue;
-          BatchPhase& d = dp[ph];
-          const bool fp32 = mixed && ph == 0;
-          {
-            ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + kinds[std::min(n, 2)] - 1);
-            for (int q = 0; q < 2; ++q)
-              HIPCHK(mttkrp_batched_launch(kinds[std::min(n, 2)], fp32, q + 1, d.md, d.mtiles[set][q],
-                                           d.mcount[set][q], d.msmem[set][q], st));
-          }
-          ProfScope ps(ctx, CP_PROF_UPDATE);
-          HIPCHK(epi_batched_launch(d.ed, d.etiles[n], d.ecount[n], st));
-        }
+    // the chunk's launches (on ctx->stream, which a graph capture redirects)
+    auto body = [&]() -> cp_status {
+      hipStream_t s = ctx->stream;
+      {
+        ProfScope ps(ctx, CP_PROF_GRAM);
+        HIPCHK(gram_batched_launch(jobs, plist, na, N, s));
       }
+      for (int k = 0; k < K; ++k)
+        for (int n = 0; n < N; ++n) {
+          const int set = (k == 0 && n == 0) ? 0 : n + 1;
+          for (int ph = 0; ph < nphase; ++ph) {
+            if (act[ph].empty()) continue;
+            BatchPhase& d = dp[ph];
+            const bool fp32 = mixed && ph == 0;
+            {
+              ProfScope ps(ctx, (fp32 ? CP_PROF_MTTKRP_MODE0_F32 : CP_PROF_MTTKRP_MODE0_F64) + kinds[std::min(n, 2)] - 1);
+              for (int q = 0; q < 2; ++q)
+                HIPCHK(mttkrp_batched_launch(kinds[std::min(n, 2)], fp32, q + 1, d.md, d.mtiles[set][q],
+                                             d.mcount[set][q], d.msmem[set][q], s));
+            }
+            ProfScope ps(ctx, CP_PROF_UPDATE);
+            HIPCHK(epi_batched_launch(d.ed, d.etiles[n], d.ecount[n], s));
+          }
+        }
+      for (int ph = 0; ph < nphase; ++ph) {
+        if (act[ph].empty()) continue;
+        ProfScope ps(ctx, CP_PROF_NORMALIZE);
+        HIPCHK(finalize_batched_launch(dp[ph].fin, plist_ph[ph], (int)act[ph].size(), smem_fin, s));
+      }
+      return CP_OK;
+    };
+    // A chunk whose launch sequence repeats the previous one (same active
+    // problems, tile counts and length: the long tail of a batch) is recorded
+    // into a HIP graph once and replayed; the launch arguments are device
+    // arrays at fixed workspace addresses that the uploads above refill.
+    std::ostringstream key;
+    key << "batch;" << (const void*)ctx->ws << ";" << ctx->ws_cap << ";" << nprob << ";" << K << ";" << na;
     for (int ph = 0; ph < nphase; ++ph) {
-      if (act[ph].empty()) continue;
-      ProfScope ps(ctx, CP_PROF_NORMALIZE);
-      HIPCHK(finalize_batched_launch(dp[ph].fin, plist_ph[ph], (int)act[ph].size(), smem_fin, st));
+      key << "|" << act[ph].size();
+      for (int set = 0; set < nsets; ++set)
+        for (int q = 0; q < 2; ++q) key << "," << dp[ph].mcount[set][q] << ":" << dp[ph].msmem[set][q];
+      for (int n = 0; n < N; ++n) key << "," << dp[ph].ecount[n];
     }
+    const std::string ks = key.str();
+    if (ctx->graphs && !ctx->prof && ks == last_key) {
+      TRY(run_graph(ctx, ks, body));
+    } else {
+      TRY(body());
+    }
+    last_key = ks;
     rounds += K;
     HIPCHK(hipMemcpyAsync(hst.data(), states, hst.size() * sizeof(BatchState), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));   // also retires the host tile lists uploaded above

@@ -504,3 +504,28 @@ def multilevel(ctx, Z, A, tfms, coarsest, tau=1e-10, max_cycles=500, setup=None,
                                         nu1_setup=setup.get("nu1", SETUP_NU1), **fas)
     return dict(setup=shist, solve=hist, rebuilt=rebuilt, levels=len(levels),
                 iterations=len(shist) + len(hist))
+
+
+def tune_batched(ctx, problems, restarts, prec, candidates=(48, 96, 192, 384, 768), sweeps=8):
+    """Launch-tile tuner of the batched solve: times `sweeps` sweeps of the whole
+    batch (every restart running: no stopping rule) for each candidate tensor
+    KiB per streaming workgroup, on copies of the factors, and returns
+    (best wg_kib, {wg_kib: seconds})."""
+    torch = _torch()
+    times = {}
+    work = [(Z, A.clone()) for Z, A in problems]
+    api.cp_als_batched(ctx, work, restarts, prec=prec, tol32=0.0, tol64=0.0, max_sweeps=2, chunk=2,
+                       wg_kib=candidates[0])
+    for kib in candidates:
+        work = [(Z, A.clone()) for Z, A in problems]
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        api.cp_als_batched(ctx, work, restarts, prec=prec, tol32=0.0, tol64=0.0, max_sweeps=sweeps,
+                           chunk=sweeps, wg_kib=kib)
+        e1.record(st)
+        torch.cuda.synchronize()
+        times[kib] = e0.elapsed_time(e1) / 1e3
+    best = min(times, key=times.get)
+    return best, times

@@ -123,3 +123,43 @@ def test_batched_rejects_bad_arguments():
         api.cp_als_batched(C, dev, 2, prec=CP_FP64, window32=1)
     with pytest.raises(api.CpError):
         api.cp_als_batched(C, dev, 2, prec=1)              # mixed needs FP32 shadows
+    with pytest.raises(api.CpError):
+        api.cp_als_batched(C, dev, 2, prec=CP_FP64, wg_kib=8)   # tile below 16 KiB
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_graph_replay_and_tiles_change_nothing(mixed):
+    """The same batch with graph replay of repeated chunks on and off, and with
+    two tile sizes: identical fits, sweep counts and factors (the tiles only
+    regroup a problem's workgroups; the partial sums are added in one fixed
+    order either way, so a change would show as a rounding difference)."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_FP64, CP_MIXED, CP_OPT_GRAPHS
+    restarts = 2
+    probs = synth.batched_problems(count=9, seed=21, restarts=restarts, lo=10, hi=40, rmin=2, rmax=5)
+    prec = CP_MIXED if mixed else CP_FP64
+    C = make_ctx()
+    outs = []
+    for graphs, kib in ((0, 192), (1, 192), (1, 192), (1, 48)):
+        C.set_option(CP_OPT_GRAPHS, graphs)
+        dev = _setup(C, probs, restarts, mixed)
+        # short chunks so that the tail repeats chunk after chunk
+        fits, sweeps = api.cp_als_batched(C, dev, restarts, prec=prec, tol32=1e-9, tol64=1e-12,
+                                          max_sweeps=600, chunk=2, wg_kib=kib)
+        sync()
+        outs.append((fits.cpu().numpy(), sweeps.cpu().numpy(), [A.to_numpy() for _, A in dev]))
+    C.set_option(CP_OPT_GRAPHS, 1)
+    ref = outs[0]
+    for got in outs[1:3]:
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+        for Ag, Ar in zip(got[2], ref[2]):
+            for a, b in zip(Ag, Ar):
+                assert np.array_equal(a, b)
+    # another tile size: the split of the contraction over workgroups changes
+    # the order of the partial sums, so rounding may differ slightly; in the
+    # mixed form the FP32 rounding also moves the FP32-to-FP64 switch, and a
+    # restart still in a swamp at the 600-sweep cap (problem 4 here) keeps that
+    # difference (4e-10 seen), so the bound there is looser
+    got = outs[3]
+    assert np.max(np.abs(got[0] - ref[0]) / np.abs(ref[0])) < (1e-8 if mixed else 1e-10)
+    assert C.status() == 0
