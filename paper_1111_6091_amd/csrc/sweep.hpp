@@ -133,7 +133,8 @@ __device__ inline void gram_mfma(const double* __restrict__ A, int64_t I, int R,
 // Gamma (in G, LDS, left unchanged; block-diagonal over `groups` column groups)
 // for the ALS update: the inverse W = L^-1 of its Cholesky factor (kind 0,
 // Gamma^-1 = W^T W, factored block by block) or, when a block fails the
-// factorization test, its pseudoinverse (kind 1) is written to out[0..R*R)
+// factorization test, the pseudoinverse (kind 1; in GROUPED kernels block by
+// block, each block with its own threshold) is written to out[0..R*R)
 // (global), with no barrier after these stores.  S, V, P: LDS scratch of R*R
 // each.  RMAX: the largest rank bucket the calling kernel instantiates; LDSV:
 // factor with the rows in LDS instead of registers.
@@ -145,8 +146,28 @@ __device__ __forceinline__ void gamma_factor(double* G, int R, int groups, doubl
     for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = S[idx];
     if (threadIdx.x == 0) *kind = 0;
   } else {
-    const int zero = wg_pinv(G, R, S, V, P);
-    for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = P[idx];
+    int zero = 0;
+    if (GROUPED && groups > 1) {
+      // block by block, each with its own size and largest eigenvalue in the
+      // dropping threshold (as a restart solved on its own): a restart whose
+      // Gamma is small in scale keeps its eigenvalues next to a singular one
+      const int n = R / groups;
+      for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x)
+        if (idx / R / n != idx % R / n) out[idx] = 0.0;
+      double* Gc = V + n * n;   // compact copy of the block (V holds R*R >= 4 n*n)
+      for (int g = 0; g < groups; ++g) {
+        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
+          Gc[idx] = G[(g * n + idx / n) * R + g * n + idx % n];
+        __syncthreads();
+        zero |= wg_pinv(Gc, n, S, V, P);
+        for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
+          out[(g * n + idx / n) * R + g * n + idx % n] = P[idx];
+        __syncthreads();
+      }
+    } else {
+      zero = wg_pinv(G, R, S, V, P);
+      for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) out[idx] = P[idx];
+    }
     if (threadIdx.x == 0) {
       *kind = 1;
       atomicOr(flags, zero ? (CP_FLAG_PINV_FALLBACK | CP_FLAG_NOT_SPD) : CP_FLAG_PINV_FALLBACK);

@@ -163,3 +163,37 @@ def test_batched_graph_replay_and_tiles_change_nothing(mixed):
     got = outs[3]
     assert np.max(np.abs(got[0] - ref[0]) / np.abs(ref[0])) < (1e-8 if mixed else 1e-10)
     assert C.status() == 0
+
+
+def test_batched_pinv_is_per_restart():
+    """One restart starts with a zero column (every Gamma singular: the
+    pseudoinverse path), the other from a start scaled by 1e-5 (Gamma about
+    1e-20 of the first's, well conditioned): each follows the oracle's ALS of
+    its own start; a pseudoinverse over the whole block-diagonal Gamma with one
+    threshold would drop every eigenvalue of the small restart."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_FP64, CP_FLAG_PINV_FALLBACK
+    restarts, R = 2, 3
+    dims = (11, 9, 10)
+    Z, _ = synth.collinear_tensor(dims, R, 0.5, 0.01, 0.0, seed=77)
+    s0 = synth.uniform_start(dims, R, 77, 0)
+    s0[1][:, 0] = 0.0
+    s1 = [1e-5 * a for a in synth.uniform_start(dims, R, 77, 1)]
+    starts = [s0, s1]
+    C = make_ctx()
+    Zd = api.DeviceTensor.from_numpy(C, Z)
+    cat = [np.hstack([starts[k][n] for k in range(restarts)]) for n in range(3)]
+    Ad = api.DeviceFactors.from_numpy(C, cat)
+    K = 3
+    fits, sweeps = api.cp_als_batched(C, [(Zd, Ad)], restarts, prec=CP_FP64, tol64=0.0, max_sweeps=K, chunk=K)
+    sync()
+    got = Ad.to_numpy()
+    flags = C.status()
+    assert flags & CP_FLAG_PINV_FALLBACK
+    for k in range(restarts):
+        A = starts[k]
+        for _ in range(K):
+            A = cp.als_sweep(Z, A)
+        G = _restart(got, k, R)
+        for n in range(3):
+            assert elem_err(G[n], A[n]) < 1e-8, (k, n, elem_err(G[n], A[n]))
