@@ -310,9 +310,10 @@ hipError_t gemm_launch(const GemmDesc& d, bool fp32, hipStream_t st) {
 // c2_j = w[2j+1][0] c1_j (zero where the neighbour does not exist): about five
 // flops per coarse entry and one pass over the input.  The tensor is viewed as
 // (Lead, I, Tail); a column is one (lead, tail) pair.
-//   Lead >= 64: a lane per column (64 consecutive columns per wave, coalesced),
-//               the recurrence run down the column;
-//   Lead < 64:  a wave per column, lanes along j: the stencil values side by
+//   Lead >= 64 (or short columns, I <= 64): a lane per column (64 consecutive
+//               columns per wave, coalesced when Lead >= 64), the recurrence
+//               run down the column;
+//   otherwise:  a wave per column, lanes along j: the stencil values side by
 //               side, then the first-order recurrence as an inclusive scan of
 //               the affine maps x -> a_j x + b_j across the wave (six
 //               shuffle rounds per 64 coarse entries), carried between blocks.
@@ -440,7 +441,9 @@ hipError_t restrict_factored_launch(const void* in, void* out, int64_t Lead, int
   const int64_t Ic = (I + 1) / 2;
   const int64_t cols = Lead * Tail;
   const RCoef* c = (const RCoef*)coef;
-  if (Lead >= 64) {
+  // short fibres (I <= 64) would leave most lanes of a per-column wave idle:
+  // a lane per column there too (consecutive columns then read I apart)
+  if (Lead >= 64 || I <= 64) {
     const int64_t blocks = (cols + kThreads - 1) / kThreads;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     if (fp32)
