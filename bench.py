@@ -153,7 +153,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures the single-GPU kernel path only; run it with --gpus 1 "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding over several GPUs is described in the design notes and not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -58,7 +58,7 @@ typedef enum {
   CP_ERR_NONFINITE = -4,   /* reported by cp_get_status on NaN/Inf */
   CP_ERR_HIP = -5,         /* a HIP runtime call failed (message in cp_last_error) */
   CP_ERR_NOMEM = -6,       /* workspace allocation failed */
-  CP_ERR_UNSUPPORTED = -7  /* valid request that this build does not implement */
+  CP_ERR_UNSUPPORTED = -7  /* valid request that the library does not implement */
 } cp_status;
 
 typedef enum { CP_FP64 = 0, CP_MIXED = 1 } cp_prec;
