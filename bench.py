@@ -244,14 +244,18 @@ def main():
         e0.record()
         api.cp_als_sweep(ctx, Zd, A, None, steps, CP_SOLVE_CHOL, 10, True, prec, fh)
         e1.record()
+        t_enq = time.perf_counter() - t0
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        timed.enqueue_us = t_enq / steps * 1e6
         return e0.elapsed_time(e1) / steps, wall
 
     ms_mixed, wall_mixed = timed(CP_MIXED, K, W)
-    log(f"mixed sweep: {ms_mixed * 1e3:.1f} us ({1e3 / ms_mixed:.0f} sweeps/s)")
+    log(f"mixed sweep: {ms_mixed * 1e3:.1f} us ({1e3 / ms_mixed:.0f} sweeps/s; "
+        f"host enqueue {timed.enqueue_us:.1f} us per sweep)")
     ms_fp64, wall_fp64 = timed(CP_FP64, K, W)
-    log(f"fp64 sweep: {ms_fp64 * 1e3:.1f} us ({1e3 / ms_fp64:.0f} sweeps/s)")
+    log(f"fp64 sweep: {ms_fp64 * 1e3:.1f} us ({1e3 / ms_fp64:.0f} sweeps/s; "
+        f"host enqueue {timed.enqueue_us:.1f} us per sweep)")
     if args.sweeps_only:
         return
     # the same sweeps with one pass over Z per mode (no dimension tree)

@@ -30,9 +30,18 @@ void mttkrp_batched(const MttkrpDesc* __restrict__ descs, const int2* __restrict
 
 // ---------------------------------------------------------------------------
 // Dimension-tree MTTKRP of mode n >= 2 from Y (FP64 throughout).  Workgroup
-// (row i_n, split) sums its chunk of rest indices; threads cover (rest index,
-// i1) pairs, each accumulating RM column sums, then a block reduction.
+// (row i_n, split) sums its chunk of rest indices q.  Lane layout: thread t
+// owns column c = t % RM of the rows t / RM, t / RM + 256 / RM, ... of each
+// Y block (Y[s] and A^(1) share the I1 x R row-major layout), so a wave reads
+// 64 / RM whole rows per load.  The work is the flat sequence of (q, row step)
+// pairs, KU of them per round with every load issued before the first use
+// (indices clamped instead of branched).  Per chunk of up to kYQ rest indices
+// the stripe offsets and the weights prod_{m >= 2, m != n} A^(m)(s_m, c) are
+// staged in LDS first.  Column sums: across the lanes of a column in a fixed
+// shuffle order, then the four waves in order.
 // ---------------------------------------------------------------------------
+constexpr int kYQ = 32;
+
 template <int RM>
 __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
   extern __shared__ double smem[];
@@ -40,73 +49,79 @@ __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
     sweep_prep<16, RM>(d.pa, smem, false);
     return;
   }
+  __shared__ double sw[kYQ * RM];        // weights of the chunk's rest indices
+  __shared__ int64_t sbase[kYQ];         // Y offsets of their blocks
+  __shared__ double swave[4 * RM];       // per-wave column sums
+  constexpr int RPW = kThreads / RM;     // rows per round of the workgroup
+  constexpr int KU = 16;                 // (q, row step) pairs per round
   const int bid = blockIdx.x - d.prep;
   const int64_t row = bid % d.In;
   const int split = (int)(bid / d.In);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = d.R;
-  const int64_t I1 = d.I1;
+  const int I1 = (int)d.I1;
   const int jn = d.n - 2;
+  const int c = tid % RM, rl = tid / RM;
+  const bool cok = c < R;
+  const int cc = cok ? c : 0;
   const int64_t qbeg = (int64_t)split * d.rchunk;
   const int64_t qend = min(d.rest_count, qbeg + d.rchunk);
-  const int lpq = I1 >= kThreads ? kThreads : (int)I1;   // threads per rest index
-  const int qpar = kThreads / lpq;
-  const int qo = tid / lpq, il = tid % lpq;
-  double acc[RM];
-#pragma unroll
-  for (int r = 0; r < RM; ++r) acc[r] = 0.0;
+  const int steps = (I1 + RPW - 1) / RPW;   // row steps per rest index
   const double* __restrict__ a1 = d.a64[1];
-  if (qo < qpar) {
-    for (int64_t q = qbeg + qo; q < qend; q += qpar) {
-      // stripe index from the output value (mode n) and the rest index q
-      int64_t s = row * d.sst[jn], qq = q;
-      double w[RM];
-#pragma unroll
-      for (int r = 0; r < RM; ++r) w[r] = 1.0;
+  const double* __restrict__ y = d.y;
+  double acc = 0.0;
+  for (int64_t q0 = qbeg; q0 < qend; q0 += kYQ) {
+    const int nq = (int)min<int64_t>(kYQ, qend - q0);
+    // stripe offsets and weights of rest indices q0 .. q0 + nq - 1
+    __syncthreads();
+    for (int e = tid; e < nq * RM; e += kThreads) {
+      const int qi = e / RM, col = e % RM;
+      int64_t s = row * d.sst[jn], qq = q0 + qi;
+      double w = col < R ? 1.0 : 0.0;
       for (int j = 0; j < d.ns; ++j) {
         if (j == jn) continue;
         const int64_t sj = qq % d.sext[j];
         qq /= d.sext[j];
         s += sj * d.sst[j];
-        const double* am = d.a64[j + 2] + sj * R;
-#pragma unroll
-        for (int r = 0; r < RM; ++r)
-          if (r < R) w[r] *= am[r];
+        if (col < R) w *= d.a64[j + 2][sj * R + col];
       }
-      const double* ys = d.y + (size_t)s * I1 * R;
-      for (int64_t i1 = il; i1 < I1; i1 += lpq) {
-        const double* yr = ys + i1 * R;
-        const double* ar = a1 + i1 * R;
+      sw[qi * RM + col] = w;
+      if (col == 0) sbase[qi] = s * d.I1 * R;
+    }
+    __syncthreads();
+    const int T = nq * steps;
+    int qi = 0, st = 0;   // (q, step) of the round's first pair
+    for (int t0 = 0; t0 < T; t0 += KU) {
+      double yv[KU], av[KU], wv[KU];
+      int qk = qi, sk = st;
 #pragma unroll
-        for (int r = 0; r < RM; ++r)
-          if (r < R) acc[r] += w[r] * yr[r] * ar[r];
+      for (int u = 0; u < KU; ++u) {
+        const int i1 = sk * RPW + rl;
+        const bool v = (t0 + u < T) && cok && i1 < I1;
+        const int qs = qk < nq ? qk : nq - 1;
+        const int64_t ar = (int64_t)(v ? i1 : 0) * R + cc;
+        yv[u] = y[sbase[qs] + ar];
+        av[u] = a1[ar];
+        wv[u] = v ? sw[qs * RM + c] : 0.0;
+        if (++sk == steps) {
+          sk = 0;
+          ++qk;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) acc = fma(wv[u] * yv[u], av[u], acc);
+      qi = qk;
+      st = sk;
     }
   }
-  // block reduction through LDS, 16 columns at a time, in a fixed order:
-  // 16 consecutive threads' values, then the 16 part sums
-  (void)lane;
-  (void)wave;
+  // column sums: lanes c, c + RM, ... of the wave (fixed order), then the waves
 #pragma unroll
-  for (int c0 = 0; c0 < RM; c0 += 16) {
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 16; ++c) smem[c * kThreads + tid] = acc[c0 + c];
-    __syncthreads();
-    {
-      const int c = tid >> 4, part = tid & 15;
-      double x = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) x += smem[c * kThreads + part * 16 + i];
-      smem[16 * kThreads + tid] = x;
-    }
-    __syncthreads();
-    if (tid < 16 && c0 + tid < R) {
-      double x = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) x += smem[16 * kThreads + tid * 16 + i];
-      d.out[((size_t)split * d.In + row) * R + c0 + tid] = x;
-    }
+  for (int off = RM; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
+  if (lane < RM) swave[wave * RM + lane] = acc;
+  __syncthreads();
+  if (tid < R) {
+    const double x = ((swave[tid] + swave[RM + tid]) + swave[2 * RM + tid]) + swave[3 * RM + tid];
+    d.out[((size_t)split * d.In + row) * R + tid] = x;
   }
 }
 
@@ -149,7 +164,7 @@ hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double
     d.pa = *prep;
     d.pa.lds = prep_smem_doubles(N, R);
   }
-  const size_t smem = sizeof(double) * (size_t)std::max(17 * kThreads, prep ? prep_smem_doubles(N, R) : 0);
+  const size_t smem = prep ? sizeof(double) * (size_t)prep_smem_doubles(N, R) : 0;
   dim3 grid((unsigned)(d.In * nsplit + d.prep)), block(kThreads);
   if (R <= 16) hipLaunchKernelGGL(ymttkrp_kernel<16>, grid, block, smem, st, d);
   else hipLaunchKernelGGL(ymttkrp_kernel<32>, grid, block, smem, st, d);

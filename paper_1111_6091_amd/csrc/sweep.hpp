@@ -176,28 +176,41 @@ __device__ __forceinline__ void gamma_factor(double* G, int R, int groups, doubl
 }
 
 
-// The bookkeeping state into LDS: the column scales into sS and, when
-// staged, the stored Grams into sGr (K loads in flight per thread).
+// The bookkeeping state (the column scales, and the stored Grams when they
+// are staged) into LDS in two steps, so that its loads share one round trip
+// with the first Gram operands: prep_issue loads up to K values per thread
+// (the address clamped into the state, no branch around a load), prep_store
+// writes them to sS / sGr and copies any remainder beyond K * kThreads values
+// in a loop.  The caller's barrier follows.  L = n1 + staged Gram entries.
 template <int K>
-__device__ inline void prep_load(const PrepArgs& a, double* sS, double* sGr) {
-  const int N = a.N, R = a.R, RR = R * R;
-  const int n1 = N * R, n2 = sGr ? N * RR : 0;
-  const int L = n1 + n2;
-  for (int base = 0; base < L; base += K * kThreads) {
-    double v[K];
+__device__ __forceinline__ void prep_issue(const double* sigma, const double* grams, int n1, int L,
+                                           double (&v)[K]) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int idx = base + threadIdx.x + k * kThreads;
-      v[k] = idx < n1 ? a.sigma[idx] : (idx < L ? a.grams[idx - n1] : 0.0);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int idx = base + threadIdx.x + k * kThreads;
-      if (idx < n1) sS[idx] = v[k];
-      else if (idx < L) sGr[idx - n1] = v[k];
+  for (int k = 0; k < K; ++k) {
+    v[k] = 0.0;
+    if (k * kThreads < L) {   // uniform
+      const int j = min((int)threadIdx.x + k * kThreads, L - 1);
+      const double* src = j < n1 ? sigma + j : grams + (j - n1);
+      v[k] = *src;
     }
   }
-  __syncthreads();
+}
+
+template <int K>
+__device__ __forceinline__ void prep_store(const double* sigma, const double* grams, int n1, int L,
+                                           const double (&v)[K], double* sS, double* sGr) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int idx = threadIdx.x + k * kThreads;
+    if (k * kThreads < L && idx < L) {
+      if (idx < n1) sS[idx] = v[k];
+      else sGr[idx - n1] = v[k];
+    }
+  }
+  for (int idx = threadIdx.x + K * kThreads; idx < L; idx += kThreads) {
+    if (idx < n1) sS[idx] = sigma[idx];
+    else sGr[idx - n1] = grams[idx - n1];
+  }
 }
 
 // Stopping rules of a batched solve, applied by thread 0 after the sweep that
@@ -283,18 +296,22 @@ __device__ inline void sweep_prep(const PrepArgs& a, double* smem, bool finalize
   double* sS = U + RR;       // sigma, N x R
   const int lds = a.lds > prep_min_doubles(N, R) ? a.lds : prep_min_doubles(N, R);
   double* sGr = prep_stage_grams(N, R, lds) ? sS + N * R : nullptr;   // stored Grams, N x R x R
-  // one round trip for every global load of the step: the first Gram operands
-  // of the factor updated last, the boundary's inner-product partials, then
-  // the scales and stored Grams
+  // one round trip for every global load of the step: the scales and stored
+  // Grams, the first Gram operands of the factor updated last, then the
+  // boundary's inner-product partials
   // (inside a streaming kernel 8 row blocks per wave and round, not 16, to keep
   // its register count)
   constexpr int GQ = LK == 8 ? 8 : 16;
+  const int n1 = N * R, Lst = n1 + (sGr ? N * RR : 0);
+  double pv[LK];
+  prep_issue<LK>(a.sigma, a.grams, n1, Lst, pv);
   double gpre[GQ];
   if (a.p >= 0) gram_first_loads<GQ>(a.Ap, a.Ip, R, gpre);
   const bool want_f = a.boundary && active && (a.f_slot || st);
   const double ip0 = (want_f && tid < a.inner_count) ? a.inner_part[(size_t)tid * NG] : 0.0;
   const double nz2 = want_f ? *a.norm2 : 0.0;
-  prep_load<LK>(a, sS, sGr);
+  prep_store<LK>(a.sigma, a.grams, n1, Lst, pv, sS, sGr);
+  __syncthreads();
   if (a.p >= 0) gram_mfma<GQ, RMAX>(a.Ap, a.Ip, R, U, gpre, sW4);
   // the updated factor is normalized (frozen groups kept their columns)
   if (a.p >= 0 && tid < R && !col_frozen(tid)) sS[a.p * R + tid] = 1.0;

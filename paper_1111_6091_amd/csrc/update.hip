@@ -44,21 +44,23 @@ __device__ inline bool arrive_last(int32_t* counter, int nblk, int* s_flag) {
 }
 
 // Sum p[k * stride] for k = k0, k0 + step, ... < count in increasing k, with
-// 32 independent (predicated) loads in flight per round; the additions stay in
-// order, and the padding adds exact zeros.
+// 8 independent loads in flight per round (the index clamped into range, no
+// branch around a load); the additions stay in order, and the padding adds
+// exact zeros.
 __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int k0, int count,
                                               int step, size_t stride) {
-  constexpr int Q = 32;
+  constexpr int Q = 8;
   double s = 0.0;
+  if (count <= 0) return s;
   for (int k = k0; k < count; k += Q * step) {
     double v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int kk = k + q * step;
-      v[q] = kk < count ? p[(size_t)kk * stride] : 0.0;
+      v[q] = p[(size_t)min(kk, count - 1) * stride];
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s += v[q];
+    for (int q = 0; q < Q; ++q) s += k + q * step < count ? v[q] : 0.0;
   }
   return s;
 }
@@ -85,42 +87,6 @@ __device__ inline void reduce_partials(const EpiDesc& d, int64_t row0, int nrows
     sM[(tid / R) * LDP + tid % R] = s;
   }
   __syncthreads();
-}
-
-// One row solve x Gamma = b on one wavefront (lane c < R holds b_c, gets x_c),
-// with X in LDS (R x R).  kind 0: X = W = L^-1 for Gamma = L L^T, so
-// x = (b W^T) W: y_i = sum_j W_ij b_j, then x_c = sum_i y_i W_ic; kind 1: X is
-// the pseudoinverse, x_c = sum_k b_k X_kc.  Sums in increasing index order;
-// values of other lanes arrive through scalar reads.  RM >= R.
-template <int RM>
-__device__ inline double wave_apply(double b, const double* X, int R, int kind, int lane) {
-  const int c = lane < R ? lane : 0;
-  double v = b;
-  if (kind == 0) {
-    double wr[RM];
-#pragma unroll
-    for (int j = 0; j < RM; ++j) wr[j] = j < R ? X[c * R + j] : 0.0;
-    double y = 0.0;
-#pragma unroll
-    for (int j = 0; j < RM; ++j) y = fma(wr[j], wave_bcast(b, j), y);
-    v = lane < R ? y : 0.0;
-  }
-  double xc[RM];
-#pragma unroll
-  for (int k = 0; k < RM; ++k) xc[k] = k < R ? X[k * R + c] : 0.0;
-  double x = 0.0;
-#pragma unroll
-  for (int k = 0; k < RM; ++k) x = fma(wave_bcast(v, k), xc[k], x);
-  return x;
-}
-
-__device__ inline double wave_apply_any(double b, const double* X, int R, int kind, int lane) {
-  if (R <= 4) return wave_apply<4>(b, X, R, kind, lane);
-  if (R <= 8) return wave_apply<8>(b, X, R, kind, lane);
-  if (R <= 12) return wave_apply<12>(b, X, R, kind, lane);
-  if (R <= 16) return wave_apply<16>(b, X, R, kind, lane);
-  if (R <= 24) return wave_apply<24>(b, X, R, kind, lane);
-  return wave_apply<32>(b, X, R, kind, lane);
 }
 
 // Gauss-Seidel on one row x Gamma = b (Gamma in G), r = 0..R-1 in order, warm
@@ -278,35 +244,69 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
     return;
   }
 
-  // ---- EPI_UPDATE: wave w solves row w in normalized coordinates -----------
+  // ---- EPI_UPDATE: the block's rows in normalized coordinates -------------
   // Gamma is block-diagonal over the column groups, so one solve of all R
   // columns solves every group; frozen groups (batched solve) keep their rows.
   const int NG = d.groups > 1 ? d.groups : 1;
   const int Rg = R / NG;
   double ip = 0.0, x = 0.0;
   bool wr = false;
-  const int64_t row = row0 + wave;
-  if (wave < nrows) {
+  int64_t orow = 0;   // output element (orow, oc) of this thread
+  int oc = 0;
+  if (kind != 2) {
+    // kinds 0 and 1: row solve x Gamma = b with X (sG) from the bookkeeping:
+    // kind 0, X = W = L^-1 for Gamma = L L^T, so x = (b W^T) W, i.e.
+    // y_i = sum_j W_ij b_j, then x_c = sum_i y_i W_ic; kind 1, X is the
+    // pseudoinverse, x_c = sum_k b_k X_kc.  Thread t < nrows R takes element
+    // (t / R, t % R); b and y pass through LDS; sums in increasing index order
+    double* sB = sT;
+    double* sY = sT + EPI_ROWS * LDP;
+    const int rl = tid / R, c = tid % R;
+    const bool act = tid < nrows * R;
+    double m = 0.0;
+    if (act) {
+      m = sC[c] * sM[rl * LDP + c];
+      sB[rl * LDP + c] = m + (d.F ? d.F[(row0 + rl) * R + c] : 0.0);
+    }
+    __syncthreads();
+    const double* v = sB;
+    if (kind == 0) {
+      if (act) {
+        double y = 0.0;
+        for (int j = 0; j < R; ++j) y = fma(sG[c * R + j], sB[rl * LDP + j], y);
+        sY[rl * LDP + c] = y;
+      }
+      __syncthreads();
+      v = sY;
+    }
+    if (act) {
+      for (int k = 0; k < R; ++k) x = fma(v[rl * LDP + k], sG[k * R + c], x);
+      wr = !(d.st && d.st->frozen[c / Rg]);
+      if (wr) ip = x * m;
+      orow = row0 + rl;
+      oc = c;
+    }
+  } else if (wave < nrows) {
+    // Gauss-Seidel: wave w solves row w, lane = column
+    const int64_t row = row0 + wave;
     const double m = (lane < R) ? sC[lane] * sM[wave * LDP + lane] : 0.0;
     const double b = (lane < R) ? m + (d.F ? d.F[row * R + lane] : 0.0) : 0.0;
-    if (kind != 2) {
-      x = wave_apply_any(b, sG, R, kind, lane);
-    } else {
-      const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
-      x = wave_gs_any(b, x0, sG, R, d.gs_iters, lane);
-    }
+    const double x0 = (lane < R) ? sC[R + lane] * d.A[row * R + lane] : 0.0;
+    x = wave_gs_any(b, x0, sG, R, d.gs_iters, lane);
     wr = lane < R && !(d.st && d.st->frozen[lane / Rg]);
     if (wr) ip = x * m;
+    orow = row;
+    oc = lane;
   }
   // the block sums (barriers) before the global stores, which a barrier would
   // wait for
   double ipb[kMaxGroups];
   if (d.want_obj)
-    for (int g = 0; g < NG; ++g) ipb[g] = block_sum((lane < R && lane / Rg == g) ? ip : 0.0, sred);
+    for (int g = 0; g < NG; ++g) ipb[g] = block_sum((wr && oc / Rg == g) ? ip : 0.0, sred);
   if (wr) {
     if (!isfinite(x)) atomicOr(d.flags, CP_FLAG_NONFINITE);
-    d.A[row * R + lane] = x;
-    if (d.A32) d.A32[row * R + lane] = (float)x;
+    d.A[orow * R + oc] = x;
+    if (d.A32) d.A32[orow * R + oc] = (float)x;
   }
   if (d.want_obj && tid == 0)
     for (int g = 0; g < NG; ++g) d.scal_part[(size_t)blk * NG + g] = ipb[g];

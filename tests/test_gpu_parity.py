@@ -129,6 +129,39 @@ def test_als_sweeps_track_oracle(C, dims, R, seed):
     assert C.status() == 0
 
 
+@pytest.mark.parametrize("dims,R", [((8, 5, 80, 256), 2), ((160, 24, 40), 20)])
+def test_dimension_tree_sweeps_track_oracle(C, dims, R):
+    """FP64 sweeps with and without the dimension tree against the oracle.  The
+    shapes reach the Y-contracting launches' edge cases: rest-index chunks of
+    32 plus a ragged one per workgroup (order 4, last split shorter), Y rows
+    fewer than one round of the workgroup (I1 = 5), and 17..32 columns."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_OPT_DIMTREE
+    say(f"dimension-tree sweeps dims={dims} R={R}")
+    Z, _ = synth.collinear_tensor(dims, R, 0.5, 0.01, 0.0, seed=7)
+    A0 = synth.uniform_start(dims, R, 7)
+    K = 3
+    A = A0
+    fref = []
+    for _ in range(K):
+        A = cp.als_sweep(Z, A)
+        fref.append(cp.objective(Z, A))
+    try:
+        for tree in (1, 0):
+            C.set_option(CP_OPT_DIMTREE, tree)
+            Zd, Ad = dev_inputs(C, Z, A0)
+            fh = torch.zeros(K, dtype=torch.float64, device="cuda")
+            api.cp_als_sweep(C, Zd, Ad, None, K, api.CP_SOLVE_CHOL, 10, True, api.CP_FP64, fh)
+            sync()
+            got = Ad.to_numpy()
+            for n in range(len(dims)):
+                assert elem_err(got[n], A[n]) < 1e-9, (tree, n, elem_err(got[n], A[n]))
+            np.testing.assert_allclose(fh.cpu().numpy(), fref, rtol=1e-9)
+    finally:
+        C.set_option(CP_OPT_DIMTREE, 1)
+    assert C.status() == 0
+
+
 def test_als_gs_with_rhs_matches_oracle_bngs(C):
     from paper_1111_6091_amd import api
     say("bngs gs10 with F")
