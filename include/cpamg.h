@@ -356,13 +356,16 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
  * split, rows per wave, FP32 lane width, contracted factor staged in LDS or
  * read from global memory) of the MTTKRP kernel of every mode of Z at precision
  * `prec` and rank A->rank, `reps` launches each, with HIP events on the
- * context's stream, and keep the fastest per mode in the context.  Later calls
+ * context's stream, and keep the fastest per mode in the context.  When a
+ * sweep of Z would use the dimension tree, the mode-1 launch that also stores
+ * the stage-1 tiles is tuned on its own too (key suffix ";y").  Later calls
  * on tensors of the same shape, rank and precision use them. */
 cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_prec prec,
                       int32_t reps);
 /* The tuned configurations as text, one line per (shape, rank, precision,
- * mode): "<key> <workgroups> <split> <rows> <lane width> <unstaged>"; owned by ctx, valid until the
- * next call on ctx. */
+ * mode, and the tile-storing mode-1 launch):
+ * "<key> <workgroups> <split> <rows> <lane width> <unstaged>"; owned by ctx,
+ * valid until the next call on ctx. */
 const char* cp_plans_export(cp_ctx ctx);
 /* Load configurations in the cp_plans_export format (replaces matching keys;
  * the last field may be omitted: staged). */

@@ -400,9 +400,13 @@ SweepPlan sweep_plan(cp_ctx ctx, const int64_t* dims, int N, int R, bool fp32,
   for (int m = 0; m < N; ++m) P *= dims[m];
   const size_t yd = (size_t)S * dims[1] * R;
   if (yd * 8 * 4 > (size_t)P * (fp32 ? 4 : 8)) return sp;
+  // the tile-storing launch's own tuned options (cp_autotune times that
+  // launch), else those of the plain mode-1 launch
   PlanOpts o = sp.p[1].opts;
+  auto ty = ctx->tuned.find(plan_key(N, dims, 1, R, fp32) + ";y");
+  if (ty != ctx->tuned.end()) o = ty->second;
   o.ksplit = 1;
-  o.nostage = 0;   // the tile-storing variant is tuned with the factor staged
+  o.nostage = 0;   // the tile-storing variant runs with the factor staged
   const MttkrpPlan p1y = mttkrp_plan(N, dims, 1, R, fp32, o);
   if (p1y.ksplit != 1) return sp;   // Y needs the whole contraction in one piece
   sp.dimtree = true;
@@ -1307,33 +1311,64 @@ cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_pr
       }
     }
   }
+  // with the dimension tree, the mode-1 launch of a sweep also stores Y: its
+  // candidates (the contraction in one piece, factor staged) are timed as well
+  size_t ydoubles = 0;
+  std::vector<PlanOpts> ycands;
+  if (ctx->dimtree && N >= 3) {
+    int64_t S = 1, P = 1;
+    for (int m = 2; m < N; ++m) S *= Z->dims[m];
+    for (int m = 0; m < N; ++m) P *= Z->dims[m];
+    const size_t yd = (size_t)S * Z->dims[1] * R;
+    if (yd * 8 * 4 <= (size_t)P * (mixed ? 4 : 8)) {
+      for (PlanOpts o : cands[1]) {
+        o.ksplit = 1;
+        o.nostage = 0;
+        const MttkrpPlan p = mttkrp_plan(N, Z->dims, 1, R, mixed, o);
+        if (p.ksplit != 1) continue;
+        bool dup = false;
+        for (const PlanOpts& q : ycands)
+          dup = dup || (q.target_wgs == o.target_wgs && q.tw == o.tw && q.vw == o.vw);
+        if (dup) continue;
+        ycands.push_back(o);
+        maxpart = std::max(maxpart, p.partial_doubles);
+      }
+      if (!ycands.empty()) ydoubles = yd;
+    }
+  }
   Sizer sz;
   sz.take<double>((size_t)N * R * R);
   sz.take<double>((size_t)N * R);
   sz.take<double>(maxpart);
+  sz.take<double>(ydoubles);
   if ((s = ensure_ws(ctx, sz.off)) != CP_OK) return s;
   Arena ar(ctx->ws);
   double* grams = ar.take<double>((size_t)N * R * R);
   double* sigma = ar.take<double>((size_t)N * R);
   double* part = ar.take<double>(maxpart);
+  double* y = ydoubles ? ar.take<double>(ydoubles) : nullptr;
   HIPCHK(gram_launch(A->a, nullptr, Z->dims, N, R, grams, ctx->stream, sigma));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   std::ostringstream report;
-  for (int n = 0; n < N; ++n) {
+  for (int pass = 0; pass <= N; ++pass) {
+    // passes 0..N-1: the plain launch of mode `pass`; pass N: mode 1 storing Y
+    const bool ys = pass == N;
+    if (ys && !y) break;
+    const int n = ys ? 1 : pass;
     const PrepArgs pa = timing_prep(ctx, Z, A, n, grams, sigma);
     double best = 1e30;
     PlanOpts bo{};
-    for (const PlanOpts& o : cands[n]) {
+    for (const PlanOpts& o : ys ? ycands : cands[n]) {
       const MttkrpPlan p = mttkrp_plan(N, Z->dims, n, R, mixed, o);
       for (int w = 0; w < 2; ++w)
         HIPCHK(mttkrp_launch(p, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
-                             &pa, ctx->stream));
+                             &pa, ctx->stream, ys ? y : nullptr));
       HIPCHK(hipEventRecord(e0, ctx->stream));
       for (int k = 0; k < reps; ++k)
         HIPCHK(mttkrp_launch(p, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part,
-                             &pa, ctx->stream));
+                             &pa, ctx->stream, ys ? y : nullptr));
       HIPCHK(hipEventRecord(e1, ctx->stream));
       HIPCHK(hipEventSynchronize(e1));
       float t = 0.f;
@@ -1344,7 +1379,7 @@ cp_status cp_autotune(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, cp_pr
         bo = o;
       }
     }
-    const std::string key = plan_key(N, Z->dims, n, R, mixed);
+    const std::string key = plan_key(N, Z->dims, n, R, mixed) + (ys ? ";y" : "");
     ctx->tuned[key] = bo;
     ctx->plans.erase(key);
     report << key << " " << bo.target_wgs << " " << bo.ksplit << " " << bo.tw << " " << bo.vw << " "

@@ -104,30 +104,36 @@ template <typename T, int NT>
 __device__ __forceinline__ void stage_b(const T* __restrict__ ak, int I, int R, T* Bs) {
   constexpr int NC = 16 * NT;
   const int ldb = (int)bstage_ld<T>(I);
-  // zeros: columns c >= R and the pad rows i >= I
-  for (int i = threadIdx.x; i < ldb; i += kThreads) {
-    const bool padrow = i >= I;
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c >= R || padrow) Bs[c * ldb + i] = T(0);
+  const int tid = threadIdx.x;
+  // zeros: the columns R..NC-1 (contiguous) and the pad rows i >= I of the others
+  for (int e = tid; e < (NC - R) * ldb; e += kThreads) Bs[R * ldb + e] = T(0);
+  const int pad = ldb - I;
+  for (int e = tid; e < pad * R; e += kThreads) {
+    const int c = e / pad;
+    Bs[c * ldb + I + (e - c * pad)] = T(0);
   }
   // the factor is contiguous (I x R): coalesced loads, 16 in flight per thread
-  // (one round trip up to 4096 entries)
+  // (one round trip up to 4096 entries); entry idx = i R + c goes to column c,
+  // row i, with (i, c) stepped along with idx instead of divided out
   constexpr int SQ = 16;
   const int total = I * R;
+  const int di = kThreads / R, dc = kThreads - di * R;
   for (int base = 0; base < total; base += SQ * kThreads) {
     T v[SQ];
 #pragma unroll
     for (int j = 0; j < SQ; ++j) {
-      const int idx = base + j * kThreads + (int)threadIdx.x;
+      const int idx = base + j * kThreads + tid;
       v[j] = ak[idx < total ? idx : 0];
     }
+    int i = (base + tid) / R, c = base + tid - i * R;
 #pragma unroll
     for (int j = 0; j < SQ; ++j) {
-      const int idx = base + j * kThreads + (int)threadIdx.x;
-      if (idx < total) {
-        const int i = idx / R, c = idx - i * R;
-        Bs[c * ldb + i] = v[j];
+      if (base + j * kThreads + tid < total) Bs[c * ldb + i] = v[j];
+      i += di;
+      c += dc;
+      if (c >= R) {
+        c -= R;
+        ++i;
       }
     }
   }
@@ -154,7 +160,46 @@ __device__ __forceinline__ T loadb(const T* __restrict__ ak, int64_t idx, bool o
 }
 
 // Product of the stripe-mode factors at stripe s, column col (skip mode `skip`).
+// q = a / b, r = a % b for a >= 0, b >= 1 (wave-uniform): 32-bit division
+// when a fits, which is far shorter than the 64-bit sequence
+__device__ __forceinline__ void divmod(int64_t a, int64_t b, int64_t& q, int64_t& r) {
+  if (b == 1) {
+    q = a;
+    r = 0;
+  } else if (a <= 0x7fffffff && b <= 0x7fffffff) {
+    const uint32_t qa = (uint32_t)a / (uint32_t)b;
+    q = qa;
+    r = a - (int64_t)qa * b;
+  } else {
+    q = a / b;
+    r = a - q * b;
+  }
+}
+
+// prod_{m >= 2, m != skip} A^(m)(s_m, col) for stripe s.  With one stripe mode
+// (order 3) the entry is a plain load whose first use is at the end of the
+// unit, so its latency hides under the tensor stream.
 __device__ __forceinline__ double stripe_weight(const MttkrpDesc& d, int64_t s, int col, int skip) {
+  if (d.ns == 1) return (col < d.R && skip != 2) ? d.a64[2][s * d.R + col] : (col < d.R ? 1.0 : 0.0);
+  if (col >= d.R) return 0.0;
+  double w = 1.0;
+  for (int j = 0; j < d.ns; ++j) {
+    const int m = j + 2;
+    int64_t q, r, sj;
+    divmod(s, d.sst[j], q, r);
+    divmod(q, d.sext[j], r, sj);
+    if (m != skip) w *= d.a64[m][sj * d.R + col];
+  }
+  return w;
+}
+
+// The same product as a loop over the stripe modes, each entry multiplied in
+// as it arrives (the wait sits at the top of the unit).  Kinds 2 and 3 keep
+// this form and the 64-bit index split except in one FP32 tile-storing
+// variant: elsewhere the forms above cost registers (a wave per SIMD in
+// several FP32 variants) or time (the FP64 mode-1 launch at 256^3 took 2 us
+// longer).
+__device__ __forceinline__ double stripe_weight_loop(const MttkrpDesc& d, int64_t s, int col, int skip) {
   if (col >= d.R) return 0.0;
   double w = 1.0;
   for (int j = 0; j < d.ns; ++j) {
@@ -221,9 +266,9 @@ __device__ __forceinline__ void kind1_body(const MttkrpDesc& d, int blk, double*
   const int64_t ubeg = (int64_t)split * d.chunk;
   const int64_t uend = min(d.units, ubeg + d.chunk);
   for (int64_t u = ubeg + wave; u < uend; u += 4) {
-    const int64_t s = u / d.ksplit;
-    const int kp = (int)(u % d.ksplit);
-    const int64_t kbeg = (int64_t)kp * d.kchunk;
+    int64_t s, kp;
+    divmod(u, d.ksplit, s, kp);
+    const int64_t kbeg = kp * d.kchunk;
     const int64_t kend = min(I1, kbeg + d.kchunk);
     double w[NT];
 #pragma unroll
@@ -365,10 +410,18 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
   const int64_t ubeg = (int64_t)split * d.chunk;
   const int64_t uend = min(d.units, ubeg + d.chunk);
   const int jn = d.n - 2;
+  // the early-issued stripe weight and the short index split only where they
+  // cost no occupancy (the FP32 one-tile, two-row-tile, tile-storing kernel)
+  constexpr bool EARLYW = sizeof(T) == 4 && YS && NT == 1 && TW == 2;
   const int64_t stride_n = KIND3 ? d.sst[jn] : 1;
   for (int64_t u = ubeg + wave; u < uend; u += 4) {
-    const int kp = (int)(u % d.ksplit);
-    const int64_t uu = u / d.ksplit;
+    int64_t uu, kp;
+    if (EARLYW) {
+      divmod(u, d.ksplit, uu, kp);
+    } else {
+      kp = u % d.ksplit;
+      uu = u / d.ksplit;
+    }
     int64_t s, rowbase;
     if (KIND3) {
       const int64_t g = uu % d.rgroups;
@@ -390,7 +443,9 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
     const int64_t kend = min(I0, kbeg + d.kchunk);
     double w[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) w[t] = stripe_weight(d, s, t * 16 + r, KIND3 ? d.n : -1);
+    for (int t = 0; t < NT; ++t)
+      w[t] = EARLYW ? stripe_weight(d, s, t * 16 + r, KIND3 ? d.n : -1)
+                    : stripe_weight_loop(d, s, t * 16 + r, KIND3 ? d.n : -1);
     // stage-2 operands are loaded before the contraction loop so that their
     // latency overlaps the tensor stream
     double a1w[KIND3 ? TW : 1][KIND3 ? NT : 1][4];
@@ -550,8 +605,13 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
   }
 }
 
+// (the FP32 one-tile, 4-wide variant with the factor in LDS is held at three waves per
+// SIMD, which its streaming path fits without spills; left to itself the
+// compiler takes a few more registers)
 template <typename T, int NT, int VW, bool VEC, bool BL>
-__global__ __launch_bounds__(kThreads) void mttkrp_kind1(MttkrpDesc d) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu((NT == 1 && VW == 4 && sizeof(T) == 4 && BL) ? 3 : 1)))
+void mttkrp_kind1(MttkrpDesc d) {
   extern __shared__ double smem[];
   kind1_body<T, NT, VW, VEC, BL>(d, blockIdx.x, smem);
 }

@@ -97,6 +97,32 @@ def test_c3_mttkrp_every_mode(C, c3, mixed):
         assert e < (2e-5 if mixed else 1e-12)
 
 
+def test_c3_tuned_plans_cover_the_tile_storing_launch_and_round_trip(C, c3):
+    """The autotuner keeps a configuration for the mode-1 launch that stores
+    the stage-1 tiles (key suffix ;y), and a second context that imports the
+    exported plans runs bit-identical sweeps."""
+    import torch
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_MIXED, CP_SOLVE_CHOL
+    Z, A0, spec, Zd = c3
+    text = api.cp_plans_export(C)
+    keys = [ln.split()[0] for ln in text.strip().splitlines()]
+    say(f"tuned plans: {len(keys)} keys")
+    for prec in ("mixed", "fp64"):
+        assert any(k.endswith(f"n=1;R=10;prec={prec};y") for k in keys), keys
+    C2 = make_ctx()
+    api.cp_plans_import(C2, text)
+    outs = []
+    for ctx in (C, C2):
+        A = api.DeviceFactors.from_numpy(ctx, A0, fp32=True)
+        fh = torch.zeros(3, dtype=torch.float64, device="cuda")
+        api.cp_als_sweep(ctx, Zd, A, None, 3, CP_SOLVE_CHOL, 10, True, CP_MIXED, fh)
+        sync()
+        outs.append([a.copy() for a in A.to_numpy()] + [fh.cpu().numpy()])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_c3_als_sweeps_match_oracle(C, c3):
     from paper_1111_6091_amd import api
     from paper_1111_6091_amd._lib import CP_FP64, CP_SOLVE_CHOL
