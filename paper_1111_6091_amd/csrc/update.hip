@@ -273,6 +273,7 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
     if (kind == 0) {
       if (act) {
         double y = 0.0;
+#pragma unroll 4
         for (int j = 0; j < R; ++j) y = fma(sG[c * R + j], sB[rl * LDP + j], y);
         sY[rl * LDP + c] = y;
       }
@@ -280,6 +281,7 @@ __device__ __forceinline__ void epi_body(const EpiDesc& d, int blk, int nblk) {
       v = sY;
     }
     if (act) {
+#pragma unroll 4
       for (int k = 0; k < R; ++k) x = fma(v[rl * LDP + k], sG[k * R + c], x);
       wr = !(d.st && d.st->frozen[c / Rg]);
       if (wr) ip = x * m;
