@@ -129,12 +129,13 @@ def test_als_sweeps_track_oracle(C, dims, R, seed):
     assert C.status() == 0
 
 
-@pytest.mark.parametrize("dims,R", [((8, 5, 80, 256), 2), ((160, 24, 40), 20)])
+@pytest.mark.parametrize("dims,R", [((8, 5, 80, 256), 2), ((160, 24, 40), 20), ((16, 3, 5, 6, 7), 1)])
 def test_dimension_tree_sweeps_track_oracle(C, dims, R):
     """FP64 sweeps with and without the dimension tree against the oracle.  The
     shapes reach the Y-contracting launches' edge cases: rest-index chunks of
     32 plus a ragged one per workgroup (order 4, last split shorter), Y rows
-    fewer than one round of the workgroup (I1 = 5), and 17..32 columns."""
+    fewer than one round of the workgroup (I1 = 5, 3), 17..32 columns, one
+    column, and weights from two other stripe modes (order 5)."""
     from paper_1111_6091_amd import api
     from paper_1111_6091_amd._lib import CP_OPT_DIMTREE
     say(f"dimension-tree sweeps dims={dims} R={R}")
