@@ -94,6 +94,9 @@ def parse():
                    help="run only the Table 3/4 legs and print their JSON")
     p.add_argument("--restrict-only", action="store_true",
                    help="time only the coarse-tensor restrictions and print their JSON")
+    p.add_argument("--batched-only", action="store_true",
+                   help="run only the batched leg (512 problems x 4 restarts, mixed then FP64) and "
+                        "print its JSON; for profiler runs")
     p.add_argument("--sweeps-only", action="store_true",
                    help="time the mixed and FP64 sweeps only, then exit; for profiler runs")
     p.add_argument("--cold", action="store_true",
@@ -169,6 +172,9 @@ def main():
         return
     if args.restrict_only:
         print(json.dumps({"restriction": restrict_leg(ctx, api, synth)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(ctx, api, synth)}), flush=True)
         return
     if args.dense_only:
         print(json.dumps({"dense_table4": dense_leg(ctx, api, drivers, synth),
