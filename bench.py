@@ -113,8 +113,9 @@ def mttkrp_bytes(dims, R, n, elem_bytes):
 
 
 def tree_y_doubles(dims, R, elem_bytes):
-    """FP64 entries of the stage-1 tiles Y = Z x_1 A^(1)T the sweep keeps, or 0 when
-    the sweep runs one pass over Z per mode (order 2, or Y above a quarter of Z)."""
+    """Entries of the stage-1 tiles Y = Z x_1 A^(1)T the sweep keeps (stored in the
+    tensor's precision, elem_bytes each), or 0 when the sweep runs one pass over Z
+    per mode (order 2, or Y in FP64 above a quarter of Z's bytes)."""
     if len(dims) < 3:
         return 0
     yd = math.prod(dims[2:]) * dims[1] * R
@@ -129,9 +130,9 @@ def sweep_mttkrp_bytes(dims, R, n, elem_bytes):
     if yd == 0 or n == 0:
         return mttkrp_bytes(dims, R, n, elem_bytes)
     if n == 1:
-        return mttkrp_bytes(dims, R, n, elem_bytes) + yd * 8
+        return mttkrp_bytes(dims, R, n, elem_bytes) + yd * elem_bytes
     other = sum(d for m, d in enumerate(dims) if m >= 1 and m != n)
-    return yd * 8 + other * R * 8 + dims[n] * R * 8
+    return yd * elem_bytes + other * R * 8 + dims[n] * R * 8
 
 
 def sweep_mttkrp_overhead_bytes(dims, R, n, elem_bytes):
@@ -139,7 +140,7 @@ def sweep_mttkrp_overhead_bytes(dims, R, n, elem_bytes):
     MTTKRP: the mode-1 launch's Y store (the dimension tree's trade: written
     once, read by the modes >= 2 instead of another pass over Z)."""
     yd = tree_y_doubles(dims, R, elem_bytes)
-    return yd * 8 if (yd and n == 1) else 0
+    return yd * elem_bytes if (yd and n == 1) else 0
 
 
 def sweep_kernel_name(dims, R, n, tag):

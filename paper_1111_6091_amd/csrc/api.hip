@@ -492,8 +492,8 @@ cp_status enqueue_sweeps(cp_ctx ctx, const int64_t* dims, int N, int R, const vo
       int nsplit = sp.p[n].nsplit;
       if (tree && n >= 2) {
         ProfScope ps(ctx, fp32 ? CP_PROF_MTTKRP_MODEN_F32 : CP_PROF_MTTKRP_MODEN_F64);
-        HIPCHK(ymttkrp_launch(dims, N, n, R, w.y, (const double* const*)A, w.partial, sp.ynsplit[n], &pa,
-                              ctx->stream));
+        HIPCHK(ymttkrp_launch(dims, N, n, R, w.y, fp32, (const double* const*)A, w.partial, sp.ynsplit[n],
+                              &pa, ctx->stream));
         nsplit = sp.ynsplit[n];
       } else if (tree && n == 1) {
         ProfScope ps(ctx, fp32 ? CP_PROF_MTTKRP_MODE1_F32 : CP_PROF_MTTKRP_MODE1_F64);
@@ -1245,7 +1245,7 @@ cp_status cp_time_mttkrp(cp_ctx ctx, const cp_tensor* Z, const cp_factors* A, in
   const void* z = mixed ? (const void*)Z->z32 : (const void*)Z->z64;
   auto launch = [&]() -> hipError_t {
     if (tree && n >= 2)
-      return ymttkrp_launch(Z->dims, N, n, R, y, A->a, part, sp.ynsplit[n], &pa, ctx->stream);
+      return ymttkrp_launch(Z->dims, N, n, R, y, mixed, A->a, part, sp.ynsplit[n], &pa, ctx->stream);
     return mttkrp_launch(plan, Z->dims, N, n, R, z, mixed, A->a, (const float* const*)A->a32, part, &pa,
                          ctx->stream, y);
   };

@@ -131,7 +131,9 @@ struct MttkrpDesc {
   int32_t prep;                   // 1: workgroup 0 runs sweep_prep(pa) instead of streaming
   int32_t vec;                    // 4-wide tensor loads allowed (I0 % 4 == 0, aligned base)
   double* y;                      // kind 2 with ksplit == 1: also store the stage-1 tiles
-                                  // Y[s][i1][r] = sum_i0 Z(i0, i1, s) A^(0)(i0, r) (FP64)
+                                  // Y[s][i1][r] = sum_i0 Z(i0, i1, s) A^(0)(i0, r), in the
+                                  // tensor's precision (FP32 tensor: the FP32 MFMA sums as
+                                  // they are, stored as float at y; FP64: doubles)
   PrepArgs pa;
 };
 
@@ -139,7 +141,8 @@ struct MttkrpDesc {
 // mode-1 launch (Y depends only on Z and A^(0), so it serves every mode after 1):
 //   M^(n)(i_n, r) = sum_{s : s_n = i_n} sum_i1 Y[s][i1][r] A^(1)(i1, r) prod_{m >= 2, m != n} A^(m)(s_m, r)
 struct YDesc {
-  const double* y;                // [S][I1][R]
+  const double* y;                // [S][I1][R]; floats when y32
+  int32_t y32;
   const double* a64[kMaxOrder];
   double* out;                    // partials [nsplit][I_n][R]
   int64_t I1, S, In;
@@ -154,7 +157,7 @@ struct YDesc {
 };
 // plan (nsplit) for a mode-n launch from Y, and the launch itself
 int ymttkrp_nsplit(const int64_t* dims, int N, int n, int R);
-hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double* y,
+hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double* y, bool y32,
                           const double* const* a64, double* out, int nsplit, const PrepArgs* prep,
                           hipStream_t st);
 

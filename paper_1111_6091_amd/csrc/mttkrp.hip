@@ -29,7 +29,8 @@ void mttkrp_batched(const MttkrpDesc* __restrict__ descs, const int2* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Dimension-tree MTTKRP of mode n >= 2 from Y (FP64 throughout).  Workgroup
+// Dimension-tree MTTKRP of mode n >= 2 from Y (Y in the tensor's precision,
+// everything else FP64).  Workgroup
 // (row i_n, split) sums its chunk of rest indices q.  Lane layout: thread t
 // owns column c = t % RM of the rows t / RM, t / RM + 256 / RM, ... of each
 // Y block (Y[s] and A^(1) share the I1 x R row-major layout), so a wave reads
@@ -42,7 +43,7 @@ void mttkrp_batched(const MttkrpDesc* __restrict__ descs, const int2* __restrict
 // ---------------------------------------------------------------------------
 constexpr int kYQ = 32;
 
-template <int RM>
+template <int RM, bool Y32>
 __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
   extern __shared__ double smem[];
   if (d.prep && blockIdx.x == 0) {
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
   const int steps = (I1 + RPW - 1) / RPW;   // row steps per rest index
   const double* __restrict__ a1 = d.a64[1];
   const double* __restrict__ y = d.y;
+  const float* __restrict__ y32 = reinterpret_cast<const float*>(d.y);
   double acc = 0.0;
   for (int64_t q0 = qbeg; q0 < qend; q0 += kYQ) {
     const int nq = (int)min<int64_t>(kYQ, qend - q0);
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void ymttkrp_kernel(YDesc d) {
         const bool v = (t0 + u < T) && cok && i1 < I1;
         const int qs = qk < nq ? qk : nq - 1;
         const int64_t ar = (int64_t)(v ? i1 : 0) * R + cc;
-        yv[u] = y[sbase[qs] + ar];
+        yv[u] = Y32 ? (double)y32[sbase[qs] + ar] : y[sbase[qs] + ar];
         av[u] = a1[ar];
         wv[u] = v ? sw[qs * RM + c] : 0.0;
         if (++sk == steps) {
@@ -135,11 +137,12 @@ int ymttkrp_nsplit(const int64_t* dims, int N, int n, int R) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(rest, want));
 }
 
-hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double* y,
+hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double* y, bool y32,
                           const double* const* a64, double* out, int nsplit, const PrepArgs* prep,
                           hipStream_t st) {
   YDesc d{};
   d.y = y;
+  d.y32 = y32 ? 1 : 0;
   for (int m = 0; m < N; ++m) d.a64[m] = a64[m];
   d.out = out;
   d.I1 = dims[1];
@@ -166,8 +169,13 @@ hipError_t ymttkrp_launch(const int64_t* dims, int N, int n, int R, const double
   }
   const size_t smem = prep ? sizeof(double) * (size_t)prep_smem_doubles(N, R) : 0;
   dim3 grid((unsigned)(d.In * nsplit + d.prep)), block(kThreads);
-  if (R <= 16) hipLaunchKernelGGL(ymttkrp_kernel<16>, grid, block, smem, st, d);
-  else hipLaunchKernelGGL(ymttkrp_kernel<32>, grid, block, smem, st, d);
+  if (R <= 16) {
+    if (y32) hipLaunchKernelGGL((ymttkrp_kernel<16, true>), grid, block, smem, st, d);
+    else hipLaunchKernelGGL((ymttkrp_kernel<16, false>), grid, block, smem, st, d);
+  } else {
+    if (y32) hipLaunchKernelGGL((ymttkrp_kernel<32, true>), grid, block, smem, st, d);
+    else hipLaunchKernelGGL((ymttkrp_kernel<32, false>), grid, block, smem, st, d);
+  }
   return hipGetLastError();
 }
 

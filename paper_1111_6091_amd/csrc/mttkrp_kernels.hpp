@@ -543,7 +543,11 @@ __device__ __forceinline__ void kind23_body(const MttkrpDesc& d, int blk, double
           for (int v = 0; v < 4; ++v) {
             const int64_t i1 = rowbase + a * 16 + mfma_row<T>(g4, v);
             const int col = t * 16 + r;
-            if (i1 < I1 && col < R) d.y[((size_t)s * I1 + i1) * R + col] = (double)D[a][t][v];
+            if (i1 < I1 && col < R) {
+              const size_t yi = ((size_t)s * I1 + i1) * R + col;
+              if (sizeof(T) == 4) reinterpret_cast<float*>(d.y)[yi] = (float)D[a][t][v];
+              else d.y[yi] = (double)D[a][t][v];
+            }
           }
     }
     // Hadamard-reduce (FP64)
