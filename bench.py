@@ -497,14 +497,54 @@ def fas_leg(ctx, api, drivers, synth):
     fit_als = drivers.exact_fit(ctx, Zd, A)
     out["fas"] = {"cycles": r.sweeps, "seconds": round(tf, 4), "ms_per_cycle": round(1e3 * tf / r.sweeps, 3),
                   "fit": r.final_fit,
-                  "rel_fit_err_vs_oracle": abs(r.final_fit - g["fas_fit"]) / abs(g["fas_fit"])}
+                  "rel_fit_err_vs_oracle": abs(r.final_fit - g["fas_fit"]) / abs(g["fas_fit"]),
+                  "ms_per_cycle_by_level": fas_cost_by_level(ctx, api, synth, levels)}
     out["als"] = {"sweeps": ra.sweeps, "seconds": round(ta, 4), "us_per_sweep": round(1e6 * ta / ra.sweeps, 1),
                   "fit": fit_als}
     if g.get("als_fit"):
         out["als"]["rel_fit_err_vs_oracle"] = abs(fit_als - g["als_fit"]) / abs(g["als_fit"])
     log(f"128^3 FAS: {r.sweeps} V-cycles in {tf:.3f} s ({1e3 * tf / r.sweeps:.2f} ms/cycle), fit {r.final_fit:.13f}; "
-        f"ALS: {ra.sweeps} sweeps in {ta:.3f} s, fit {fit_als:.13f}")
+        f"ALS: {ra.sweeps} sweeps in {ta:.3f} s, fit {fit_als:.13f}; ms per cycle by level "
+        f"{[lv['ms'] for lv in out['fas']['ms_per_cycle_by_level']]}")
     return out
+
+
+def fas_cost_by_level(ctx, api, synth, levels, cycles=20):
+    """Cost of one V-cycle by level.  t_k: a cycle on the hierarchy from level k
+    down (level k then takes the finest level's place, without a right-hand
+    side), for every k with a coarser level below it; the coarsest level's
+    share is its nu_c = 50 Gauss-Seidel sweeps as the cycle runs them (one
+    workgroup).  Level k's share is t_k - t_(k+1), the last intermediate
+    level's t_k minus the coarsest share.  Factors of level k: 5 FP64 ALS
+    sweeps from a seeded start on that level's tensor."""
+    import torch
+
+    def timed(fn):
+        fn()   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(cycles):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / cycles
+
+    def factors(k):
+        Zk = levels[k][0]
+        A = api.DeviceFactors.from_numpy(ctx, synth.uniform_start(tuple(Zk.dims), 5, 11))
+        api.cp_als_sweep(ctx, Zk, A, None, 5, api.CP_SOLVE_CHOL, 10, True, api.CP_FP64)
+        return A
+
+    L = len(levels)
+    t = []
+    for k in range(L - 1):
+        A = factors(k)
+        t.append(timed(lambda: api.cp_fas_vcycle(ctx, levels[k:], A, nu1=1, nu2=1, nuc=50, gs_iters=10)))
+    A = factors(L - 1)
+    coarse = timed(lambda: api.cp_als_sweep(ctx, levels[-1][0], A, None, 50, api.CP_SOLVE_GS, 10, False,
+                                            api.CP_FP64))
+    share = [t[k] - t[k + 1] for k in range(L - 2)] + [t[L - 2] - coarse, coarse]
+    return [{"level": k, "dims": [int(d) for d in levels[k][0].dims], "ms": round(share[k], 3)}
+            for k in range(L)]
 
 
 # Table 4 (dense problem, averages over the paper's successful runs; MATLAB on a
