@@ -12,9 +12,12 @@
 // Per sweep and mode n (in the order of the oracle's BNGS sweep):
 //   Gamma^(n) = Hadamard product of the Grams of the other modes (eq. (8)),
 //   M^(n)     = Z_(n) Phi^(n) (eq. (6)-(7)), Khatri-Rao matrix never formed:
-//               mode 0 sums fibres along mode 0 weighted by the products of the
-//               other factors; after A^(0) is updated, the stage-1 tiles
-//               T0[s][r] = sum_i0 Z(i0, s) A^(0)(i0, r) serve every mode >= 1,
+//               mode 0 contracts the fibres along mode 0 with their weights,
+//               the products of the other factors; after A^(0) is updated, the
+//               stage-1 tiles T0[s][r] = sum_i0 Z(i0, s) A^(0)(i0, r) serve
+//               every mode >= 1.  Both mode-0 contractions are dense products
+//               and run on the matrix cores (v_mfma_f64_16x16x4f64), as do
+//               the Grams below,
 //   A^(n)     <- gs_iters Gauss-Seidel iterations on A^(n) Gamma = M + F, r in
 //               increasing order with the newest values, warm-started (the
 //               division by the pivot applied as a product with its reciprocal),
@@ -25,7 +28,14 @@
 
 namespace cpamg {
 
+typedef double sd4 __attribute__((ext_vector_type(4)));
+
 constexpr int kSmallThreads = 512;    // 8 waves, two per SIMD; leaves room for Gamma in registers
+constexpr int kSmallWaves = kSmallThreads / 64;
+
+// Fibre stride of the tensor in LDS: odd, so that the 16 fibres of one matrix
+// core operand (one entry each) fall on different banks.
+__host__ __device__ inline int64_t small_fibre_stride(int64_t I0) { return I0 | 1; }
 
 // LDS layout (in doubles unless noted); the host computes the same offsets
 struct SmallLayout {
@@ -48,12 +58,12 @@ __host__ __device__ inline SmallLayout small_layout(const SmallDesc& d, int esz)
   L.grams = o;  o += d.N * RR;
   L.gam = o;    o += RR;
   L.m = o;      o += imax * d.R;
-  L.red = o;    o += kSmallThreads;
+  L.red = o;    o += 128 * d.R > kSmallThreads ? 128 * d.R : kSmallThreads;   // also 8 partial 16 x R tiles or R x R Grams
   L.t0 = o;     o += S0 * d.R;
   L.dig = o;    o += (S0 * (d.N - 1) * 2 + 7) / 8;        // digits s_m of every fibre, uint16
   L.perm = o;   o += (S0 * (d.N - 1) * 4 + 7) / 8;        // fibres ordered by s_n, per mode n >= 1
   L.z = o;
-  L.bytes = o * 8 + d.P * esz;
+  L.bytes = o * 8 + S0 * small_fibre_stride(d.dims[0]) * esz;
   return L;
 }
 
@@ -191,7 +201,9 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
     }
   }
   const int I0 = I[0];
+  const int I0p = (int)small_fibre_stride(I0);
   const int S0 = (int)(d.P / I0);
+  const int lane = tid & 63, wave = tid >> 6, lc = lane & 15, lj = lane >> 4;
   const int NM = N - 1;   // modes 1..N-1
   const T* __restrict__ z = reinterpret_cast<const T*>(d.z);
   // tensor and factors into LDS (several loads in flight per thread)
@@ -205,7 +217,10 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t idx = base + tid + q * kSmallThreads;
-      if (idx < d.P) sZ[idx] = v[q];
+      if (idx < d.P) {
+        const int s = (int)idx / I0;
+        sZ[s * I0p + ((int)idx - s * I0)] = v[q];
+      }
     }
   }
   for (int m = 0; m < N; ++m)
@@ -234,34 +249,46 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
     }
   }
   __syncthreads();
-  // Gram of mode m from the LDS factor: the rows split over GG thread groups,
-  // the group sums added in group order (every thread calls it)
+  // Gram of mode m from the LDS factor on the matrix cores: A^T A as products
+  // of the 16-column tile with itself, the rows four per step.  Up to 64 rows
+  // one wave forms it alone; above that every wave takes a block of rows and
+  // the wave tiles are added in wave order (every thread calls it)
   auto gram = [&](int m) {
-    const int GG = RR >= kSmallThreads ? 1 : (kSmallThreads / RR < 16 ? kSmallThreads / RR : 16);
     const double* a = sA + offA[m];
-    for (int q0 = 0; q0 < RR; q0 += kSmallThreads) {
-      const int idx = q0 + (RR < kSmallThreads ? tid % RR : tid);
-      const int g = RR < kSmallThreads ? tid / RR : 0;
-      double acc = 0.0;
-      if (idx < RR && g < GG) {
-        const int r = idx / R, c = idx % R;
-        double a2 = 0.0;
-        int i = g;
-        for (; i + GG < I[m]; i += 2 * GG) {
-          acc += a[i * R + r] * a[i * R + c];
-          a2 += a[(i + GG) * R + r] * a[(i + GG) * R + c];
+    const int Im = I[m];
+    const int rc = lc < R ? lc : R - 1;
+    const bool one = Im <= 64;
+    const int chunk = one ? Im : ((Im + kSmallWaves - 1) / kSmallWaves + 15) & ~15;
+    const int sb = one ? 0 : wave * chunk;
+    const int se = sb + chunk < Im ? sb + chunk : Im;
+    if (!one || wave == 0) {
+      sd4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = sb; k0 < se; k0 += 16) {
+        double av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kc = k0 + 4 * u + lj < Im ? k0 + 4 * u + lj : Im - 1;
+          av[u] = a[kc * R + rc];
         }
-        if (i < I[m]) acc += a[i * R + r] * a[i * R + c];
-        acc += a2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double v = (k0 + 4 * u + lj < se && lc < R) ? av[u] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+        }
       }
-      if (GG > 1) {
-        if (idx < RR && g < GG) sRed[g * RR + idx] = acc;
-        __syncthreads();
-        if (tid < RR) sGr[m * RR + tid] = sum4(sRed + tid, GG, RR);
-        __syncthreads();
-      } else if (idx < RR) {
-        sGr[m * RR + idx] = acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = lj + 4 * v;
+        if (row < R && lc < R) {
+          if (one) sGr[m * RR + row * R + lc] = acc[v];
+          else sRed[wave * RR + row * R + lc] = acc[v];
+        }
       }
+    }
+    if (!one) {
+      __syncthreads();
+      if (tid < RR) sGr[m * RR + tid] = sum4(sRed + tid, kSmallWaves, RR);
+      __syncthreads();
     }
   };
   for (int m = 0; m < N; ++m) gram(m);
@@ -286,10 +313,59 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
         }
         __syncthreads();
       }
-      // M^(n): (row, column) pairs, the contraction split over G thread groups
-      const int pairs = I[n] * R;
-      const int G = pairs >= kSmallThreads ? 1 : kSmallThreads / pairs;
-      const int rest = S0 / (n == 0 ? 1 : I[n]);
+      if (n == 0) {
+        // M^(0) = Z_(0) W on the matrix cores: 16-row tiles of mode 0 by the R
+        // columns, the fibres s (the contraction) four per step; with fewer
+        // row tiles than waves the fibres are split into KC chunks whose
+        // partial tiles are then added in chunk order
+        const int nt = (I0 + 15) >> 4;
+        const int KC = nt >= kSmallWaves ? 1 : kSmallWaves / nt;
+        const int chunk = ((S0 + KC - 1) / KC + 3) & ~3;
+        for (int w = wave; w < nt * KC; w += kSmallWaves) {
+          const int t = w % nt, kc = w / nt;
+          const int sb = kc * chunk, se = sb + chunk < S0 ? sb + chunk : S0;
+          const int i = t * 16 + lc;
+          const int ic = i < I0 ? i : I0 - 1, cc = lc < R ? lc : R - 1;
+          sd4 acc = {0.0, 0.0, 0.0, 0.0};
+          // four steps per round, every operand load issued before the first
+          // product (addresses clamped in range, masked entries zeroed after)
+          for (int s0 = sb; s0 < se; s0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int sc = s0 + 4 * u + lj < S0 ? s0 + 4 * u + lj : S0 - 1;
+              av[u] = (double)sZ[sc * I0p + ic];
+              bv[u] = sT0[sc * R + cc];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool in = s0 + 4 * u + lj < se;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64((in && i < I0) ? av[u] : 0.0,
+                                                        (in && lc < R) ? bv[u] : 0.0, acc, 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = t * 16 + lj + 4 * v;   // result rows interleave as g + 4v
+            if (lc < R && row < I0) {
+              if (KC == 1) sM[row * R + lc] = acc[v];
+              else sRed[(kc * nt + t) * 16 * R + (lj + 4 * v) * R + lc] = acc[v];
+            }
+          }
+        }
+        if (KC > 1) {
+          __syncthreads();
+          for (int idx = tid; idx < I0 * R; idx += kSmallThreads) {
+            const int i = idx / R, c = idx - (idx / R) * R;
+            const double* p = sRed + ((i >> 4) * 16 + (i & 15)) * R + c;
+            sM[idx] = sum4(p, KC, nt * 16 * R);
+          }
+        }
+      }
+      // M^(n), n >= 1: (row, column) pairs, the contraction split over G thread groups
+      const int pairs = n == 0 ? 0 : I[n] * R;
+      const int G = pairs >= kSmallThreads ? 1 : kSmallThreads / (pairs > 0 ? pairs : 1);
+      const int rest = S0 / I[n];
       for (int q0 = 0; q0 < pairs; q0 += kSmallThreads) {
         const int q = q0 + tid % (pairs < kSmallThreads ? pairs : kSmallThreads);
         const int g = pairs < kSmallThreads ? tid / pairs : 0;
@@ -300,14 +376,7 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
           double a4[4] = {0.0, 0.0, 0.0, 0.0};
           // four accumulators with static indices (a runtime index would
           // move the array out of registers)
-          if (n == 0) {
-            int s = g;
-            for (; s + 3 * G < S0; s += 4 * G)
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                a4[u] += (double)sZ[(s + u * G) * I0 + i] * sT0[(s + u * G) * R + r];
-            for (; s < S0; s += G) a4[0] += (double)sZ[s * I0 + i] * sT0[s * R + r];
-          } else {
+          {
             const int32_t* pr = sPerm + (n - 1) * S0 + i * rest;
             auto term = [&](int k) {
               const int s = pr[k];
@@ -338,21 +407,35 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
       __syncthreads();
       gram(n);
       if (n == 0 && N > 1) {
-        // stage-1 tiles of the updated A^(0) for the modes >= 1 of this sweep
-        for (int idx = tid; idx < S0 * R; idx += kSmallThreads) {
-          const int s = idx / R, r = idx - (idx / R) * R;
-          const T* zf = sZ + s * I0;
-          const double* a0 = sA + offA[0];
-          double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-          int i0 = 0;
-          for (; i0 + 3 < I0; i0 += 4) {
-            t0 += (double)zf[i0] * a0[i0 * R + r];
-            t1 += (double)zf[i0 + 1] * a0[(i0 + 1) * R + r];
-            t2 += (double)zf[i0 + 2] * a0[(i0 + 2) * R + r];
-            t3 += (double)zf[i0 + 3] * a0[(i0 + 3) * R + r];
+        // stage-1 tiles of the updated A^(0) for the modes >= 1 of this sweep,
+        // T0 = Z_(0)^T A^(0) on the matrix cores: 16 fibres by the R columns
+        // per tile, mode 0 (the contraction) four entries per step
+        const double* a0 = sA + offA[0];
+        for (int s0 = wave * 16; s0 < S0; s0 += 16 * kSmallWaves) {
+          const int s = s0 + lc;
+          const T* zf = sZ + (s < S0 ? s : S0 - 1) * I0p;
+          const int cc = lc < R ? lc : R - 1;
+          sd4 acc = {0.0, 0.0, 0.0, 0.0};
+          for (int k0 = 0; k0 < I0; k0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int kc = k0 + 4 * u + lj < I0 ? k0 + 4 * u + lj : I0 - 1;
+              av[u] = (double)zf[kc];
+              bv[u] = a0[kc * R + cc];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool in = k0 + 4 * u + lj < I0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64((in && s < S0) ? av[u] : 0.0,
+                                                        (in && lc < R) ? bv[u] : 0.0, acc, 0, 0, 0);
+            }
           }
-          for (; i0 < I0; ++i0) t0 += (double)zf[i0] * a0[i0 * R + r];
-          sT0[idx] = (t0 + t1) + (t2 + t3);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int so = s0 + lj + 4 * v;
+            if (lc < R && so < S0) sT0[so * R + lc] = acc[v];
+          }
         }
       }
       __syncthreads();
