@@ -98,14 +98,16 @@ __device__ __forceinline__ void gs_rows(double* X, const double* sM, const doubl
   for (int i = threadIdx.x; i < I; i += NT) {
     // the equations scaled by the reciprocal pivots: c_r = b_r / Gamma_rr,
     // h[k][r] = Gamma_kr / Gamma_rr, so that x_r = c_r - sum_{k != r} x_k h[k][r]
-    double x[RM], c[RM], h[RM][RM];
-    bool piv[RM];
+    // A zero pivot (and every r >= R) gets c_r = 0, h[.][r] = 0 and keep_r =
+    // 1, so that t_r = x_r: the old value stays without a select in the chain
+    double x[RM], c[RM], h[RM][RM], keep[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       x[r] = r < R ? X[i * R + r] : 0.0;
       const double dg = r < R ? sG[r * R + r] : 0.0;
-      piv[r] = dg != 0.0;
-      const double dinv = piv[r] ? 1.0 / dg : 0.0;
+      const bool piv = dg != 0.0;
+      keep[r] = piv ? 0.0 : 1.0;
+      const double dinv = piv ? 1.0 / dg : 0.0;
       c[r] = r < R ? (sM[i * R + r] + sF[i * R + r]) * dinv : 0.0;
 #pragma unroll
       for (int k = 0; k < RM; ++k) h[k][r] = (k < R && r < R) ? sG[k * R + r] * dinv : 0.0;
@@ -120,11 +122,11 @@ __device__ __forceinline__ void gs_rows(double* X, const double* sM, const doubl
         double u = 0.0;
 #pragma unroll
         for (int k = r + 1; k < RM; ++k) u += x[k] * h[k][r];
-        t[r] = c[r] - u;
+        t[r] = fma(x[r], keep[r], c[r] - u);
       }
 #pragma unroll
       for (int r = 0; r < RM; ++r) {
-        x[r] = piv[r] ? t[r] : x[r];
+        x[r] = t[r];
 #pragma unroll
         for (int j = r + 1; j < RM; ++j) t[j] -= x[r] * h[r][j];
       }
@@ -304,12 +306,27 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
         sG[idx] = g;
       }
       if (n == 0) {
-        // weights W[s][r] = prod_{m >= 1} A^(m)(s_m, r) of every fibre
-        for (int idx = tid; idx < S0 * R; idx += kSmallThreads) {
-          const int s = idx / R, r = idx - (idx / R) * R;
-          double w = 1.0;
-          for (int m = 1; m < N; ++m) w *= sA[offA[m] + sDig[s * NM + m - 1] * R + r];
-          sT0[idx] = w;
+        // weights W[s][r] = prod_{m >= 1} A^(m)(s_m, r) of every fibre, four
+        // entries per thread at a time so that their loads overlap
+        for (int base = tid; base < S0 * R; base += 4 * kSmallThreads) {
+          double w[4] = {1.0, 1.0, 1.0, 1.0};
+          int sx[4], rx[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int idx = base + u * kSmallThreads < S0 * R ? base + u * kSmallThreads : S0 * R - 1;
+            sx[u] = idx / R;
+            rx[u] = idx - sx[u] * R;
+          }
+          for (int m = 1; m < N; ++m) {
+            int dg[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dg[u] = sDig[sx[u] * NM + m - 1];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] *= sA[offA[m] + dg[u] * R + rx[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (base + u * kSmallThreads < S0 * R) sT0[base + u * kSmallThreads] = w[u];
         }
         __syncthreads();
       }
@@ -362,8 +379,41 @@ __global__ __launch_bounds__(kSmallThreads) void relax_small_kernel(SmallDesc d)
           }
         }
       }
-      // M^(n), n >= 1: (row, column) pairs, the contraction split over G thread groups
-      const int pairs = n == 0 ? 0 : I[n] * R;
+      if (n > 0 && N == 3) {
+        // three-way tensors: the fibres with s_n = i are s = i st[n] + k st[m]
+        // over the index k of the other mode m, so every (row, column) pair
+        // sums its I_m terms itself, the loads of eight terms issued first;
+        // each row starts at its own k = i mod I_m and wraps around, so that
+        // the rows of one wave read from different banks
+        const int m = 3 - n, Im = I[m], tsd = st[m] * R;
+        for (int q = tid; q < I[n] * R; q += kSmallThreads) {
+          const int i = q / R, r = q - (q / R) * R;
+          const double* tp = sT0 + i * st[n] * R + r;
+          const double* ap = sA + offA[m] + r;
+          int k = i % Im;
+          double a4[4] = {0.0, 0.0, 0.0, 0.0};
+          int c = 0;
+          for (; c + 7 < Im; c += 8) {
+            double tv[8], av[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              tv[u] = tp[k * tsd];
+              av[u] = ap[k * R];
+              k = k + 1 == Im ? 0 : k + 1;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a4[u & 3] += tv[u] * av[u];
+          }
+          for (; c < Im; ++c) {
+            a4[0] += tp[k * tsd] * ap[k * R];
+            k = k + 1 == Im ? 0 : k + 1;
+          }
+          sM[q] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        }
+      }
+      // M^(n), n >= 1, other orders: (row, column) pairs, the contraction
+      // split over G thread groups
+      const int pairs = (n == 0 || N == 3) ? 0 : I[n] * R;
       const int G = pairs >= kSmallThreads ? 1 : kSmallThreads / (pairs > 0 ? pairs : 1);
       const int rest = S0 / I[n];
       for (int q0 = 0; q0 < pairs; q0 += kSmallThreads) {

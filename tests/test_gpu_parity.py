@@ -230,11 +230,14 @@ def test_als_gs_with_rhs_matches_oracle_bngs(C):
 @pytest.mark.parametrize("dims,R,sweeps,mixed", [
     ((14, 15, 16), 3, 3, False), ((10, 10, 10), 5, 50, False), ((6, 7, 8, 5), 4, 4, False),
     ((12, 9), 2, 5, False), ((16, 16, 16), 16, 3, False), ((16, 16, 16), 5, 20, True),
-    ((7, 5, 9), 8, 6, False)])
+    ((7, 5, 9), 8, 6, False), ((40, 70, 3), 4, 4, False), ((130, 6, 5), 3, 4, False)])
 def test_small_level_relaxation_matches_oracle(C, dims, R, sweeps, mixed):
     """BNGS sweeps with a right-hand side and Gauss-Seidel solves, no
     normalization (a coarse-level relaxation of Algorithm 2) on tensors that fit
-    in LDS: one workgroup runs every sweep.  With an FP32 tensor the kernel widens
+    in LDS: one workgroup runs every sweep.  The shapes cover one and several
+    16-row tiles of mode 0 (the matrix-core contractions split over the waves
+    or looping over tiles), Grams of more than 64 rows (split over the waves),
+    orders 2, 3 and 4, and ragged sizes.  With an FP32 tensor the kernel widens
     each entry and computes in FP64, so it is held against the oracle on the
     FP32-rounded tensor.  The same call with the option off (general kernels)
     agrees too."""
@@ -261,6 +264,41 @@ def test_small_level_relaxation_matches_oracle(C, dims, R, sweeps, mixed):
         for n in range(len(dims)):
             e = elem_err(got[n], ref[n], floor=1e-3 if sweeps <= 6 else 1.0)
             assert e < tol, (small, n, e)
+    C.set_option(CP_OPT_SMALL_LEVELS, 1)
+    assert C.status() == 0
+
+
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_small_level_gs_zero_pivot_keeps_the_entry(C, sweeps):
+    """A zero column in the starting A^(1) makes Gamma^(0) and Gamma^(2) singular
+    with a zero diagonal entry: Gauss-Seidel leaves that component of the row as
+    it is (Section 5.2 solves only where the pivot is nonzero; the oracle does
+    the same), in the small-level kernel and in the general kernels alike."""
+    from paper_1111_6091_amd import api
+    from paper_1111_6091_amd._lib import CP_OPT_SMALL_LEVELS
+    say(f"small-level GS zero pivot sweeps={sweeps}")
+    dims, R = (10, 11, 12), 3
+    rng = np.random.default_rng(8)
+    Z = rng.standard_normal(dims)
+    A0 = [rng.random((d, R)) for d in dims]
+    A0[1][:, 2] = 0.0
+    F = [0.1 * rng.standard_normal((d, R)) for d in dims]
+    ref = A0
+    for _ in range(sweeps):
+        ref = amg.bngs(Z, ref, F, gs_iters=10, normalize_after=False)
+    Fd = api.DeviceFactors.from_numpy(C, F)
+    for small in (1, 0):
+        C.set_option(CP_OPT_SMALL_LEVELS, small)
+        Zd, Ad = dev_inputs(C, Z, A0, fp32=False)
+        api.cp_als_sweep(C, Zd, Ad, Fd, sweeps, api.CP_SOLVE_GS, 10, False, api.CP_FP64, None)
+        sync()
+        got = Ad.to_numpy()
+        for n in range(3):
+            e = elem_err(got[n], ref[n], floor=1e-3)
+            assert e < 1e-9, (small, n, e)
+        if sweeps == 1:
+            # mode 0 ran with the zero pivot: column 2 of A^(0) is the start's
+            np.testing.assert_array_equal(got[0][:, 2], A0[0][:, 2])
     C.set_option(CP_OPT_SMALL_LEVELS, 1)
     assert C.status() == 0
 
