@@ -116,96 +116,129 @@ hipError_t transfer_build_launch(int64_t I, const double* w, double* phat, doubl
 }
 
 // ---------------------------------------------------------------------------
-__global__ void prolong_kernel(int64_t I, int64_t Ic, int R, const double* __restrict__ phat,
-                               const double* __restrict__ Ac, const double* __restrict__ Act,
-                               double* __restrict__ A) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= I * R) return;
-  const int64_t i = idx / R;
-  const int r = (int)(idx % R);
+// The three products with P^ (operands of at most a few hundred rows) are
+// latency-bound: each output is the sum of one dense row or column of P^
+// against a factor column.  kSplit consecutive lanes share an output, lane g
+// taking the terms g, g + kSplit, ... (four partial sums), and the lanes' sums
+// meet in an xor tree; the order is fixed, so results are deterministic.
+constexpr int kSplit = 8;
+
+__device__ __forceinline__ double split_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < kSplit; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+inline unsigned split_blocks(int64_t outputs) {
+  return (unsigned)((outputs * kSplit + 255) / 256);
+}
+
+__global__ __launch_bounds__(256) void prolong_kernel(int64_t I, int64_t Ic, int R,
+                                                      const double* __restrict__ phat,
+                                                      const double* __restrict__ Ac,
+                                                      const double* __restrict__ Act,
+                                                      double* __restrict__ A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = t / kSplit;
+  const int g = (int)(t % kSplit);
+  const bool live = o < I * R;
+  const int64_t oc = live ? o : I * R - 1;   // idle lanes still take part in the sums
+  const int64_t i = oc / R;
+  const int r = (int)(oc % R);
   double acc;
   if (phat) {
-    // four partial sums, so that many loads are in flight per thread
     const double* prow = phat + i * Ic;
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t j = 0;
-    for (; j + 3 < Ic; j += 4)
+    int64_t j = g;
+    for (; j + 3 * kSplit < Ic; j += 4 * kSplit)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t jj = j + u;
+        const int64_t jj = j + u * kSplit;
         a4[u] += prow[jj] * (Act ? (Ac[jj * R + r] - Act[jj * R + r]) : Ac[jj * R + r]);
       }
-    for (int u = 0; j < Ic; ++j, ++u)
+    for (int u = 0; j < Ic; j += kSplit, ++u)
       a4[u] += prow[j] * (Act ? (Ac[j * R + r] - Act[j * R + r]) : Ac[j * R + r]);
-    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    acc = split_sum((a4[0] + a4[1]) + (a4[2] + a4[3]));
   } else {
     acc = Act ? (Ac[i * R + r] - Act[i * R + r]) : Ac[i * R + r];
   }
-  A[idx] = Act ? A[idx] + acc : acc;
+  if (live && g == 0) A[o] = Act ? A[o] + acc : acc;
 }
 
 hipError_t prolong_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* Ac,
                           const double* Act, double* A, hipStream_t st) {
-  const int64_t n = I * R;
-  hipLaunchKernelGGL(prolong_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, I, Ic,
-                     R, phat, Ac, Act, A);
+  if (I * R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prolong_kernel, dim3(split_blocks(I * R)), dim3(256), 0, st, I, Ic, R, phat,
+                     Ac, Act, A);
   return hipGetLastError();
 }
 
-__global__ void restrict_factor_kernel(int64_t I, int64_t Ic, int R,
-                                       const double* __restrict__ phat,
-                                       const double* __restrict__ A, double* __restrict__ Ac) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= Ic * R) return;
-  const int64_t j = idx / R;
-  const int r = (int)(idx % R);
-  double acc = 0.0;
+__global__ __launch_bounds__(256) void restrict_factor_kernel(int64_t I, int64_t Ic, int R,
+                                                              const double* __restrict__ phat,
+                                                              const double* __restrict__ A,
+                                                              double* __restrict__ Ac) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = t / kSplit;
+  const int g = (int)(t % kSplit);
+  const bool live = o < Ic * R;
+  const int64_t oc = live ? o : Ic * R - 1;
+  const int64_t j = oc / R;
+  const int r = (int)(oc % R);
+  double acc;
   if (phat) {
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t i = 0;
-    for (; i + 3 < I; i += 4)
+    int64_t i = g;
+    for (; i + 3 * kSplit < I; i += 4 * kSplit)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] += phat[(i + u) * Ic + j] * A[(i + u) * R + r];
-    for (int u = 0; i < I; ++i, ++u) a4[u] += phat[i * Ic + j] * A[i * R + r];
-    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+      for (int u = 0; u < 4; ++u) a4[u] += phat[(i + u * kSplit) * Ic + j] * A[(i + u * kSplit) * R + r];
+    for (int u = 0; i < I; i += kSplit, ++u) a4[u] += phat[i * Ic + j] * A[i * R + r];
+    acc = split_sum((a4[0] + a4[1]) + (a4[2] + a4[3]));
   } else {
     acc = A[j * R + r];
   }
-  Ac[idx] = acc;
+  if (live && g == 0) Ac[o] = acc;
 }
 
 hipError_t restrict_factor_launch(int64_t I, int64_t Ic, int R, const double* phat,
                                   const double* A, double* Ac, hipStream_t st) {
-  const int64_t n = Ic * R;
-  hipLaunchKernelGGL(restrict_factor_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     I, Ic, R, phat, A, Ac);
+  if (Ic * R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(restrict_factor_kernel, dim3(split_blocks(Ic * R)), dim3(256), 0, st, I, Ic,
+                     R, phat, A, Ac);
   return hipGetLastError();
 }
 
-__global__ void fas_rhs_kernel(int64_t I, int64_t Ic, int R, const double* __restrict__ phat,
-                               const double* __restrict__ F, const double* __restrict__ H,
-                               const double* __restrict__ Hc, double* __restrict__ Fc) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= Ic * R) return;
-  const int64_t j = idx / R;
-  const int r = (int)(idx % R);
+__global__ __launch_bounds__(256) void fas_rhs_kernel(int64_t I, int64_t Ic, int R,
+                                                      const double* __restrict__ phat,
+                                                      const double* __restrict__ F,
+                                                      const double* __restrict__ H,
+                                                      const double* __restrict__ Hc,
+                                                      double* __restrict__ Fc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = t / kSplit;
+  const int g = (int)(t % kSplit);
+  const bool live = o < Ic * R;
+  const int64_t oc = live ? o : Ic * R - 1;
+  const int64_t j = oc / R;
+  const int r = (int)(oc % R);
   double a4[4] = {0.0, 0.0, 0.0, 0.0};
-  int64_t i = 0;
-  for (; i + 3 < I; i += 4)
+  int64_t i = g;
+  for (; i + 3 * kSplit < I; i += 4 * kSplit)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t ii = i + u;
+      const int64_t ii = i + u * kSplit;
       a4[u] += phat[ii * Ic + j] * ((F ? F[ii * R + r] : 0.0) - H[ii * R + r]);
     }
-  for (int u = 0; i < I; ++i, ++u) a4[u] += phat[i * Ic + j] * ((F ? F[i * R + r] : 0.0) - H[i * R + r]);
-  Fc[idx] = Hc[idx] + ((a4[0] + a4[1]) + (a4[2] + a4[3]));
+  for (int u = 0; i < I; i += kSplit, ++u)
+    a4[u] += phat[i * Ic + j] * ((F ? F[i * R + r] : 0.0) - H[i * R + r]);
+  const double acc = split_sum((a4[0] + a4[1]) + (a4[2] + a4[3]));
+  if (live && g == 0) Fc[o] = Hc[o] + acc;
 }
 
 hipError_t fas_rhs_launch(int64_t I, int64_t Ic, int R, const double* phat, const double* F,
                           const double* H, const double* Hc, double* Fc, hipStream_t st) {
-  const int64_t n = Ic * R;
-  hipLaunchKernelGGL(fas_rhs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, I, Ic,
-                     R, phat, F, H, Hc, Fc);
+  if (Ic * R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fas_rhs_kernel, dim3(split_blocks(Ic * R)), dim3(256), 0, st, I, Ic, R, phat,
+                     F, H, Hc, Fc);
   return hipGetLastError();
 }
 

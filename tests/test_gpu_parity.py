@@ -436,10 +436,13 @@ def test_identity_restriction_returns_z(C):
     np.testing.assert_array_equal(Zc.to_numpy(), Z)
 
 
-def test_prolong_and_restrict_factor(C):
+@pytest.mark.parametrize("I,R", [(21, 4), (130, 5), (3, 1)])
+def test_prolong_and_restrict_factor(C, I, R):
+    """A = P^ Ac, A += P^ (Ac - A~c) and A~c = P^T A (Algorithm 2's transfers of
+    the factors): sizes whose contraction is shorter than, a ragged multiple of,
+    and several times the kernels' eight-lane split."""
     from paper_1111_6091_amd import api
     rng = np.random.default_rng(9)
-    I, R = 21, 4
     p = amg.transfer(amg.interp_from_weights(I, synth.linear_interp_weights(I)))[2]
     Ic = p.shape[1]
     A = rng.standard_normal((I, R))
