@@ -99,11 +99,19 @@ def als_solve(ctx, Z, A, max_sweeps=10000, fit_tol=1e-12, chunk=16, prec=CP_FP64
     return res
 
 
-def exact_fit(ctx, Z, A):
+def exact_fit(ctx, Z, A, f=None, norm2=None):
+    """Fit 1 - ||Z - [[A]]|| / ||Z|| from the exact objective.  In a loop, pass
+    ``f`` (a device scalar to reuse) and ``norm2`` (||Z||^2 read once) to spare
+    the allocation and the second read-back per call."""
     torch = _torch()
-    f = torch.zeros(1, dtype=torch.float64, device=Z.device)
+    if f is None:
+        f = torch.zeros(1, dtype=torch.float64, device=Z.device)
+    else:
+        f.zero_()
     api.cp_objective(ctx, Z, A, exact=True, f=f)
-    return fit_from_f(float(f.item()), float(Z.norm2.item()))
+    if norm2 is None:
+        norm2 = float(Z.norm2.item())
+    return fit_from_f(float(f.item()), norm2)
 
 
 def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000, chunk64=16):
@@ -191,14 +199,17 @@ def fas_solve(ctx, levels, Z, A, fit_tol=1e-12, max_cycles=500, nu1=1, nu2=1, nu
     ``window`` > 1 stops only when the last ``window`` changes are all within
     the tolerance (1: the plain rule, as the oracle's driver applies it).
     """
+    torch = _torch()
     res = SolveResult()
     prev = None
     cur = prec
     small = 0
+    fbuf = torch.zeros(1, dtype=torch.float64, device=Z.device)
+    norm2 = float(Z.norm2.item())
     while res.sweeps < max_cycles:
         api.cp_fas_vcycle(ctx, levels, A, nu1=nu1, nu2=nu2, nuc=nuc, gs_iters=gs_iters, ic_rule=ic_rule,
                           prec=cur)
-        fit = exact_fit(ctx, Z, A)
+        fit = exact_fit(ctx, Z, A, fbuf, norm2)
         res.fits.append(fit)
         res.sweeps += 1
         if cur == CP_MIXED:
