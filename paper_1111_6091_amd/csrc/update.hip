@@ -376,10 +376,52 @@ struct GramArgs {
   int64_t dims[kMaxOrder];
 };
 
+typedef double gd4 __attribute__((ext_vector_type(4)));
+
+// R <= 16: U = A^T A on the matrix cores, as products of the 16-column row
+// tile with itself (v_mfma_f64_16x16x4f64), four rows per step with the loads
+// of a step issued first; the four waves take interleaved 16-row blocks and
+// their tiles are added in wave order.
+__device__ __forceinline__ void gram_body_mfma(const double* __restrict__ A, float* A32, int64_t I,
+                                               int R, double* gram_out, double* sigma_out) {
+  __shared__ double part[(kThreads / 64) * 256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lc = lane & 15, lj = lane >> 4;
+  const int RR = R * R;
+  const int rc = lc < R ? lc : R - 1;
+  gd4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = (int64_t)wave * 16; i0 < I; i0 += 16 * (kThreads / 64)) {
+    double av[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = i0 + 4 * u + lj;
+      av[u] = A[(row < I ? row : I - 1) * R + rc];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double v = (i0 + 4 * u + lj < I && lc < R) ? av[u] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = lj + 4 * v;   // result rows interleave as g + 4v
+    if (row < R && lc < R) part[wave * RR + row * R + lc] = acc[v];
+  }
+  if (A32)
+    for (int64_t idx = tid; idx < I * R; idx += kThreads) A32[idx] = (float)A[idx];
+  __syncthreads();
+  if (tid < RR) gram_out[tid] = (part[tid] + part[RR + tid]) + (part[2 * RR + tid] + part[3 * RR + tid]);
+  if (sigma_out && tid < R) sigma_out[tid] = 1.0;
+}
+
 // Gram U = A^T A of one I x R factor into gram_out (R x R); refreshes the FP32
 // shadow when A32 is set and resets the column scales when sigma_out is set.
 __device__ __forceinline__ void gram_body(const double* __restrict__ A, float* A32, int64_t I, int R,
                                           double* gram_out, double* sigma_out) {
+  if (R <= 16) {
+    gram_body_mfma(A, A32, I, R, gram_out, sigma_out);
+    return;
+  }
   __shared__ double tile[64 * LDP];
   double acc[4] = {0, 0, 0, 0};
   for (int64_t i0 = 0; i0 < I; i0 += 64) {
