@@ -517,11 +517,17 @@ def multilevel(ctx, Z, A, tfms, coarsest, tau=1e-10, max_cycles=500, setup=None,
                 iterations=len(shist) + len(hist))
 
 
-def tune_batched(ctx, problems, restarts, prec, candidates=(48, 96, 192, 384, 768), sweeps=8):
+def tune_batched(ctx, problems, restarts, prec, candidates=(48, 96, 192, 384, 768), sweeps=8,
+                 near=0.03):
     """Launch-tile tuner of the batched solve: times `sweeps` sweeps of the whole
     batch (every restart running: no stopping rule) for each candidate tensor
     KiB per streaming workgroup, on copies of the factors, and returns
-    (best wg_kib, {wg_kib: seconds})."""
+    (chosen wg_kib, {wg_kib: seconds}).
+
+    The choice is the smallest tile within ``near`` (relative) of the fastest:
+    the timed sweeps have every restart active, while the solve spends much of
+    its time with fewer problems left, where smaller tiles spread what remains
+    over more workgroups."""
     torch = _torch()
     times = {}
     work = [(Z, A.clone()) for Z, A in problems]
@@ -538,5 +544,10 @@ def tune_batched(ctx, problems, restarts, prec, candidates=(48, 96, 192, 384, 76
         e1.record(st)
         torch.cuda.synchronize()
         times[kib] = e0.elapsed_time(e1) / 1e3
-    best = min(times, key=times.get)
-    return best, times
+    return pick_tile(times, near), times
+
+
+def pick_tile(times, near=0.03):
+    """Smallest key of {tile: seconds} whose time is within ``near`` of the fastest."""
+    fastest = min(times.values())
+    return min(k for k, t in times.items() if t <= fastest * (1.0 + near))

@@ -34,3 +34,15 @@ def test_no_tree_cases():
     assert bench.tree_y_doubles((300, 200), 5, 8) == 0
     assert bench.tree_y_doubles((4, 64, 64), 10, 8) == 0   # Y = 64*64*10*8 B > (4*64*64*8) / 4 B
     assert bench.sweep_mttkrp_bytes((4, 64, 64), 10, 2, 8) == bench.mttkrp_bytes((4, 64, 64), 10, 2, 8)
+
+
+def test_batched_tile_choice_prefers_the_smaller_tile_on_a_near_tie():
+    """The batched tile tuner times the batch with every restart active; on a
+    near tie (within 3 %) the smaller tile wins, otherwise the fastest."""
+    from paper_1111_6091_amd.drivers import pick_tile
+    # measured: 96 KiB 16.56 ms against 192 KiB 16.43 ms (mixed) -> 96
+    assert pick_tile({48: 24.17, 96: 16.56, 192: 16.43, 384: 17.44, 768: 19.15}) == 96
+    # 96 KiB 4 % slower than 192 KiB (FP64) -> 192
+    assert pick_tile({48: 19.45, 96: 17.05, 192: 16.39, 384: 16.63, 768: 17.78}) == 192
+    assert pick_tile({48: 1.0}) == 48
+    assert pick_tile({48: 2.0, 96: 1.0}, near=0.0) == 96
