@@ -368,7 +368,9 @@ def main():
         fitm = drivers.exact_fit(ctx, Zd, A)
         log(f"mixed to 1e-12: {rm.sweeps32} FP32 + {rm.sweeps64} FP64 sweeps, {tm:.3f} s, fit {fitm:.15f}")
         equal_fit = {
-            "stop": "relative fit change <= 1e-12 (FP32 phase: mean gain <= 1e-9 per sweep)",
+            "stop": "relative fit change <= 1e-12 (FP32 phase: alarm at a mean FP32-objective gain <= 1e-9 "
+                    "per sweep, then ends at a mean FP64-contraction fit gain <= 1e-11 per sweep over a "
+                    "16-sweep chunk)",
             "fp64": {"sweeps": r64.sweeps, "seconds": round(t64, 4), "fit": fit64},
             "mixed": {"sweeps_fp32": rm.sweeps32, "sweeps_fp64": rm.sweeps64,
                       "seconds": round(tm, 4), "fit": fitm},

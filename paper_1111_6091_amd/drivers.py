@@ -114,17 +114,35 @@ def exact_fit(ctx, Z, A, f=None, norm2=None):
     return fit_from_f(float(f.item()), norm2)
 
 
-def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000, chunk64=16):
+def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000, chunk64=16,
+                tol32_fp64=1e-11):
     """Mixed form: FP32-contraction sweeps, then FP64 refinement sweeps.
 
-    The FP32 phase runs in chunks of ``chunk32`` sweeps and ends when the mean
-    per-sweep gain of the fused objective over a chunk is <= tol32 * fit (a
-    negative gain means the FP32 contractions have reached their noise floor).
+    The FP32 phase runs in chunks of ``chunk32`` sweeps.  Its own fused
+    objective (from the FP32 contraction) raises the alarm when the mean
+    per-sweep gain over a chunk is <= tol32 * fit; a negative gain means the
+    FP32 values have reached their noise floor.  That noise is larger than the
+    late gains, so the alarm comes hundreds of sweeps before the FP32 sweeps
+    stop tracking the FP64 trajectory.  With ``tol32_fp64`` (and an FP64 copy
+    of Z) the alarm is therefore checked: from then on the fit after each chunk
+    comes from the objective with an FP64 contraction (cp_objective's fused
+    identity, one FP64 MTTKRP), and the phase ends when that per-sweep gain is
+    <= tol32_fp64 * fit.  Without it the alarm ends the phase.
+
     The FP64 phase then runs until the per-sweep fit change is <= tol64 * fit.
     """
     torch = _torch()
     norm2 = float(Z.norm2.item())
     fh = torch.zeros(chunk32, dtype=torch.float64, device=Z.device)
+    check = bool(tol32_fp64) and Z.z64 is not None
+    fbuf = torch.zeros(1, dtype=torch.float64, device=Z.device)
+
+    def fit_fp64():
+        fbuf.zero_()
+        api.cp_objective(ctx, Z, A, exact=False, f=fbuf, prec=CP_FP64)
+        return fit_from_f(float(fbuf.item()), norm2)
+
+    prev = None   # FP64-contraction fit after the last chunk, once the alarm came
     res = SolveResult()
     while res.sweeps < max_sweeps:
         k = min(chunk32, max_sweeps - res.sweeps)
@@ -133,8 +151,15 @@ def mixed_solve(ctx, Z, A, tol32=1e-9, tol64=1e-12, chunk32=16, max_sweeps=10000
         res.fits.extend(fits)
         res.sweeps += k
         res.sweeps32 += k
-        if k >= 2 and (fits[-1] - fits[0]) / (k - 1) <= tol32 * abs(fits[-1]):
-            break
+        if prev is not None:
+            cur = fit_fp64()
+            gain, prev = (cur - prev) / k, cur
+            if gain <= tol32_fp64 * abs(cur):
+                break
+        elif k >= 2 and (fits[-1] - fits[0]) / (k - 1) <= tol32 * abs(fits[-1]):
+            if not check:
+                break
+            prev = fit_fp64()
     r64 = als_solve(ctx, Z, A, max_sweeps=max(1, max_sweeps - res.sweeps), fit_tol=tol64,
                     chunk=chunk64, prec=CP_FP64)
     res.sweeps64 = r64.sweeps
