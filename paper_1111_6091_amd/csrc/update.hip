@@ -488,53 +488,97 @@ hipError_t gram_launch(double* const* A, float* const* A32, const int64_t* dims,
 }
 
 // ---------------------------------------------------------------------------
-// Exact residual 1/2 ||Z - [[A]]||^2: one pass over Z; each block walks a range
-// of mode-0 fibres, forming W_f(r) = prod_{m>=1} A^(m)(f_m, r) once per fibre.
+// Exact residual 1/2 ||Z - [[A]]||^2: one pass over Z; each block takes a range
+// of mode-0 fibres.  It forms the weights W_f(r) = prod_{m>=1} A^(m)(f_m, r) of
+// all its fibres at once (LDS), stages A^(0) in LDS when it fits, and then each
+// thread walks its rows i0 across the block's fibres, four fibres at a time
+// with their tensor loads issued first.
 struct ResArgs {
   const double* A[kMaxOrder];
   int64_t dims[kMaxOrder];
 };
+
+constexpr int kResA0 = 4096;   // doubles of A^(0) staged in LDS at most
+constexpr int kResW = 2048;    // doubles of fibre weights per block
+
+template <bool STAGED>
+__device__ __forceinline__ double residual_rows(const double* __restrict__ z, const double* a0,
+                                                const double* sW, int64_t I0, int R, int64_t fb,
+                                                int nf) {
+  double acc = 0.0;
+  for (int64_t i0 = threadIdx.x; i0 < I0; i0 += kThreads) {
+    const double* arow = a0 + i0 * R;
+    int fl = 0;
+    for (; fl + 3 < nf; fl += 4) {
+      double zv[4], m4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) zv[u] = z[(fb + fl + u) * I0 + i0];
+      for (int r = 0; r < R; ++r) {
+        const double a = arow[r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m4[u] += a * sW[(fl + u) * R + r];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double df = zv[u] - m4[u];
+        acc += df * df;
+      }
+    }
+    for (; fl < nf; ++fl) {
+      const double zv = z[(fb + fl) * I0 + i0];
+      double mdl = 0.0;
+      for (int r = 0; r < R; ++r) mdl += arow[r] * sW[fl * R + r];
+      const double df = zv - mdl;
+      acc += df * df;
+    }
+  }
+  return acc;
+}
 
 __global__ __launch_bounds__(kThreads) void residual_kernel(const double* __restrict__ z,
                                                             ResArgs ra, int N, int R,
                                                             int64_t fibres, int64_t fpb,
                                                             double* part, int32_t* counter,
                                                             double* f) {
-  __shared__ double W[kMaxRank];
+  __shared__ double sA0[kResA0];
+  __shared__ double sW[kResW];
   __shared__ double sred[8];
   __shared__ int s_flag;
   const int64_t I0 = ra.dims[0];
-  const int64_t fb = (int64_t)blockIdx.x * fpb;
-  const int64_t fe = std::min<int64_t>(fibres, fb + fpb);
+  const int64_t fb0 = (int64_t)blockIdx.x * fpb;
+  const int64_t fe = std::min<int64_t>(fibres, fb0 + fpb);
+  const int fcap = kResW / R;   // fibres whose weights fit in sW at once
+  const bool staged = I0 * R <= kResA0;
+  if (staged)
+    for (int idx = threadIdx.x; idx < I0 * R; idx += kThreads) sA0[idx] = ra.A[0][idx];
   double acc = 0.0;
-  for (int64_t fi = fb; fi < fe; ++fi) {
-    __syncthreads();
-    if (threadIdx.x < R) {
-      int64_t q = fi;
+  for (int64_t fb = fb0; fb < fe; fb += fcap) {
+    const int nf = (int)std::min<int64_t>(fcap, fe - fb);
+    if (fb != fb0) __syncthreads();   // the previous fibres' weights are consumed
+    for (int idx = threadIdx.x; idx < nf * R; idx += kThreads) {
+      const int fl = idx / R, r = idx - (idx / R) * R;
+      int64_t q = fb + fl;
       double w = 1.0;
       for (int m = 1; m < N; ++m) {
         const int64_t im = q % ra.dims[m];
         q /= ra.dims[m];
-        w *= ra.A[m][im * R + threadIdx.x];
+        w *= ra.A[m][im * R + r];
       }
-      W[threadIdx.x] = w;
+      sW[idx] = w;
     }
     __syncthreads();
-    const double* zf = z + fi * I0;
-    for (int64_t i0 = threadIdx.x; i0 < I0; i0 += kThreads) {
-      double mdl = 0.0;
-      for (int r = 0; r < R; ++r) mdl += ra.A[0][i0 * R + r] * W[r];
-      const double df = zf[i0] - mdl;
-      acc += df * df;
-    }
+    acc += staged ? residual_rows<true>(z, sA0, sW, I0, R, fb, nf)
+                  : residual_rows<false>(z, ra.A[0], sW, I0, R, fb, nf);
   }
   const double tot = block_sum(acc, sred);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
   if (arrive_last(counter, (int)gridDim.x, &s_flag)) {
+    // the last block adds the block sums, every thread a strided share
+    double s = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kThreads) s += part[b];
+    const double all = block_sum(s, sred);
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += part[b];
-      *f = 0.5 * s;
+      *f = 0.5 * all;
       atomicExch(counter, 0);
     }
   }
@@ -550,8 +594,10 @@ hipError_t residual_launch(const double* z, const int64_t* dims, int N, int R,
     ra.dims[m] = dims[m];
     if (m >= 1) fibres *= dims[m];
   }
-  // about 8k entries per block, at most 2048 blocks
+  // about 8k entries per block (whose weights sW holds at once), at most 2048
+  // blocks (a block then walks its fibres in groups that sW holds)
   int64_t fpb = std::max<int64_t>(1, 8192 / std::max<int64_t>(1, dims[0]));
+  fpb = std::min<int64_t>(fpb, kResW / R);
   int64_t nb = (fibres + fpb - 1) / fpb;
   if (nb > 2048) {
     fpb = (fibres + 2047) / 2048;

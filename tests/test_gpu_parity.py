@@ -106,6 +106,24 @@ def test_norm2_and_objectives(C):
     assert g.item() == pytest.approx(cp.grad_norm(Z, A), rel=1e-11)
 
 
+@pytest.mark.parametrize("dims,R", [((600, 8, 3), 8), ((2, 400, 400), 32), ((5, 6, 7, 8), 4)])
+def test_exact_objective_matches_oracle(C, dims, R):
+    """f = 1/2 ||Z - [[A]]||^2 (eq. (2)) by the residual pass, against the oracle:
+    A^(0) too large for the kernel's LDS copy (600 x 8), fibres whose weights
+    need several LDS groups per block (rank 32 over 160000 fibres), order 4."""
+    from paper_1111_6091_amd import api
+    say(f"exact objective dims={dims} R={R}")
+    rng = np.random.default_rng(sum(dims) + R)
+    Z = rng.standard_normal(dims)
+    A = [rng.standard_normal((d, R)) / np.sqrt(R) for d in dims]
+    Zd, Ad = dev_inputs(C, Z, A)
+    f = torch.zeros(1, dtype=torch.float64, device="cuda")
+    api.cp_objective(C, Zd, Ad, exact=True, f=f)
+    sync()
+    assert f.item() == pytest.approx(cp.objective(Z, A), rel=1e-12)
+    assert C.status() == 0
+
+
 @pytest.mark.parametrize("dims,R,seed", [((20, 20, 20), 3, 1), ((17, 9, 13), 4, 2), ((8, 9, 10, 7), 3, 3)])
 def test_als_sweeps_track_oracle(C, dims, R, seed):
     from paper_1111_6091_amd import api
