@@ -110,42 +110,43 @@ __device__ inline double wave_gs(double b, double x, const double* G, int R, int
 
 // The same Gauss-Seidel iterations with every lane holding the whole row
 // (uniform across the wave) and Gamma in registers: no broadcasts or LDS reads
-// inside the iteration; x_r <- (b_r - sum_{k != r} x_k Gamma_kr) / Gamma_rr with
-// the division applied as a product with the reciprocal pivot.  RM >= R.
+// inside the iteration.  The equations are scaled by the reciprocal pivots
+// once, c_r = b_r / Gamma_rr and h[k][r] = Gamma_kr / Gamma_rr, so that
+// x_r <- c_r - sum_{k != r} x_k h[k][r]; a zero pivot (and every r >= R) gets
+// c_r = 0, h[.][r] = 0 and a unit term that keeps x_r as it is.  RM >= R.
 template <int RM>
 __device__ inline double wave_gs_reg(double b, double x, const double* G, int R, int iters, int lane) {
-  double xv[RM], bv[RM], dinv[RM], g[RM][RM];
+  double xv[RM], c[RM], keep[RM], h[RM][RM];
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
     xv[r] = r < R ? wave_bcast(x, r) : 0.0;
-    bv[r] = r < R ? wave_bcast(b, r) : 0.0;
+    const double br = r < R ? wave_bcast(b, r) : 0.0;
     const double dg = r < R ? G[r * R + r] : 0.0;
-    dinv[r] = dg != 0.0 ? 1.0 / dg : 0.0;
+    const bool piv = dg != 0.0;
+    const double dinv = piv ? 1.0 / dg : 0.0;
+    keep[r] = piv ? 0.0 : 1.0;
+    c[r] = br * dinv;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) h[k][r] = (k < R && r < R) ? G[k * R + r] * dinv : 0.0;
   }
-#pragma unroll
-  for (int k = 0; k < RM; ++k)
-#pragma unroll
-    for (int r = 0; r < RM; ++r) g[k][r] = (k < R && r < R) ? G[k * R + r] : 0.0;
-  // static indices only (entries r >= R are zero and never change).  Per
-  // iteration the sums over k > r (previous iterate) are formed side by side
-  // first; each new x_r is then added into the pending sums of the later
-  // components (serial chain per component: one product, a subtraction, a scaling)
+  // static indices only.  Per iteration the terms of the previous iterate
+  // (k > r) are formed side by side first; each new x_r then enters the
+  // pending values of the later components (serial chain per component: one
+  // product and subtraction)
   for (int it = 0; it < iters; ++it) {
-    double up[RM], lo[RM];
+    double t[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-      double t = 0.0;
+      double u = 0.0;
 #pragma unroll
-      for (int k = r + 1; k < RM; ++k) t += xv[k] * g[k][r];
-      up[r] = t;
-      lo[r] = 0.0;
+      for (int k = r + 1; k < RM; ++k) u += xv[k] * h[k][r];
+      t[r] = fma(xv[r], keep[r], c[r] - u);
     }
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-      const double v = (bv[r] - (up[r] + lo[r])) * dinv[r];
-      xv[r] = (r < R && dinv[r] != 0.0) ? v : xv[r];
+      xv[r] = t[r];
 #pragma unroll
-      for (int j = r + 1; j < RM; ++j) lo[j] += xv[r] * g[r][j];
+      for (int j = r + 1; j < RM; ++j) t[j] -= xv[r] * h[r][j];
     }
   }
   double out = 0.0;
