@@ -451,7 +451,11 @@ def solve_phase(ctx, Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500, st
     """Solve cycles of Section 6.1: CP-FAS V-cycles until g < tau; once five
     cycles have completed, a cycle with g_new >= g_old is discarded and the
     transfer operators are rebuilt by one down-sweep from the previous iterate
-    (once).  A is updated in place.  Returns (levels, g history, rebuilt)."""
+    (once).  A is updated in place.  Returns (levels, g history, rebuilt).
+
+    A cycle whose g is not finite (the cycle diverged) is discarded at any
+    point: it triggers the one rebuild, or ends the phase once that is spent,
+    leaving A at the last finite iterate."""
     g_old = grad_norm(ctx, Z, A)
     rebuilt = False
     hist = []
@@ -459,6 +463,12 @@ def solve_phase(ctx, Z, A, levels, tfms, coarsest, tau=1e-10, max_cycles=500, st
         An = A.clone()
         api.cp_fas_vcycle(ctx, levels, An, **fas)
         g_new = grad_norm(ctx, Z, An)
+        if not math.isfinite(g_new):
+            if rebuilt:
+                break
+            levels, _ = down_sweep(ctx, Z, A, tfms, coarsest, nu1=nu1_setup)
+            rebuilt = True
+            continue
         if c + 1 > stagnation_after and g_new >= g_old and not rebuilt:
             levels, _ = down_sweep(ctx, Z, A, tfms, coarsest, nu1=nu1_setup)
             rebuilt = True
